@@ -1,0 +1,277 @@
+/*
+ * spgemm.h - C ABI of the MI355X (gfx950) sparse matrix-matrix product.
+ *
+ * The library computes C = A * B for row-major compressed sparse (CSR) FP64
+ * matrices, row by row in the form the paper attributes to Gustavson
+ * (Scharpff, Iglberger, Hager, Ruede, "Model-guided Performance Analysis of
+ * the Sparse Matrix-Matrix Multiplication", arXiv:1303.1651, Section IV-A):
+ * row r of C is the sum, over the stored a(r,c) of row r of A in stored
+ * order, of a(r,c) times row c of B.
+ *
+ * Output contract (Section IV-B, the append/finalize interface): C is written
+ * as one contiguous block, rows in increasing order and, inside a row, column
+ * indices strictly increasing.  An entry exists in C exactly when some product
+ * a(r,c) * b(c,x) was formed for it, whatever its value (a sum that cancels
+ * to 0.0 is stored).  Each entry is accumulated from +0.0, one FP64 multiply
+ * and one FP64 add per product, in A's column order (the listing of the
+ * row-major computation kernel), unless SPGEMM_OPT_FAST is set, in which case
+ * rows above the workgroup limit may add their products in another order
+ * (values then agree to a few ulps, structure is still exact).
+ *
+ * Sizing (Section IV-B): the number of multiplications of a row is an upper
+ * bound of its number of entries; the library reports the sum of these
+ * bounds so that a caller can size C with one allocation, or the exact size
+ * after the symbolic pass, or a learned estimate.
+ *
+ * Memory and ownership
+ *   - Every matrix pointer in spgemm_csr is a DEVICE pointer owned by the
+ *     caller.  The library never allocates device memory: the caller passes
+ *     a workspace (size from spgemm_plan_workspace_size) and, where the
+ *     plan reports one, a scratch buffer.  Host-side plan objects are
+ *     allocated with malloc and freed by spgemm_plan_destroy.
+ *   - Row pointers are int64 (rows + 1 entries, row_ptr[0] == 0,
+ *     non-decreasing, row_ptr[rows] == nnz).  Column indices are int32 in
+ *     [0, cols), strictly increasing inside each row.  Values are FP64.
+ *     cols must be < 2^31.
+ *   - All work is enqueued on the caller's HIP stream.  Calls that return
+ *     a size to the host (plan, symbolic, numeric) synchronise that stream.
+ *
+ * Errors are returned as spgemm_status; no call exits or throws.  A HIP
+ * runtime error is reported as SPGEMM_E_HIP and its code is kept in the plan
+ * (spgemm_plan_last_hip_error).
+ */
+#ifndef SPGEMM_H
+#define SPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spgemm_status {
+    SPGEMM_OK = 0,
+    SPGEMM_E_NULL = 1,            /* a required pointer is NULL                     */
+    SPGEMM_E_DIM = 2,             /* A.cols != B.rows, negative sizes               */
+    SPGEMM_E_NOT_CANONICAL = 3,   /* validate: unsorted/duplicate/out-of-range cols  */
+    SPGEMM_E_INDEX_OVERFLOW = 4,  /* cols >= 2^31                                    */
+    SPGEMM_E_WORKSPACE = 5,       /* workspace or scratch smaller than required      */
+    SPGEMM_E_CAPACITY = 6,        /* C capacity too small; required size returned    */
+    SPGEMM_E_NO_MODEL = 7,        /* learned sizing requested without a model        */
+    SPGEMM_E_STATE = 8,           /* calls out of order (e.g. numeric before plan)   */
+    SPGEMM_E_HIP = 9,             /* HIP runtime error                               */
+    SPGEMM_E_INVALID = 10,        /* bad option value                                */
+    SPGEMM_E_IO = 11              /* model file could not be read or written         */
+} spgemm_status;
+
+/* A CSR matrix; pointers are device pointers.  val may be NULL where only
+ * the structure is used (plan, symbolic). */
+typedef struct spgemm_csr {
+    int64_t rows, cols, nnz;
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val;
+} spgemm_csr;
+
+/* How output rows are sized before the numeric pass. */
+typedef enum spgemm_sizer {
+    SPGEMM_SIZER_EXACT = 0,        /* two passes: symbolic (exact counts), scan, numeric      */
+    SPGEMM_SIZER_UPPER_BOUND = 1,  /* one pass, per-row accumulators sized by the multiplication
+                                      count (Section IV-B estimate)                         */
+    SPGEMM_SIZER_LEARNED = 2       /* one pass, accumulators sized by the learned network;
+                                      rows that overflow fall back to exact counting        */
+} spgemm_sizer;
+
+enum {
+    SPGEMM_OPT_FAST = 1,           /* allow reordered accumulation in workgroup-level rows  */
+    SPGEMM_OPT_VALIDATE = 2        /* check that A and B are canonical CSR                  */
+};
+
+typedef struct spgemm_model spgemm_model;   /* learned row-size network (host object) */
+
+/* Launch and tier parameters.  Zero fields take the library defaults; the
+  * autotuner fills them for a workload family.  pool_slots = -1 means no LDS
+ * pool (every row that is not merged goes to the workgroup-level tier);
+ * merge_max_nnz = -1 turns the register-merge tier off. */
+typedef struct spgemm_tuning {
+    int32_t hash_group;      /* lanes per row in the LDS hash tier: 4..64, power of two   */
+    int32_t pool_slots;      /* LDS accumulator slots per workgroup (12 bytes each)        */
+    int32_t max_tile_rows;   /* rows per tile, <= 512                                      */
+    int32_t merge_max_nnz;   /* register-merge tier: largest row (entries) it takes        */
+    int32_t merge_lists;     /* register-merge tier: max stored entries of the A row (4/8) */
+    float dense_ratio;       /* dense window used when column span <= ratio * capacity     */
+    float margin;            /* learned sizing: capacity = pred * (1 + margin) + slack     */
+    int32_t slack;
+    int32_t blocks_per_cu;   /* persistent workgroups per compute unit                     */
+} spgemm_tuning;
+
+typedef struct spgemm_options {
+    int32_t sizer;                    /* spgemm_sizer                                   */
+    int32_t flags;                    /* SPGEMM_OPT_*                                   */
+    const spgemm_model *model;        /* required for SPGEMM_SIZER_LEARNED              */
+    const spgemm_tuning *tuning;      /* NULL: defaults                                 */
+} spgemm_options;
+
+/* Host-visible facts about a plan, filled by spgemm_plan. */
+typedef struct spgemm_info {
+    int64_t multiplications;   /* Section III count, sum over rows of the per-row bound   */
+    int64_t c_capacity_hint;   /* entries to allocate for C: sum of per-row bounds
+                                  (EXACT, UPPER_BOUND) or of learned capacities (LEARNED) */
+    int64_t c_nnz;             /* exact nnz(C) once known (after symbolic or numeric), else -1 */
+    size_t scratch_bytes;      /* scratch the numeric (and symbolic) call needs            */
+    int64_t rows_merge, rows_hash, rows_global, rows_empty;  /* tier histogram          */
+    int64_t overflow_rows;     /* rows whose learned capacity was too small (after numeric) */
+    int64_t tiles;
+} spgemm_info;
+
+typedef struct spgemm_plan spgemm_plan;
+
+/* Device workspace needed by spgemm_plan for these operands (dims only). */
+spgemm_status spgemm_plan_workspace_size(const spgemm_csr *A, const spgemm_csr *B,
+                                         const spgemm_options *opts, size_t *bytes);
+
+/* Validates descriptors, computes per-row features (entries of the A row,
+ * multiplication count, longest selected B row, column span), runs the
+ * learned sizer when asked, assigns tiers and tiles, and returns the sizes
+ * the caller must provide.  `workspace` must stay alive and untouched until
+ * the plan is destroyed.  Synchronises `stream`.  The plan keeps copies of
+ * the descriptors (not of the data): A and B must not change until the plan
+ * is destroyed. */
+spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B,
+                                 const spgemm_options *opts,
+                                 void *workspace, size_t workspace_bytes,
+                                 void *stream, spgemm_plan **out, spgemm_info *info);
+
+/* Symbolic pass (SPGEMM_SIZER_EXACT only): exact entries per row of C and
+ * their exclusive scan, written to c_row_ptr (device, rows + 1).  *c_nnz
+ * (host) receives nnz(C).  Synchronises `stream`. */
+spgemm_status spgemm_symbolic(spgemm_plan *plan, void *scratch, size_t scratch_bytes,
+                              int64_t *c_row_ptr, int64_t *c_nnz, void *stream);
+
+/* Numeric pass: writes C.  For SPGEMM_SIZER_EXACT, c_row_ptr must hold the
+ * result of spgemm_symbolic.  For the one-pass sizers it is written here.
+ * c_col / c_val (device) have room for c_capacity entries.  If C needs more,
+ * nothing past c_capacity is written, the call returns SPGEMM_E_CAPACITY and
+ * *c_nnz holds the required size (call again with a larger C).  a_val and
+ * b_val may be NULL to use the values in the plan's descriptors.
+ * Synchronises `stream`. */
+spgemm_status spgemm_numeric(spgemm_plan *plan, void *scratch, size_t scratch_bytes,
+                             const double *a_val, const double *b_val,
+                             int64_t *c_row_ptr, int32_t *c_col, double *c_val,
+                             int64_t c_capacity, int64_t *c_nnz, void *stream);
+
+spgemm_status spgemm_plan_info(const spgemm_plan *plan, spgemm_info *info);
+int spgemm_plan_last_hip_error(const spgemm_plan *plan);
+void spgemm_plan_destroy(spgemm_plan *plan);
+const char *spgemm_status_string(spgemm_status s);
+
+/* ---------------------------------------------------------------- batched
+ * Many independent products C_i = A_i * B_i in one persistent launch.
+ * A, B: host arrays of `count` descriptors (device data).  The outputs of
+ * product i are placed at c_row_base[i] (row pointers, rows_i + 1 entries,
+ * relative to the product's own first entry) and c_nnz_base[i] (entries) of
+ * the pools; the caller takes both from spgemm_batched_plan.
+ * First, size query: spgemm_batched_plan fills row bases (host, count + 1),
+ * capacity bases (host, count + 1), and the workspace and scratch it needs.
+ * It reads only descriptors (no device data) and does not synchronise. */
+typedef struct spgemm_batch spgemm_batch;
+
+spgemm_status spgemm_batched_plan(int64_t count, const spgemm_csr *A, const spgemm_csr *B,
+                                  const spgemm_options *opts,
+                                  int64_t *c_row_base, size_t *workspace_bytes,
+                                  spgemm_batch **out);
+
+/* Runs the whole batch: features, sizing, tiling and the persistent tiled
+ * numeric kernel over all products, captured in a HIP graph on first use and
+ * replayed afterwards (same batch object, same pointers).  c_nnz_base
+ * (host, count + 1) receives the entry bases chosen from the capacities; the
+ * pools must hold c_capacity entries in total.  c_nnz (host, count) receives
+ * each product's nnz.  Returns SPGEMM_E_CAPACITY (and the required total in
+ * *c_required) when the pools are too small.  Synchronises `stream`. */
+spgemm_status spgemm_batched(spgemm_batch *batch, void *workspace, size_t workspace_bytes,
+                             int64_t *c_row_pool, int32_t *c_col_pool, double *c_val_pool,
+                             int64_t c_capacity, int64_t *c_nnz_base, int64_t *c_nnz,
+                             int64_t *c_required, void *stream);
+
+/* Capacity the batch needs (host, after one spgemm_batched_reserve call):
+ * runs the feature and sizing kernels and returns the total capacity. */
+spgemm_status spgemm_batched_reserve(spgemm_batch *batch, void *workspace, size_t workspace_bytes,
+                                     int64_t *c_capacity, void *stream);
+void spgemm_batched_destroy(spgemm_batch *batch);
+
+/* ------------------------------------------------------------- learned sizer
+ * A 3-32-32-1 perceptron (ReLU, logistic output, FP32, 1217 parameters)
+ * mapping per-row features (entries of the A row, multiplication count,
+ * longest selected B row; each as standardised log2(1 + x)) to the fraction
+ * of the interval [longest B row, multiplication count] that nnz(C_row)
+ * reaches.  Not part of the paper. */
+
+/* Model from host arrays: theta[1217] (W1 32x3, b1, W2 32x32, b2, w3, b3),
+ * mu[3], sd[3]. */
+spgemm_status spgemm_model_create(const float *theta, const float *mu, const float *sd,
+                                  spgemm_model **out);
+spgemm_status spgemm_model_get(const spgemm_model *m, float *theta, float *mu, float *sd);
+spgemm_status spgemm_model_save(const spgemm_model *m, const char *path);
+spgemm_status spgemm_model_load(const char *path, spgemm_model **out);
+void spgemm_model_destroy(spgemm_model *m);
+
+/* Features of every row of A*B on the device (int32, rows each): entries of
+ * the A row, multiplication count (saturated at B.cols), longest selected B
+ * row.  Used to build training sets.  Synchronises nothing. */
+spgemm_status spgemm_row_features(const spgemm_csr *A, const spgemm_csr *B,
+                                  int32_t *f_nnz_a, int32_t *f_ub, int32_t *f_maxb, void *stream);
+
+/* Device parameter block of a model (theta, mu, sd as float32) and its
+ * upload; used by spgemm_model_predict.  The upload synchronises `stream`. */
+size_t spgemm_model_device_bytes(void);
+spgemm_status spgemm_model_upload(const spgemm_model *m, void *dev_params, void *stream);
+
+/* Training-set statistics: mu/sd (host, 3 each) of log2(1 + feature) over n
+ * rows of device features.  scratch: device, spgemm_model_stats_scratch(n)
+ * bytes.  Synchronises `stream`. */
+size_t spgemm_model_stats_scratch(int64_t n);
+spgemm_status spgemm_model_feature_stats(const int32_t *f_nnz_a, const int32_t *f_ub,
+                                         const int32_t *f_maxb, int64_t n,
+                                         float *mu, float *sd, void *scratch, void *stream);
+
+/* Loss and gradient (device, float[1217]) of the network over n device
+ * samples (features and exact row sizes).  scratch: device,
+ * spgemm_model_grad_scratch(n) bytes.  *loss (host) is the mean squared
+ * error over rows with UB > longest B row.  Synchronises `stream`. */
+size_t spgemm_model_grad_scratch(int64_t n);
+spgemm_status spgemm_model_loss_grad(const spgemm_model *m,
+                                     const int32_t *f_nnz_a, const int32_t *f_ub,
+                                     const int32_t *f_maxb, const int32_t *nnz_c, int64_t n,
+                                     float *grad, void *scratch, float *loss, void *stream);
+
+/* Mini-batch Adam training on the device (forward, backward and update
+ * kernels of this library).  Batches are taken in order, batch_size rows
+ * each, for `epochs` passes.  theta0, mu, sd (host) are the starting point
+ * and the input standardisation; the trained model is returned in *out.
+ * scratch: device, spgemm_model_train_scratch bytes.  loss_curve (host,
+ * epochs) receives the loss of each epoch's last batch and may be NULL. */
+typedef struct spgemm_train_params {
+    int32_t epochs;
+    int32_t batch_size;
+    float lr, beta1, beta2, eps;
+} spgemm_train_params;
+
+size_t spgemm_model_train_scratch(int64_t n, int32_t batch_size);
+spgemm_status spgemm_model_train(const float *theta0, const float *mu, const float *sd,
+                                 const int32_t *f_nnz_a, const int32_t *f_ub,
+                                 const int32_t *f_maxb, const int32_t *nnz_c, int64_t n,
+                                 const spgemm_train_params *hp, void *scratch, size_t scratch_bytes,
+                                 float *loss_curve, spgemm_model **out, void *stream);
+
+/* Predicted nnz(C_row) (device float, n rows) from device features.
+ * dev_params: device, spgemm_model_device_bytes() bytes, overwritten with
+ * the model's parameters. */
+spgemm_status spgemm_model_predict(const spgemm_model *m, const int32_t *f_nnz_a,
+                                   const int32_t *f_ub, const int32_t *f_maxb, int64_t n,
+                                   float *pred, void *dev_params, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPGEMM_H */

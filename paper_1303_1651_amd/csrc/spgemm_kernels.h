@@ -1,0 +1,139 @@
+// Kernel parameter blocks and launch entry points of the SpGEMM pipeline.
+// Host code (spgemm_host.hip) fills these; the kernels live in
+// spgemm_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spg {
+
+// Per-row tier.  EMPTY rows produce nothing; MERGE rows are merged in
+// registers by one thread; HASH rows accumulate in a slice of the
+// workgroup's LDS pool, one group of lanes per row; GLOBAL rows (too large
+// for LDS) accumulate in a per-workgroup table in device memory.
+enum Tier : uint32_t { kTierEmpty = 0, kTierMerge = 1, kTierHash = 2, kTierGlobal = 3 };
+
+// info word of a row: bits 0-1 tier, bit 2 dense window, bits 3-31 slots.
+__host__ __device__ inline uint32_t pack_info(uint32_t tier, bool dense, uint32_t slots) {
+  return tier | (dense ? 4u : 0u) | (slots << 3);
+}
+__host__ __device__ inline uint32_t info_tier(uint32_t w) { return w & 3u; }
+__host__ __device__ inline bool info_dense(uint32_t w) { return (w >> 2) & 1u; }
+__host__ __device__ inline uint32_t info_slots(uint32_t w) { return w >> 3; }
+
+// Pass kinds of the tile kernel.
+enum Mode : int { kSymbolic = 0, kNumeric = 1, kOnePass = 2 };
+
+// counters[] layout (int64, device)
+enum Counter : int {
+  kCtrTicket = 0,      // tile ticket of the running tile kernel
+  kCtrTiles = 1,       // number of tiles
+  kCtrMults = 2,       // sum of per-row multiplication counts (exact, int64)
+  kCtrCapSum = 3,      // sum of per-row capacities (learned capacity hint)
+  kCtrMerge = 4, kCtrHash = 5, kCtrGlobal = 6, kCtrEmpty = 7,
+  kCtrOverflow = 8,    // one-pass rows whose capacity was too small
+  kCtrScratch = 9,     // largest device table (slots) a workgroup-level row needs
+  kCtrError = 10,      // bit flags, see kErr*
+  kCtrNnz = 11,        // nnz(C) after a one-pass numeric
+  kCtrScanTicket = 12,
+  kCtrPoolRows = 13,   // rows that use the LDS pool
+  kCtrMaxCap = 14,
+  kNumCounters = 32
+};
+enum : int64_t { kErrCapacity = 1, kErrNotCanonical = 2, kErrInconsistent = 4, kErrScratch = 8, kErrLookback = 16 };
+
+struct Operands {
+  const int64_t *a_rp;
+  const int32_t *a_col;
+  const double *a_val;
+  const int64_t *b_rp;
+  const int32_t *b_col;
+  const double *b_val;
+  int64_t rows;       // rows of A (and C)
+  int32_t b_cols;     // columns of B (and C)
+};
+
+struct Features {
+  int32_t *nnz_a;     // entries of the A row
+  int32_t *ub;        // multiplication count, saturated at b_cols
+  int32_t *maxb;      // longest selected B row
+  int32_t *lo, *hi;   // smallest / largest column any selected B row touches
+};
+
+struct SizeParams {
+  int mode;             // Mode of the pass being sized
+  int sizer;            // spgemm_sizer for kOnePass
+  int pool_slots;       // LDS pool of one workgroup (slots)
+  int pad;              // probe room after a hashed table
+  int merge_lists;      // template M of the merge tier
+  int merge_max;        // largest capacity the merge tier takes
+  int tile_rows;        // target rows per tile
+  float dense_ratio;
+  float margin;
+  int slack;
+  const float *pred;    // learned prediction (kOnePass + learned)
+  const int32_t *cnt;   // exact counts (kNumeric)
+};
+
+struct PlanArrays {
+  Features f;
+  uint32_t *info;       // per row
+  int32_t *cap;         // per row capacity (keys)
+  int64_t *cost;        // per row tile cost, scanned in place to an exclusive prefix (rows + 1)
+  int32_t *tile_row;    // first row of every tile (tiles + 1)
+  uint64_t *status;     // look-back status, one per tile
+  uint64_t *scan_status;
+  int64_t *counters;
+  int32_t *cnt;         // exact per-row counts (symbolic output)
+  float *pred;          // learned prediction
+};
+
+struct TileParams {
+  Operands op;
+  const uint32_t *info;
+  const int32_t *cap;
+  const int32_t *ub;
+  const int32_t *lo, *hi;
+  const int64_t *cost;      // exclusive prefix of tile cost
+  const int32_t *tile_row;
+  int64_t *counters;
+  uint64_t *status;
+  int32_t *cnt_out;         // kSymbolic
+  int64_t *c_rp;            // kNumeric: input; kOnePass: output
+  int32_t *c_col;
+  double *c_val;
+  int64_t c_capacity;
+  char *scratch;            // per-workgroup device tables
+  int64_t scratch_slots;    // slots per workgroup
+  int pool_slots;
+  int pad;
+  int fast;                 // reordered accumulation allowed in workgroup-level rows
+};
+
+constexpr int kMaxTileRows = 512;
+
+__host__ __device__ inline int64_t tile_budget(int pool_slots, int tile_rows) {
+  return pool_slots > 0 ? (int64_t)(pool_slots / 2) : (int64_t)tile_rows;
+}
+
+// ---- launchers (spgemm_kernels.hip) ----
+hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+hipError_t launch_validate(const int64_t *rp, const int32_t *col, int64_t rows, int64_t cols,
+                           int64_t nnz, int64_t *counters, hipStream_t s);
+hipError_t launch_features(const Operands &op, const Features &f, int64_t *counters, hipStream_t s);
+hipError_t launch_size_rows(const Operands &op, const PlanArrays &pa, const SizeParams &sp,
+                            hipStream_t s);
+// exclusive scan of rows int32 (or int64 when in64) values into out[0..n], out[n] = total
+hipError_t launch_scan_i32(const int32_t *in, int64_t *out, int64_t n, uint64_t *status,
+                           int64_t *ticket, int64_t *total_dst, int64_t *err, hipStream_t s);
+hipError_t launch_scan_i64_inplace(int64_t *inout, int64_t n, uint64_t *status, int64_t *ticket,
+                                   int64_t *err, hipStream_t s);
+hipError_t launch_tile_bounds(const int64_t *cost, int64_t rows, int64_t half_pool,
+                              int32_t *tile_row, int64_t *counters, hipStream_t s);
+hipError_t launch_tiles(const TileParams &tp, int mode, int group, int merge_lists, int grid,
+                        size_t lds_bytes, hipStream_t s);
+size_t tile_static_lds(int mode);
+
+}  // namespace spg

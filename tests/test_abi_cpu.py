@@ -1,0 +1,103 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function that include/spgemm.h declares, and rejects bad descriptors
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spgemm.h")
+LIB = os.path.join(ROOT, "paper_1303_1651_amd", "libspgemm.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1303_1651_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(spgemm_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_the_four_entry_points():
+    names = declared_functions()
+    for n in ["spgemm_plan_create", "spgemm_symbolic", "spgemm_numeric", "spgemm_batched"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_function(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings(lib):
+    lib.spgemm_status_string.restype = ctypes.c_char_p
+    assert lib.spgemm_status_string(0) == b"ok"
+    assert lib.spgemm_status_string(6) == b"output capacity too small"
+    assert lib.spgemm_status_string(99) == b"unknown status"
+
+
+def test_descriptor_errors_before_any_device_call():
+    from paper_1303_1651_amd import _lib as L
+    A = L.spgemm_csr(10, 5, 0, 1, None, None)
+    B = L.spgemm_csr(6, 5, 0, 1, None, None)    # A.cols != B.rows
+    opts = L.spgemm_options(0, 0, None, None)
+    nb = L.SZ()
+    assert L.spgemm_plan_workspace_size(ctypes.byref(A), ctypes.byref(B), ctypes.byref(opts), ctypes.byref(nb)) == 2
+    B.rows = 5
+    assert L.spgemm_plan_workspace_size(ctypes.byref(A), ctypes.byref(B), ctypes.byref(opts), ctypes.byref(nb)) == 0
+    assert nb.value > 0
+    A.nnz = 3                                     # nnz > 0 but no column array
+    assert L.spgemm_plan_workspace_size(ctypes.byref(A), ctypes.byref(B), ctypes.byref(opts), ctypes.byref(nb)) == 1
+    A.nnz = 0
+    A.cols = B.rows = 1 << 31                     # columns beyond int32
+    assert L.spgemm_plan_workspace_size(ctypes.byref(A), ctypes.byref(B), ctypes.byref(opts), ctypes.byref(nb)) == 4
+    A.rows = -1
+    assert L.spgemm_plan_workspace_size(ctypes.byref(A), ctypes.byref(B), ctypes.byref(opts), ctypes.byref(nb)) == 2
+
+
+def test_learned_sizer_without_model_is_rejected():
+    from paper_1303_1651_amd import _lib as L
+    A = L.spgemm_csr(4, 4, 0, 1, None, None)
+    opts = L.spgemm_options(2, 0, None, None)
+    plan = ctypes.c_void_p()
+    code = L.spgemm_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(opts), 1, 1 << 20, None,
+                                ctypes.byref(plan), None)
+    assert code == 7 and not plan.value
+
+
+def test_invalid_tuning_is_rejected():
+    from paper_1303_1651_amd import _lib as L
+    A = L.spgemm_csr(4, 4, 0, 1, None, None)
+    t = L.spgemm_tuning(hash_group=12)
+    opts = L.spgemm_options(0, 0, None, ctypes.pointer(t))
+    plan = ctypes.c_void_p()
+    code = L.spgemm_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(opts), 1, 1 << 20, None,
+                                ctypes.byref(plan), None)
+    assert code == 10
+
+
+def test_model_file_round_trip(tmp_path):
+    import numpy as np
+    from paper_1303_1651_amd import Model
+    th = np.linspace(-1, 1, 1217).astype(np.float32)
+    m = Model.create(th, [1, 2, 3], [4, 5, 6])
+    p = str(tmp_path / "m.bin")
+    m.save(p)
+    m2 = Model.load(p)
+    th2, mu2, sd2 = m2.params()
+    np.testing.assert_array_equal(th2, th)
+    np.testing.assert_array_equal(mu2, [1, 2, 3])
+    np.testing.assert_array_equal(sd2, [4, 5, 6])
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"not a model")
+    with pytest.raises(Exception):
+        Model.load(str(bad))

@@ -1,0 +1,229 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Structure (row_ptr, col) must match bit-exactly.  Values must match
+bit-exactly in the default (ordered) mode, which accumulates every entry in
+A's column order with separate multiply and add, exactly like the oracle;
+the FAST flag is held to 1e-13 relative per entry.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import golden_io
+from tests.gpu_util import (assert_bit_exact, assert_close, bits, check_row_blocks, gpu_product,
+                            sample_blocks)
+
+pytestmark = pytest.mark.gpu
+
+SIZERS = ["exact", "upper_bound"]
+
+# tier forcing through the tuning block
+TIERS = {
+    "default": None,
+    "hash_only": {"merge_max_nnz": -1},
+    "global_only": {"merge_max_nnz": -1, "pool_slots": -1},
+    "hash_dense": {"merge_max_nnz": -1, "dense_ratio": 1e9},
+    "hash_sparse": {"merge_max_nnz": -1, "dense_ratio": 1e-9},
+    "small_pool": {"merge_max_nnz": -1, "pool_slots": 256, "max_tile_rows": 64},
+    "group4": {"merge_max_nnz": -1, "hash_group": 4},
+    "group64": {"merge_max_nnz": -1, "hash_group": 64},
+}
+
+
+@pytest.mark.parametrize("name", ["hand_product.txt", "cancellation.txt"])
+@pytest.mark.parametrize("sizer", SIZERS)
+def test_hand_examples(name, sizer):
+    d = golden_io.load(name)
+    A, B, C = golden_io.csr(d, "A"), golden_io.csr(d, "B"), golden_io.csr(d, "C")
+    got = gpu_product(A, B, sizer)
+    assert_bit_exact(got, (C.row_ptr, C.col, C.val))
+
+
+@pytest.mark.parametrize("sizer", SIZERS)
+@pytest.mark.parametrize("tier", list(TIERS))
+def test_stencil64_all_tiers(sizer, tier):
+    # the 64x64 five-point matrix squared (the small configuration)
+    A = synth.stencil(64)
+    got = gpu_product(A, A, sizer, tuning=TIERS[tier])
+    assert_bit_exact(got, oracle.spgemm(A, A))
+    assert got[3]["multiplications"] == 25 * 64 * 64 - 36 * 64 + 8
+
+
+@pytest.mark.parametrize("tier", list(TIERS))
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_random_rows_all_tiers(tier, seed):
+    A = synth.random_uniform_lengths(3001, 1, 24, seed)
+    B = synth.random_uniform_lengths(3001, 0, 30, seed + 100)
+    want = oracle.spgemm(A, B)
+    for sizer in SIZERS:
+        assert_bit_exact(gpu_product(A, B, sizer, tuning=TIERS[tier]), want)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_tiny_random_rectangular(seed):
+    m = 1 + (seed * 7) % 37
+    k = 1 + (seed * 5) % 29
+    n = 1 + (seed * 3) % 41
+    A = synth.random_sparse(m, k, [0.05, 0.2, 0.5][seed % 3], 2 * seed + 1)
+    B = synth.random_sparse(k, n, [0.1, 0.3, 0.6][seed % 3], 2 * seed + 2)
+    want = oracle.spgemm(A, B)
+    for sizer in SIZERS:
+        for tier in ["default", "hash_only", "global_only"]:
+            assert_bit_exact(gpu_product(A, B, sizer, tuning=TIERS[tier]), want)
+
+
+@pytest.mark.parametrize("n,dim,points", [(40, 2, 9), (12, 3, 27)])
+def test_wider_stencils(n, dim, points):
+    A = synth.stencil(n, dim, points)
+    want = oracle.spgemm(A, A)
+    for sizer in SIZERS:
+        assert_bit_exact(gpu_product(A, A, sizer), want)
+
+
+def test_power_law_rows():
+    A = synth.zipf_matrix(30000, 11)
+    want = oracle.spgemm(A, A)
+    for sizer in SIZERS:
+        for tier in ["default", "small_pool"]:
+            assert_bit_exact(gpu_product(A, A, sizer, tuning=TIERS[tier]), want)
+
+
+def test_fast_mode_within_tolerance():
+    A = synth.zipf_matrix(20000, 12)
+    want = oracle.spgemm(A, A)
+    got = gpu_product(A, A, "exact", fast=True, tuning=TIERS["global_only"])
+    assert_close(got, want, 1e-13)
+
+
+def test_ordered_accumulation_on_gpu():
+    # 1e16 + 1 - 1e16: only A's column order gives 0
+    A = synth.CSR(1, 3, np.array([0, 3]), np.array([0, 1, 2], np.int32), np.array([1e16, 1.0, -1e16]))
+    B = synth.CSR(3, 1, np.array([0, 1, 2, 3]), np.array([0, 0, 0], np.int32), np.ones(3))
+    for sizer in SIZERS:
+        for tier in TIERS:
+            got = gpu_product(A, B, sizer, tuning=TIERS[tier])
+            assert got[2][0] == 0.0
+
+
+def test_no_fma_on_gpu():
+    a = 1.0 + 2.0 ** -30
+    c = -(1.0 + 2.0 ** -29)
+    A = synth.CSR(1, 2, np.array([0, 2]), np.array([0, 1], np.int32), np.array([1.0, a]))
+    B = synth.CSR(2, 1, np.array([0, 1, 2]), np.array([0, 0], np.int32), np.array([c, a]))
+    for sizer in SIZERS:
+        for tier in TIERS:
+            got = gpu_product(A, B, sizer, tuning=TIERS[tier])
+            assert got[2][0] == 0.0
+
+
+def test_negative_zero_becomes_positive_zero():
+    A = synth.CSR(1, 1, np.array([0, 1]), np.array([0], np.int32), np.array([-0.0]))
+    B = synth.CSR(1, 1, np.array([0, 1]), np.array([0], np.int32), np.array([5.0]))
+    for sizer in SIZERS:
+        for tier in TIERS:
+            got = gpu_product(A, B, sizer, tuning=TIERS[tier])
+            assert bits(got[2])[0] == bits(0.0)
+
+
+@pytest.mark.parametrize("m,k,n", [(0, 0, 0), (0, 5, 3), (4, 0, 3), (4, 5, 0), (5, 4, 3)])
+def test_empty_operands(m, k, n):
+    A = synth.CSR(m, k, np.zeros(m + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    B = synth.random_sparse(k, n, 0.5, 1)
+    for sizer in SIZERS:
+        got = gpu_product(A, B, sizer)
+        assert got[0].shape == (m + 1,) and got[0][-1] == 0 and got[1].size == 0
+
+
+def test_empty_rows_between_full_rows():
+    lengths = np.where(np.arange(5000) % 3 == 0, 0, 7)
+    A = synth.random_rows(5000, 5000, lengths, 3)
+    B = synth.random_uniform_lengths(5000, 0, 9, 4)
+    want = oracle.spgemm(A, B)
+    for sizer in SIZERS:
+        assert_bit_exact(gpu_product(A, B, sizer), want)
+
+
+def test_identity_products():
+    A = synth.random_uniform_lengths(4000, 0, 20, 8)
+    I = synth.identity(4000)
+    for sizer in SIZERS:
+        assert_bit_exact(gpu_product(A, I, sizer), (A.row_ptr, A.col, A.val))
+        assert_bit_exact(gpu_product(I, A, sizer), (A.row_ptr, A.col, A.val))
+
+
+def test_dense_row_hits_every_column():
+    # one row of A selects every row of B: the output row is dense
+    n = 3000
+    A = synth.CSR(1, n, np.array([0, n]), np.arange(n, dtype=np.int32), np.ones(n))
+    B = synth.random_uniform_lengths(n, 1, 6, 9)
+    want = oracle.spgemm(A, B)
+    for sizer in SIZERS:
+        for tier in ["default", "global_only", "hash_sparse"]:
+            assert_bit_exact(gpu_product(A, B, sizer, tuning=TIERS[tier]), want)
+
+
+def test_capacity_error_reports_required_size():
+    import paper_1303_1651_amd as P
+    import torch
+    A = synth.stencil(32)
+    dA = P.DeviceCSR.from_host(A)
+    want = oracle.spgemm(A, A)
+    nnz = int(want[0][-1])
+    plan = P.Plan(dA, dA, "upper_bound")
+    rp = torch.empty(A.rows + 1, dtype=torch.int64, device="cuda")
+    col = torch.empty(nnz - 1, dtype=torch.int32, device="cuda")
+    val = torch.empty(nnz - 1, dtype=torch.float64, device="cuda")
+    code, got = plan.numeric(rp, col, val)
+    assert code == 6 and got == nnz
+    col = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    val = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    code, got = plan.numeric(rp, col, val)
+    assert code == 0 and got == nnz
+    assert_bit_exact((rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()), want)
+    plan.close()
+
+
+def test_validate_rejects_unsorted_columns():
+    import paper_1303_1651_amd as P
+    A = synth.CSR(2, 3, np.array([0, 2, 3]), np.array([2, 1, 0], np.int32), np.ones(3))
+    B = synth.random_sparse(3, 3, 0.6, 1)
+    with pytest.raises(P.SpgemmError) as e:
+        gpu_product(A, B, "exact", validate=True)
+    assert e.value.code == 3
+    # canonical input passes validation
+    A2 = synth.CSR(2, 3, np.array([0, 2, 3]), np.array([1, 2, 0], np.int32), np.ones(3))
+    assert_bit_exact(gpu_product(A2, B, "exact", validate=True), oracle.spgemm(A2, B))
+
+
+def test_repeated_runs_identical():
+    A = synth.zipf_matrix(20000, 5)
+    first = gpu_product(A, A, "upper_bound")
+    for _ in range(3):
+        again = gpu_product(A, A, "upper_bound")
+        assert_bit_exact(again, first[:3])
+
+
+# ----------------------------------------------------------- full sizes
+def test_stencil2048_full_size():
+    A = synth.stencil(2048)
+    want = oracle.spgemm(A, A)
+    for sizer in SIZERS:
+        got = gpu_product(A, A, sizer)
+        assert got[3]["multiplications"] == 104783880
+        assert int(got[0][-1]) == 54484996
+        assert_bit_exact(got, want)
+
+
+def test_random_2pow21_sampled_blocks():
+    n = 1 << 21
+    A = synth.random_fixed(n, 16, 1)
+    B = synth.random_fixed(n, 16, 2)
+    for sizer in SIZERS:
+        got = gpu_product(A, B, sizer)
+        assert got[3]["multiplications"] == n * 256
+        blocks = sample_blocks(n, 24, 512, 7)
+        check_row_blocks(got, A, B, blocks, exact=True)
+        # every row has between 16 and 256 entries
+        lens = np.diff(got[0])
+        assert lens.min() >= 16 and lens.max() <= 256
