@@ -85,7 +85,8 @@ typedef enum spgemm_sizer {
 
 enum {
     SPGEMM_OPT_FAST = 1,           /* allow reordered accumulation in workgroup-level rows  */
-    SPGEMM_OPT_VALIDATE = 2        /* check that A and B are canonical CSR                  */
+    SPGEMM_OPT_VALIDATE = 2,       /* check that A and B are canonical CSR                  */
+    SPGEMM_OPT_TIMING = 4          /* time the tile kernel with HIP events (spgemm_info)    */
 };
 
 typedef struct spgemm_model spgemm_model;   /* learned row-size network (host object) */
@@ -123,6 +124,8 @@ typedef struct spgemm_info {
     int64_t rows_merge, rows_hash, rows_global, rows_empty;  /* tier histogram          */
     int64_t overflow_rows;     /* rows whose learned capacity was too small (after numeric) */
     int64_t tiles;
+    double tile_ms;            /* SPGEMM_OPT_TIMING: duration of the last tile-kernel launch */
+    double tile_ms_total;      /* SPGEMM_OPT_TIMING: sum over the plan's tile-kernel launches */
 } spgemm_info;
 
 typedef struct spgemm_plan spgemm_plan;

@@ -187,13 +187,13 @@ class Plan:
     """One product C = A * B: plan, then (symbolic) and numeric passes."""
 
     def __init__(self, A: DeviceCSR, B: DeviceCSR, sizer="exact", model: Model | None = None,
-                 fast=False, validate=False, tuning: dict | None = None, stream=None):
+                 fast=False, validate=False, tuning: dict | None = None, stream=None, timing=False):
         self.A, self.B = A, B
         self.device = A.row_ptr.device
         self.stream = stream
         self._da, self._db = A.descriptor(), B.descriptor()
         self._tuning = make_tuning(**tuning) if tuning else None
-        flags = (OPT_FAST if fast else 0) | (OPT_VALIDATE if validate else 0)
+        flags = (OPT_FAST if fast else 0) | (OPT_VALIDATE if validate else 0) | (_lib.OPT_TIMING if timing else 0)
         self._opts = _lib.spgemm_options(SIZERS[sizer] if isinstance(sizer, str) else int(sizer), flags,
                                          model.handle if model is not None else None,
                                          ctypes.pointer(self._tuning) if self._tuning is not None else None)

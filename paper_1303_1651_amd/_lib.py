@@ -32,7 +32,7 @@ STATUS = {
     11: "SPGEMM_E_IO",
 }
 SIZER_EXACT, SIZER_UPPER_BOUND, SIZER_LEARNED = 0, 1, 2
-OPT_FAST, OPT_VALIDATE = 1, 2
+OPT_FAST, OPT_VALIDATE, OPT_TIMING = 1, 2, 4
 MLP_PARAMS = 1217
 
 
@@ -54,7 +54,8 @@ class spgemm_options(ctypes.Structure):
 class spgemm_info(ctypes.Structure):
     _fields_ = [("multiplications", I64), ("c_capacity_hint", I64), ("c_nnz", I64),
                 ("scratch_bytes", SZ), ("rows_merge", I64), ("rows_hash", I64),
-                ("rows_global", I64), ("rows_empty", I64), ("overflow_rows", I64), ("tiles", I64)]
+                ("rows_global", I64), ("rows_empty", I64), ("overflow_rows", I64), ("tiles", I64),
+                ("tile_ms", ctypes.c_double), ("tile_ms_total", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -150,6 +150,8 @@ struct spgemm_plan {
   spgemm_info info;
   hipError_t last_err;
   const spgemm_model *model;
+  hipEvent_t ev0, ev1;   // SPGEMM_OPT_TIMING
+  int timing_pending;
 };
 
 #define HIPCK(plan, expr)                                  \
@@ -182,12 +184,28 @@ static spgemm_status lookback_failed(spgemm_plan *p) {
   return SPGEMM_E_HIP;
 }
 
+// Device-side consistency failures (a key that found no slot, a numeric
+// count that differs from the symbolic one, a look-back that gave up).
+static spgemm_status device_errors(spgemm_plan *p, const int64_t *h) {
+  if (h[kCtrError] & kErrScratch) return SPGEMM_E_WORKSPACE;
+  if (h[kCtrError] & kErrLookback) return lookback_failed(p);
+  if (h[kCtrError] & kErrInconsistent) return SPGEMM_E_STATE;
+  return SPGEMM_OK;
+}
+
 // Read the device counters into the pinned host buffer (synchronises).
 static spgemm_status read_counters(spgemm_plan *p, hipStream_t s, int64_t **out) {
   int64_t *h = host_counters();
   if (!h) return SPGEMM_E_HIP;
   HIPCK(p, hipMemcpyAsync(h, ctr(p), sizeof(int64_t) * kNumCounters, hipMemcpyDeviceToHost, s));
   HIPCK(p, hipStreamSynchronize(s));
+  if (p->timing_pending) {
+    float ms = 0.f;
+    HIPCK(p, hipEventElapsedTime(&ms, p->ev0, p->ev1));
+    p->info.tile_ms = ms;
+    p->info.tile_ms_total += ms;
+    p->timing_pending = 0;
+  }
   *out = h;
   return SPGEMM_OK;
 }
@@ -282,7 +300,12 @@ static spgemm_status run_tiles(spgemm_plan *p, int mode, void *scratch, size_t s
   HIPCK(p, launch_fill_i64(ctr(p) + kCtrOverflow, 0, 1, s));
   if (mode == kOnePass) HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
   int grid = tile_grid(p, scratch_bytes);
+  if (p->ev0) HIPCK(p, hipEventRecord(p->ev0, s));
   HIPCK(p, launch_tiles(tp, mode, p->tune.hash_group, p->tune.merge_lists, grid, pool_bytes(p), s));
+  if (p->ev1) {
+    HIPCK(p, hipEventRecord(p->ev1, s));
+    p->timing_pending = 1;
+  }
   return SPGEMM_OK;
 }
 
@@ -350,6 +373,13 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   p->ws_bytes = workspace_bytes;
   p->L = L;
   p->info.c_nnz = -1;
+  if (opts->flags & SPGEMM_OPT_TIMING) {
+    if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess) {
+      if (p->ev0) (void)hipEventDestroy(p->ev0);
+      free(p);
+      return SPGEMM_E_HIP;
+    }
+  }
   char *w = p->ws;
   p->pa.counters = (int64_t *)(w + L.counters);
   p->pa.f.nnz_a = (int32_t *)(w + L.nnz_a);
@@ -369,7 +399,7 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
 
   auto fail = [&](spgemm_status e) {
     if (e != SPGEMM_OK) {
-      free(p);
+      spgemm_plan_destroy(p);
       *out = nullptr;
     }
     return e;
@@ -421,8 +451,8 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return st;
-  if (h[kCtrError] & kErrScratch) return SPGEMM_E_WORKSPACE;
-  if (h[kCtrError] & kErrLookback) return lookback_failed(p);
+  st = device_errors(p, h);
+  if (st != SPGEMM_OK) return st;
   int64_t nnz = p->A.rows > 0 ? h[kCtrNnz] : 0;
   p->info.c_nnz = nnz;
   p->info.c_capacity_hint = nnz;
@@ -457,10 +487,8 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
     int64_t *h;
     st = read_counters(p, s, &h);
     if (st != SPGEMM_OK) return st;
-    if (h[kCtrError] & kErrScratch) return SPGEMM_E_WORKSPACE;
-  if (h[kCtrError] & kErrLookback) return lookback_failed(p);
-    if (h[kCtrError] & kErrLookback) return lookback_failed(p);
-    if (h[kCtrError] & kErrInconsistent) return SPGEMM_E_STATE;
+    st = device_errors(p, h);
+    if (st != SPGEMM_OK) return st;
     *c_nnz = p->info.c_nnz;
     if (h[kCtrError] & kErrCapacity) return SPGEMM_E_CAPACITY;
     p->stage = 2;
@@ -480,8 +508,8 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return st;
-  if (h[kCtrError] & kErrScratch) return SPGEMM_E_WORKSPACE;
-  if (h[kCtrError] & kErrLookback) return lookback_failed(p);
+  st = device_errors(p, h);
+  if (st != SPGEMM_OK) return st;
   int64_t nnz = h[kCtrNnz];
   p->info.c_nnz = nnz;
   p->info.overflow_rows = h[kCtrOverflow];
@@ -499,6 +527,11 @@ spgemm_status spgemm_plan_info(const spgemm_plan *p, spgemm_info *info) {
 
 int spgemm_plan_last_hip_error(const spgemm_plan *p) { return p ? (int)p->last_err : 0; }
 
-void spgemm_plan_destroy(spgemm_plan *p) { free(p); }
+void spgemm_plan_destroy(spgemm_plan *p) {
+  if (!p) return;
+  if (p->ev0) (void)hipEventDestroy(p->ev0);
+  if (p->ev1) (void)hipEventDestroy(p->ev1);
+  free(p);
+}
 
 }  // extern "C"

@@ -491,31 +491,56 @@ __device__ void hash_row(const Operands &op, int64_t row, int32_t *keys, double 
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
   }
+  // every lane takes part in every shuffle (no short-circuit around them)
+  int32_t of = ovf ? 1 : 0;
 #pragma unroll
   for (int d = G / 2; d > 0; d >>= 1) {
     cnt += __shfl_xor(cnt, d, G);
     dmax = max(dmax, __shfl_xor(dmax, d, G));
-    ovf = ovf || (__shfl_xor((int)ovf, d, G) != 0);
+    of |= __shfl_xor(of, d, G);
   }
   if (gl == 0) {
     *cnt_out = cnt;
     *dmax_out = dmax;
-    *ovf_out = ovf ? 1 : 0;
+    *ovf_out = of;
   }
+}
+
+// The per-workgroup tables live in device memory and are written by
+// several waves: initial stores, atomic claims (performed in L2) and value
+// updates.  Reads go around the L1 cache (agent-scope atomic loads), and
+// phases are separated by agent-scope fences on both sides of the barrier,
+// so a late initial store can never land on a claimed slot and no wave
+// reads a stale L1 line.
+__device__ __forceinline__ int32_t gload(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double gloadd(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gstored(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void wg_sync_global() {
+  __threadfence();
+  __syncthreads();
+  __threadfence();
 }
 
 // Rank of the key in slot s among all keys of the table: occupied slots
 // before s, corrected for keys that probing pushed past larger ones (they
 // sit at most dmax slots after their home).
+template <bool GLOBAL = false>
 __device__ __forceinline__ int64_t rank_fix(const int32_t *keys, int64_t alloc, int64_t s,
                                             int32_t key, int32_t dmax, const RowHash &hs) {
+  auto ld = [&](int64_t q) { return GLOBAL ? gload(keys + q) : keys[q]; };
   int64_t fix = 0;
   int64_t end = min(s + (int64_t)dmax, alloc - 1);
   for (int64_t q = s + 1; q <= end; ++q) {
-    int32_t y = keys[q];
+    int32_t y = ld(q);
     fix += (y != kEmpty && y < key) ? 1 : 0;
   }
-  for (int64_t q = hs.home(key); q < s; ++q) fix -= (keys[q] > key) ? 1 : 0;
+  for (int64_t q = hs.home(key); q < s; ++q) fix -= (ld(q) > key) ? 1 : 0;
   return fix;
 }
 
@@ -609,15 +634,16 @@ __device__ __forceinline__ int32_t global_probe_insert(int32_t *keys, int64_t al
 // Slot holding key j (inserted earlier), or -1 if it is missing.
 __device__ __forceinline__ int64_t global_find(const int32_t *keys, int64_t alloc, const RowHash &hs, int32_t j) {
   for (int64_t s = hs.home(j); s < alloc; ++s)
-    if (keys[s] == j) return s;
+    if (gload(keys + s) == j) return s;
   return -1;
 }
 
 // Builds the row's key set in the table and returns its size.  The table
 // has room for every product (c >= the row's multiplication count or its
-// exact size), so no probe leaves it.
+// exact size), so no probe leaves it; a key that would is reported through
+// *err (kErrInconsistent) rather than dropped silently.
 __device__ int32_t wg_global_keys(const Operands &op, int64_t row, int32_t *keys, int64_t alloc,
-                                  const RowHash &hs, WgScratch &ws, double *vals_or_null) {
+                                  const RowHash &hs, WgScratch &ws, double *vals_or_null, int64_t *err) {
   for (int64_t s = threadIdx.x; s < alloc; s += kBlock) {
     keys[s] = kEmpty;
     if (vals_or_null) vals_or_null[s] = 0.0;
@@ -626,22 +652,24 @@ __device__ int32_t wg_global_keys(const Operands &op, int64_t row, int32_t *keys
     ws.cnt = 0;
     ws.dmax = 0;
   }
-  __syncthreads();
+  wg_sync_global();
   wg_for_products(op, row, ws, [&](int64_t bpos, double) {
     int32_t j = op.b_col[bpos];
     bool nw;
     int32_t disp;
-    global_probe_insert(keys, alloc, hs, j, &nw, &disp);
+    int32_t s = global_probe_insert(keys, alloc, hs, j, &nw, &disp);
+    if (s >= alloc) atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
     if (nw) atomicAdd(&ws.cnt, 1);
     if (disp > 0) atomicMax(&ws.dmax, disp);
   });
-  __syncthreads();
+  wg_sync_global();
   return ws.cnt;
 }
 
 // Values of the row into the table built by wg_global_keys.  Ordered: one
-// wave takes the A entries in stored order, lanes over the B row, with a
-// fence between entries.  Fast: every product at once with atomic adds.
+// wave takes the A entries in stored order, lanes over the B row (distinct
+// columns, so distinct slots), and every entry's updates complete before
+// the next entry's begin.  Fast: every product at once with atomic adds.
 __device__ void wg_global_values(const Operands &op, int64_t row, const int32_t *keys, double *vals,
                                  int64_t alloc, const RowHash &hs, WgScratch &ws, bool fast) {
   if (fast) {
@@ -664,12 +692,12 @@ __device__ void wg_global_values(const Operands &op, int64_t row, const int32_t 
       for (int64_t f = bs + threadIdx.x; f < be; f += kWave) {
         int32_t j = op.b_col[f];
         int64_t s = global_find(keys, alloc, hs, j);
-        if (s >= 0) vals[s] = mul_add_rn(vals[s], av, op.b_val[f]);
+        if (s >= 0) gstored(vals + s, mul_add_rn(gloadd(vals + s), av, op.b_val[f]));
       }
-      __threadfence_block();
+      __threadfence();
     }
   }
-  __syncthreads();
+  wg_sync_global();
 }
 
 // Sorted write-out of a device table by the whole workgroup.
@@ -679,16 +707,16 @@ __device__ void wg_global_extract(const int32_t *keys, const double *vals, int64
   int64_t run = 0;
   for (int64_t c = 0; c < alloc; c += kBlock) {
     int64_t s = c + threadIdx.x;
-    int32_t key = s < alloc ? keys[s] : kEmpty;
+    int32_t key = s < alloc ? gload(keys + s) : kEmpty;
     int64_t occ = key != kEmpty ? 1 : 0;
     int64_t tot;
     int64_t ex = block_exclusive_sum(occ, ws.wtot, &tot);
     if (occ) {
       int64_t rank = run + ex;
-      if (dmax > 0) rank += rank_fix(keys, alloc, s, key, dmax, hs);
+      if (dmax > 0) rank += rank_fix<true>(keys, alloc, s, key, dmax, hs);
       if (rank >= 0 && rank < lim) {
         out_col[rank] = key;
-        if (out_val) out_val[rank] = vals[s];
+        if (out_val) out_val[rank] = gloadd(vals + s);
       }
     }
     run += tot;
@@ -825,7 +853,8 @@ __global__ void __launch_bounds__(kBlock) k_tile(TileParams p) {
         continue;
       }
       const RowHash hs = make_hash(p.lo[row], p.hi[row], slots, dense);
-      const int32_t n = wg_global_keys(op, row, gkeys, alloc, hs, sh.ws, MODE == kNumeric ? gvals : nullptr);
+      const int32_t n = wg_global_keys(op, row, gkeys, alloc, hs, sh.ws, MODE == kNumeric ? gvals : nullptr,
+                                         p.counters + kCtrError);
       if (threadIdx.x == 0) {
         sh.cnt[r] = n;
         sh.dmax[r] = sh.ws.dmax;
@@ -920,7 +949,7 @@ __global__ void __launch_bounds__(kBlock) k_tile(TileParams p) {
         const int64_t alloc = global_table_alloc(span, c, &dense, &slots);
         if (alloc > p.scratch_slots) continue;
         const RowHash hs = make_hash(p.lo[row], p.hi[row], slots, dense);
-        wg_global_keys(op, row, gkeys, alloc, hs, sh.ws, gvals);
+        wg_global_keys(op, row, gkeys, alloc, hs, sh.ws, gvals, p.counters + kCtrError);
         wg_global_values(op, row, gkeys, gvals, alloc, hs, sh.ws, p.fast != 0);
         const int64_t o = sh.out[r];
         const int64_t lim = max((int64_t)0, min((int64_t)sh.cnt[r], p.c_capacity - o));

@@ -259,3 +259,16 @@ def batch_mix(count: int, seed: int, lo: int = 256, hi: int = 65536, rmin: int =
             B = random_uniform_lengths(n, rmin, rmax, _sub_seed(seed, 1001 + 2 * i))
             out.append(BatchInstance("random", A, B))
     return out
+
+
+# ------------------------------------------------ row-size network start
+def mlp_init(seed: int, hidden: int = 32) -> np.ndarray:
+    """Starting parameters of the 3-32-32-1 row-size network, flat in the
+    order W1 (32x3), b1, W2 (32x32), b2, w3, b3: weights uniform in
+    +-sqrt(6 / fan_in) (He et al., 2015, uniform form), biases zero."""
+    u = uniform_pm1(splitmix64(_sub_seed(seed, 8), np.arange(hidden * 3 + hidden * hidden + hidden, dtype=np.uint64)))
+    w1 = u[:hidden * 3] * math.sqrt(6.0 / 3.0)
+    w2 = u[hidden * 3:hidden * 3 + hidden * hidden] * math.sqrt(6.0 / hidden)
+    w3 = u[hidden * 3 + hidden * hidden:] * math.sqrt(6.0 / hidden)
+    z = np.zeros(hidden)
+    return np.concatenate([w1, z, w2, z, w3, [0.0]])
