@@ -117,11 +117,15 @@ constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagPre = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1ull;
 
+// The status word carries everything a successor needs (flag and value in
+// one 64-bit atomic), so relaxed agent-scope accesses suffice: they bypass
+// the non-coherent caches without the L2 write-back (release) or
+// invalidation (acquire) that stronger orderings cost on a multi-XCD part.
 __device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t status_load(uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Called by all 64 lanes of ONE wave.  Publishes the tile's aggregate, walks

@@ -21,6 +21,7 @@
 #include "../../include/spgemm.h"
 #include "device_common.h"
 #include "spgemm_internal.h"
+#include "spgemm_kernels.h"
 
 namespace spg {
 
@@ -67,13 +68,39 @@ __device__ __forceinline__ float predict_one(const float *__restrict__ dev, int3
   return (float)f3 + rho * (float)(f2 - f3);
 }
 
+// The same prediction computed by a half-wave of 32 lanes: lane j owns
+// hidden unit j of both layers.  W (LDS) holds the device parameter block;
+// hbuf (LDS, 32 floats per half-wave) passes the first layer across lanes.
+// Every lane of the half-wave returns the prediction.
+__device__ __forceinline__ float predict_coop(const float *W, float *hbuf, int32_t f1, int32_t f2, int32_t f3) {
+  const int j = lane_id() & 31;
+  float x[3];
+  mlp_inputs(W + kMlpParams, W + kMlpParams + 3, f1, f2, f3, x);
+  float a1 = W[OB1 + j];
+  a1 = fmaf(W[OW1 + 3 * j + 0], x[0], a1);
+  a1 = fmaf(W[OW1 + 3 * j + 1], x[1], a1);
+  a1 = fmaf(W[OW1 + 3 * j + 2], x[2], a1);
+  hbuf[j] = fmaxf(a1, 0.0f);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  float a2 = W[OB2 + j];
+#pragma unroll 8
+  for (int i = 0; i < H; ++i) a2 = fmaf(W[OW2 + H * j + i], hbuf[i], a2);
+  float z = W[OW3 + j] * fmaxf(a2, 0.0f);
+#pragma unroll
+  for (int d = 16; d > 0; d >>= 1) z += __shfl_xor(z, d, 32);
+  z += W[OB3];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const float rho = logistic(z);
+  return (float)f3 + rho * (float)(f2 - f3);
+}
+
 // ---------------------------------------------------------------- predict
 // Rows with the same feature triple get the same prediction, and sparse
 // matrices repeat triples heavily (a stencil has a handful).  Each
 // workgroup collects the distinct triples of its 2048 rows in an LDS hash,
 // evaluates the network once per distinct triple (one per lane), and hands
 // the results back to the rows.
-constexpr int kPredRowsPerThread = 8;
+constexpr int kPredRowsPerThread = 4;
 constexpr int kPredRows = kBlock * kPredRowsPerThread;
 constexpr int kPredTab = 2 * kPredRows;
 constexpr uint64_t kNoKey = 1ull << 63;
@@ -90,33 +117,65 @@ __device__ __forceinline__ uint32_t triple_hash(uint64_t k) {
   return (uint32_t)k & (kPredTab - 1);
 }
 
-__global__ void __launch_bounds__(kBlock) k_mlp_predict(const float *__restrict__ dev, const int32_t *f1,
-                                                        const int32_t *f2, const int32_t *f3, int64_t n,
-                                                        float *pred) {
+// KEYS: the rows' packed feature triples come from `keys` (written by the
+// feature kernel; all ones when a field did not fit) and only
+// per-workgroup partial sums of the learned capacity are written.
+// Otherwise the features come from the per-row arrays and the prediction
+// of every row is stored.
+template <bool KEYS>
+__global__ void __launch_bounds__(kBlock) k_mlp_predict(const float *__restrict__ dev, const uint64_t *rowkeys,
+                                                        const int32_t *f1a, const int32_t *f2a, const int32_t *f3a,
+                                                        int64_t n, float *pred, float margin, int slack,
+                                                        int64_t *partials) {
   __shared__ unsigned long long keys[kPredTab];
   __shared__ int32_t slot_idx[kPredTab];
   __shared__ uint64_t ukey[kPredRows];
   __shared__ float upred[kPredRows];
   __shared__ int64_t wtot[kWavesPerBlock + 1];
+  __shared__ float W[kMlpDevFloats];
+  __shared__ float hbuf[kBlock / 32][32];
   for (int s = threadIdx.x; s < kPredTab; s += kBlock) keys[s] = kNoKey;
+  for (int s = threadIdx.x; s < kMlpDevFloats; s += kBlock) W[s] = dev[s];
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kPredRows;
   uint64_t mine[kPredRowsPerThread];
 #pragma unroll
   for (int j = 0; j < kPredRowsPerThread; ++j) {
-    int64_t r = base + j * kBlock + threadIdx.x;
+    const int64_t r = base + j * kBlock + threadIdx.x;
     mine[j] = kNoKey;
     if (r < n) {
-      uint64_t k = triple_key(f1[r], f2[r], f3[r]);
-      mine[j] = k;
-      if (k != kNoKey) {
-        uint32_t s = triple_hash(k);
+      if (KEYS) {
+        const uint64_t k = rowkeys[r];
+        mine[j] = (k == ~0ull) ? kNoKey : k;
+      } else {
+        mine[j] = triple_key(f1a[r], f2a[r], f3a[r]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kPredRowsPerThread; ++j) {
+    // one insertion per distinct triple per wave: the lowest lane holding a
+    // triple inserts it for every lane that holds the same one (rows of a
+    // stencil share a handful of triples; contended atomics on one LDS slot
+    // would serialise them)
+    uint64_t pending = __ballot(mine[j] != kNoKey);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const uint64_t lk = __shfl(mine[j], leader, kWave);
+      const uint64_t same = __ballot(mine[j] == lk);
+      if (lane_id() == leader) {
+        uint32_t s = triple_hash(lk);
         while (true) {
-          unsigned long long old = atomicCAS(&keys[s], (unsigned long long)kNoKey, (unsigned long long)k);
-          if (old == kNoKey || old == k) break;
+          unsigned long long cur = keys[s];
+          if (cur == lk) break;
+          if (cur == kNoKey) {
+            unsigned long long old = atomicCAS(&keys[s], (unsigned long long)kNoKey, (unsigned long long)lk);
+            if (old == kNoKey || old == lk) break;
+          }
           s = (s + 1) & (kPredTab - 1);
         }
       }
+      pending &= ~same;
     }
   }
   __syncthreads();
@@ -137,36 +196,76 @@ __global__ void __launch_bounds__(kBlock) k_mlp_predict(const float *__restrict_
     }
   }
   __syncthreads();
-  for (int u = threadIdx.x; u < total; u += kBlock) {
-    uint64_t k = ukey[u];
-    int32_t a = (int32_t)(k & ((1u << 21) - 1));
-    int32_t b = (int32_t)((k >> 21) & ((1u << 22) - 1));
-    int32_t c = (int32_t)(k >> 43);
-    upred[u] = predict_one(dev, a, b, c);
+  // distinct triples, one per half-wave at a time (uniform trip count per
+  // half-wave, so every lane of it takes part in every shuffle)
+  const int half = threadIdx.x / 32;
+  for (int u0 = 0; u0 < total; u0 += kBlock / 32) {
+    const int u = u0 + half;
+    if (u < total) {
+      const uint64_t k = ukey[u];
+      const int32_t a = (int32_t)(k & ((1u << 21) - 1));
+      const int32_t b = (int32_t)((k >> 21) & ((1u << 22) - 1));
+      const int32_t c = (int32_t)(k >> 43);
+      const float pr = predict_coop(W, hbuf[half], a, b, c);
+      if ((threadIdx.x & 31) == 0) upred[u] = pr;
+    }
   }
   __syncthreads();
+  int64_t capsum = 0;
 #pragma unroll
   for (int j = 0; j < kPredRowsPerThread; ++j) {
-    int64_t r = base + j * kBlock + threadIdx.x;
+    const int64_t r = base + j * kBlock + threadIdx.x;
     if (r >= n) continue;
-    uint64_t k = mine[j];
+    const uint64_t k = mine[j];
     float p;
+    int32_t b, c;
     if (k == kNoKey) {
-      p = predict_one(dev, f1[r], f2[r], f3[r]);
+      // features too large to pack: the row is sized by its bound (its
+      // multiplication count) instead of a prediction
+      if (KEYS) {
+        p = -1.0f;
+        b = c = 0;
+      } else {
+        b = f2a[r];
+        c = f3a[r];
+        p = (float)b;
+      }
     } else {
       uint32_t s = triple_hash(k);
       while (keys[s] != k) s = (s + 1) & (kPredTab - 1);
       p = upred[slot_idx[s]];
+      b = (int32_t)((k >> 21) & ((1u << 22) - 1));
+      c = (int32_t)(k >> 43);
     }
-    pred[r] = p;
+    if (!KEYS) pred[r] = p;
+    if (p >= 0.0f) capsum += learned_capacity(p, b, c, margin, slack);
+  }
+  if (partials) {
+    int64_t tot;
+    block_exclusive_sum(capsum, wtot, &tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
   }
 }
 
+int64_t mlp_predict_blocks(int64_t n) { return (n + kPredRows - 1) / kPredRows; }
+
 hipError_t launch_mlp_predict(const float *dev, const int32_t *f1, const int32_t *f2, const int32_t *f3,
-                              int64_t n, float *pred, hipStream_t s) {
+                              int64_t n, float *pred, hipStream_t s, float margin, int slack,
+                              int64_t *partials) {
   if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + kPredRows - 1) / kPredRows;
-  hipLaunchKernelGGL(k_mlp_predict, dim3((unsigned)blocks), dim3(kBlock), 0, s, dev, f1, f2, f3, n, pred);
+  int64_t blocks = mlp_predict_blocks(n);
+  hipLaunchKernelGGL(k_mlp_predict<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, dev, (const uint64_t *)nullptr,
+                     f1, f2, f3, n, pred, margin, slack, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_capacity(const float *dev, const uint64_t *rowkeys, int64_t n, hipStream_t s, float margin,
+                               int slack, int64_t *partials) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = mlp_predict_blocks(n);
+  hipLaunchKernelGGL(k_mlp_predict<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, dev, rowkeys,
+                     (const int32_t *)nullptr, (const int32_t *)nullptr, (const int32_t *)nullptr, n, (float *)nullptr,
+                     margin, slack, partials);
   return hipGetLastError();
 }
 

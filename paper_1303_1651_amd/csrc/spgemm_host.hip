@@ -46,7 +46,7 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace carve-up: every array 256-byte aligned.
 struct Layout {
-  size_t counters, model, nnz_a, ub, maxb, lo, hi, pred, cnt, info, cap, cost, tile_row, status, scan_status, total;
+  size_t counters, model, partials, keys, nnz_a, ub, maxb, lo, hi, pred, cnt, info, cap, cost, tile_row, status, scan_status, total;
 };
 
 Layout layout_for(int64_t rows) {
@@ -62,6 +62,8 @@ Layout layout_for(int64_t rows) {
   const size_t scan_tiles = R / 2048 + 2;
   L.counters = take(sizeof(int64_t) * kNumCounters);
   L.model = take(sizeof(float) * kMlpDevFloats);
+  L.partials = take(sizeof(int64_t) * 8 * (R / 256 + 2));
+  L.keys = take(sizeof(uint64_t) * R);
   L.nnz_a = take(4 * R);
   L.ub = take(4 * R);
   L.maxb = take(4 * R);
@@ -113,7 +115,7 @@ static bool tuning_ok(const spgemm_tuning &t) {
   bool g_ok = t.hash_group == 4 || t.hash_group == 8 || t.hash_group == 16 || t.hash_group == 32 ||
               t.hash_group == 64;
   return g_ok && t.pool_slots >= 0 && t.pool_slots <= 12288 && t.max_tile_rows >= 1 &&
-         t.max_tile_rows <= kMaxTileRows && t.merge_lists == 8 && t.merge_max_nnz >= 0 &&
+         t.max_tile_rows <= kMaxTileRows && (t.merge_lists == 4 || t.merge_lists == 8) && t.merge_max_nnz >= 0 &&
          t.dense_ratio >= 0 && t.margin >= 0 && t.slack >= 0 && t.blocks_per_cu >= 1 &&
          t.blocks_per_cu <= 16;
 }
@@ -147,9 +149,12 @@ struct spgemm_plan {
   int64_t scratch_slots_plan;
   int grid;
   int has_pool;
+  int has_hash;
+  int merge_only;      // every row takes the register-merge tier: row-per-thread kernels
   spgemm_info info;
   hipError_t last_err;
   const spgemm_model *model;
+  uint64_t *keys;        // packed feature triple per row
   hipEvent_t ev0, ev1;   // SPGEMM_OPT_TIMING
   int timing_pending;
 };
@@ -226,10 +231,6 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   sp.pred = p->pa.pred;
   sp.cnt = p->pa.cnt;
   Operands op = operands_of(p, nullptr, nullptr);
-  // zero the per-pass counters (tier histogram, capacity sum, scratch need)
-  HIPCK(p, launch_fill_i64(ctr(p) + kCtrCapSum, 0, 1, s));
-  HIPCK(p, launch_fill_i64(ctr(p) + kCtrMerge, 0, 4, s));
-  HIPCK(p, launch_fill_i64(ctr(p) + kCtrScratch, 0, 1, s));
   HIPCK(p, launch_size_rows(op, p->pa, sp, s));
   const int64_t R = p->A.rows;
   HIPCK(p, launch_scan_i64_inplace(p->pa.cost, R, p->pa.scan_status, ctr(p) + kCtrScanTicket,
@@ -242,7 +243,8 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   if (h[kCtrError] & kErrLookback) return lookback_failed(p);
   p->ntiles = h[kCtrTiles];
   p->scratch_slots = (h[kCtrScratch] + 1) & ~(int64_t)1;
-  p->has_pool = h[kCtrHash] > 0;
+  p->has_pool = h[kCtrPoolRows] > 0;
+  p->has_hash = h[kCtrHash] + h[kCtrGlobal] > 0;
   p->cur_mode = mode;
   p->info.rows_merge = h[kCtrMerge];
   p->info.rows_hash = h[kCtrHash];
@@ -301,7 +303,8 @@ static spgemm_status run_tiles(spgemm_plan *p, int mode, void *scratch, size_t s
   if (mode == kOnePass) HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
   int grid = tile_grid(p, scratch_bytes);
   if (p->ev0) HIPCK(p, hipEventRecord(p->ev0, s));
-  HIPCK(p, launch_tiles(tp, mode, p->tune.hash_group, p->tune.merge_lists, grid, pool_bytes(p), s));
+  HIPCK(p, launch_tiles(tp, mode, p->tune.hash_group, p->tune.merge_lists, p->has_hash != 0, grid,
+                        pool_bytes(p), s));
   if (p->ev1) {
     HIPCK(p, hipEventRecord(p->ev1, s));
     p->timing_pending = 1;
@@ -395,6 +398,8 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   p->pa.tile_row = (int32_t *)(w + L.tile_row);
   p->pa.status = (uint64_t *)(w + L.status);
   p->pa.scan_status = (uint64_t *)(w + L.scan_status);
+  p->pa.partials = (int64_t *)(w + L.partials);
+  p->keys = (uint64_t *)(w + L.keys);
   hipStream_t s = (hipStream_t)stream;
 
   auto fail = [&](spgemm_status e) {
@@ -414,20 +419,53 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
     if (h[kCtrError] & kErrNotCanonical) return fail(SPGEMM_E_NOT_CANONICAL);
   }
   Operands op = operands_of(p, nullptr, nullptr);
-  if (launch_features(op, p->pa.f, p->pa.counters, s) != hipSuccess) return fail(SPGEMM_E_HIP);
-  if (opts->sizer == SPGEMM_SIZER_LEARNED) {
-    float *dev = (float *)(w + L.model);
+  p->first_mode = opts->sizer == SPGEMM_SIZER_EXACT ? kSymbolic : kOnePass;
+  const bool learned = opts->sizer == SPGEMM_SIZER_LEARNED;
+  float *dev = (float *)(w + L.model);
+  if (learned) {
     st = spgemm_model_upload(p->model, dev, stream);
     if (st != SPGEMM_OK) return fail(st);
-    if (launch_mlp_predict(dev, p->pa.f.nnz_a, p->pa.f.ub, p->pa.f.maxb, A->rows, p->pa.pred, s) != hipSuccess)
+  }
+  // Row sums (multiplications, longest A row, empty rows) and, for the
+  // learned sizer, the packed feature triple of every row and the learned
+  // capacity; one synchronisation.
+  if (launch_features(op, p->pa.f, p->keys, p->pa.counters, p->pa.partials, learned ? 1 : 0, s) != hipSuccess)
+    return fail(SPGEMM_E_HIP);
+  if (learned) {
+    if (launch_mlp_capacity(dev, p->keys, A->rows, s, p->tune.margin, p->tune.slack, p->pa.partials) != hipSuccess)
+      return fail(SPGEMM_E_HIP);
+    const int32_t dst[1] = {kCtrCapSum};
+    if (launch_sum_partials(p->pa.partials, std::max<int64_t>(1, mlp_predict_blocks(A->rows)), 1, 1, dst, nullptr,
+                            p->pa.counters, s) != hipSuccess)
       return fail(SPGEMM_E_HIP);
   }
-  p->first_mode = opts->sizer == SPGEMM_SIZER_EXACT ? kSymbolic : kOnePass;
-  st = size_pass(p, p->first_mode, s);
-  if (st != SPGEMM_OK) return fail(st);
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return fail(st);
+  // Every row merges in registers when no row of A has more stored entries
+  // than the merge tier's lists (and the tier is not switched off); then no
+  // per-row plan arrays are needed.
+  p->merge_only = A->rows > 0 && h[kCtrMaxA] <= p->tune.merge_lists && p->tune.merge_max_nnz > 0;
+  if (p->merge_only) {
+    p->info.rows_empty = h[kCtrEmpty];
+    p->info.rows_merge = A->rows - h[kCtrEmpty];
+    p->info.tiles = (A->rows + 63) / 64;
+    p->info.c_capacity_hint = learned ? h[kCtrCapSum] + h[kCtrUnpacked] : h[kCtrMults];
+    p->ntiles = p->info.tiles;
+    p->cur_mode = p->first_mode;
+  } else {
+    if (launch_features(op, p->pa.f, p->keys, p->pa.counters, p->pa.partials, 2, s) != hipSuccess)
+      return fail(SPGEMM_E_HIP);
+    if (learned) {
+      if (launch_mlp_predict(dev, p->pa.f.nnz_a, p->pa.f.ub, p->pa.f.maxb, A->rows, p->pa.pred, s, p->tune.margin,
+                             p->tune.slack, nullptr) != hipSuccess)
+        return fail(SPGEMM_E_HIP);
+    }
+    st = size_pass(p, p->first_mode, s);
+    if (st != SPGEMM_OK) return fail(st);
+    st = read_counters(p, s, &h);
+    if (st != SPGEMM_OK) return fail(st);
+  }
   p->info.multiplications = h[kCtrMults];
   p->scratch_slots_plan = p->scratch_slots;
   // room for one table per resident workgroup
@@ -443,9 +481,15 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
   if (!p || !c_row_ptr || !c_nnz) return SPGEMM_E_NULL;
   if (p->first_mode != kSymbolic || p->stage != 0) return SPGEMM_E_STATE;
   hipStream_t s = (hipStream_t)stream;
-  spgemm_status st = run_tiles(p, kSymbolic, scratch, scratch_bytes, nullptr, nullptr, nullptr, nullptr,
-                               nullptr, 0, s);
-  if (st != SPGEMM_OK) return st;
+  spgemm_status st = SPGEMM_OK;
+  if (p->merge_only) {
+    HIPCK(p, launch_fill_i64(ctr(p) + kCtrError, 0, 1, s));
+    HIPCK(p, launch_wave_merge(operands_of(p, nullptr, nullptr), kSymbolic, p->tune.merge_lists, ctr(p),
+                               p->pa.status, p->pa.cnt, nullptr, nullptr, nullptr, 0, s));
+  } else {
+    st = run_tiles(p, kSymbolic, scratch, scratch_bytes, nullptr, nullptr, nullptr, nullptr, nullptr, 0, s);
+    if (st != SPGEMM_OK) return st;
+  }
   HIPCK(p, launch_scan_i32(p->pa.cnt, c_row_ptr, p->A.rows, p->pa.scan_status, ctr(p) + kCtrScanTicket,
                            ctr(p) + kCtrNnz, ctr(p) + kCtrError, s));
   int64_t *h;
@@ -458,8 +502,10 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
   p->info.c_capacity_hint = nnz;
   *c_nnz = nnz;
   // size the numeric pass from the exact counts
-  st = size_pass(p, kNumeric, s);
-  if (st != SPGEMM_OK) return st;
+  if (!p->merge_only) {
+    st = size_pass(p, kNumeric, s);
+    if (st != SPGEMM_OK) return st;
+  }
   p->info.c_capacity_hint = nnz;
   p->stage = 1;
   return SPGEMM_OK;
@@ -481,9 +527,20 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
       *c_nnz = p->info.c_nnz;
       return SPGEMM_E_CAPACITY;
     }
-    spgemm_status st = run_tiles(p, kNumeric, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val,
-                                 c_capacity, s);
-    if (st != SPGEMM_OK) return st;
+    spgemm_status st = SPGEMM_OK;
+    if (p->merge_only) {
+      HIPCK(p, launch_fill_i64(ctr(p) + kCtrError, 0, 1, s));
+      if (p->ev0) HIPCK(p, hipEventRecord(p->ev0, s));
+      HIPCK(p, launch_wave_merge(operands_of(p, av, bv), kNumeric, p->tune.merge_lists, ctr(p), p->pa.status,
+                                 nullptr, c_row_ptr, c_col, c_val, c_capacity, s));
+      if (p->ev1) {
+        HIPCK(p, hipEventRecord(p->ev1, s));
+        p->timing_pending = 1;
+      }
+    } else {
+      st = run_tiles(p, kNumeric, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+      if (st != SPGEMM_OK) return st;
+    }
     int64_t *h;
     st = read_counters(p, s, &h);
     if (st != SPGEMM_OK) return st;
@@ -502,9 +559,22 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
     p->info.c_nnz = 0;
     return SPGEMM_OK;
   }
-  spgemm_status st = run_tiles(p, kOnePass, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val,
-                               c_capacity, s);
-  if (st != SPGEMM_OK) return st;
+  spgemm_status st = SPGEMM_OK;
+  if (p->merge_only) {
+    HIPCK(p, launch_fill_i64(ctr(p) + kCtrTicket, 0, 1, s));
+    HIPCK(p, launch_fill_i64(ctr(p) + kCtrError, 0, 1, s));
+    HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
+    if (p->ev0) HIPCK(p, hipEventRecord(p->ev0, s));
+    HIPCK(p, launch_wave_merge(operands_of(p, av, bv), kOnePass, p->tune.merge_lists, ctr(p), p->pa.status,
+                               nullptr, c_row_ptr, c_col, c_val, c_capacity, s));
+    if (p->ev1) {
+      HIPCK(p, hipEventRecord(p->ev1, s));
+      p->timing_pending = 1;
+    }
+  } else {
+    st = run_tiles(p, kOnePass, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+    if (st != SPGEMM_OK) return st;
+  }
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return st;

@@ -18,7 +18,23 @@ int64_t *host_counters();
 // Predicted nnz(C_row) for n rows; dev_params holds kMlpDevFloats floats
 // (theta, mu, sd) already on the device.
 hipError_t launch_mlp_predict(const float *dev_params, const int32_t *f1, const int32_t *f2,
-                              const int32_t *f3, int64_t n, float *pred, hipStream_t s);
+                              const int32_t *f3, int64_t n, float *pred, hipStream_t s, float margin = 0.f,
+                              int slack = 0, int64_t *partials = nullptr);
+int64_t mlp_predict_blocks(int64_t n);
+// Learned capacity summed per workgroup (partials[b]) from the packed
+// feature triples of the rows (rows whose triple did not fit count 0 and
+// are covered by the caller).
+hipError_t launch_mlp_capacity(const float *dev_params, const uint64_t *rowkeys, int64_t n, hipStream_t s,
+                               float margin, int slack, int64_t *partials);
+
+// Capacity of a row sized by the learned prediction: ceil(pred * (1 +
+// margin)) + slack, clamped to [longest selected B row, multiplication
+// count].  Shared by the sizing kernel and the prediction kernel.
+__host__ __device__ inline int64_t learned_capacity(float pred, int32_t ub, int32_t maxb, float margin, int slack) {
+  double want = ceil((double)pred * (1.0 + (double)margin)) + (double)slack;
+  double c = want < (double)maxb ? (double)maxb : want;
+  return (int64_t)(c > (double)ub ? (double)ub : c);
+}
 
 }  // namespace spg
 

@@ -39,6 +39,8 @@ enum Counter : int {
   kCtrScanTicket = 12,
   kCtrPoolRows = 13,   // rows that use the LDS pool
   kCtrMaxCap = 14,
+  kCtrMaxA = 15,       // longest row of A
+  kCtrUnpacked = 16,   // summed bounds of rows whose feature triple does not pack
   kNumCounters = 32
 };
 enum : int64_t { kErrCapacity = 1, kErrNotCanonical = 2, kErrInconsistent = 4, kErrScratch = 8, kErrLookback = 16 };
@@ -87,6 +89,7 @@ struct PlanArrays {
   int64_t *counters;
   int32_t *cnt;         // exact per-row counts (symbolic output)
   float *pred;          // learned prediction
+  int64_t *partials;    // per-workgroup partial sums of the sizing kernel (8 per workgroup)
 };
 
 struct TileParams {
@@ -122,7 +125,11 @@ hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_validate(const int64_t *rp, const int32_t *col, int64_t rows, int64_t cols,
                            int64_t nnz, int64_t *counters, hipStream_t s);
-hipError_t launch_features(const Operands &op, const Features &f, int64_t *counters, hipStream_t s);
+// mode 0: sums only; 1: plus a packed feature triple per row (keys); 2: plus
+// the per-row plan arrays in f.
+hipError_t launch_features(const Operands &op, const Features &f, uint64_t *keys, int64_t *counters,
+                           int64_t *partials, int mode, hipStream_t s);
+hipError_t launch_row_max(const int64_t *rp, int64_t rows, int64_t *counters, int64_t *partials, hipStream_t s);
 hipError_t launch_size_rows(const Operands &op, const PlanArrays &pa, const SizeParams &sp,
                             hipStream_t s);
 // exclusive scan of rows int32 (or int64 when in64) values into out[0..n], out[n] = total
@@ -132,8 +139,14 @@ hipError_t launch_scan_i64_inplace(int64_t *inout, int64_t n, uint64_t *status, 
                                    int64_t *err, hipStream_t s);
 hipError_t launch_tile_bounds(const int64_t *cost, int64_t rows, int64_t half_pool,
                               int32_t *tile_row, int64_t *counters, hipStream_t s);
-hipError_t launch_tiles(const TileParams &tp, int mode, int group, int merge_lists, int grid,
+hipError_t launch_tiles(const TileParams &tp, int mode, int group, int merge_lists, bool hash, int grid,
                         size_t lds_bytes, hipStream_t s);
 size_t tile_static_lds(int mode);
+hipError_t launch_sum_partials(const int64_t *partials, int64_t nblocks, int n, int stride, const int32_t *dst,
+                               const int32_t *is_max, int64_t *counters, hipStream_t s);
+// Row-per-thread merge kernels for matrices whose rows all take the merge tier.
+hipError_t launch_wave_merge(const Operands &op, int mode, int merge_lists, int64_t *counters, uint64_t *status,
+                             int32_t *cnt_out, int64_t *c_rp, int32_t *c_col, double *c_val, int64_t c_capacity,
+                             hipStream_t s);
 
 }  // namespace spg
