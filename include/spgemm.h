@@ -92,19 +92,19 @@ enum {
 typedef struct spgemm_model spgemm_model;   /* learned row-size network (host object) */
 
 /* Launch and tier parameters.  Zero fields take the library defaults; the
-  * autotuner fills them for a workload family.  pool_slots = -1 means no LDS
- * pool (every row that is not merged goes to the workgroup-level tier);
- * merge_max_nnz = -1 turns the register-merge tier off. */
+ * autotuner fills them for a workload family.  table_slots = -1 turns the
+ * wave hash tier off (every row that is not merged goes to the workgroup
+ * tier); merge_max_nnz = -1 turns the register-merge tier off. */
 typedef struct spgemm_tuning {
-    int32_t hash_group;      /* lanes per row in the LDS hash tier: 4..64, power of two   */
-    int32_t pool_slots;      /* LDS accumulator slots per workgroup (12 bytes each)        */
-    int32_t max_tile_rows;   /* rows per tile, <= 512                                      */
+    int32_t table_slots;     /* largest LDS hash table of a wave: 256..4096, power of two   */
+    int32_t stage_slots;     /* LDS staging of a wave tile (entries): 256..8192, with
+                                12 * (table_slots + stage_slots) <= 147456 bytes          */
     int32_t merge_max_nnz;   /* register-merge tier: largest row (entries) it takes        */
     int32_t merge_lists;     /* register-merge tier: max stored entries of the A row (4/8) */
     float dense_ratio;       /* dense window used when column span <= ratio * capacity     */
     float margin;            /* learned sizing: capacity = pred * (1 + margin) + slack     */
     int32_t slack;
-    int32_t blocks_per_cu;   /* persistent workgroups per compute unit                     */
+    int32_t blocks_per_cu;   /* workgroups per compute unit of the workgroup-tier kernel   */
 } spgemm_tuning;
 
 typedef struct spgemm_options {
@@ -122,10 +122,14 @@ typedef struct spgemm_info {
     int64_t c_nnz;             /* exact nnz(C) once known (after symbolic or numeric), else -1 */
     size_t scratch_bytes;      /* scratch the numeric (and symbolic) call needs            */
     int64_t rows_merge, rows_hash, rows_global, rows_empty;  /* tier histogram          */
-    int64_t overflow_rows;     /* rows whose learned capacity was too small (after numeric) */
-    int64_t tiles;
-    double tile_ms;            /* SPGEMM_OPT_TIMING: duration of the last tile-kernel launch */
-    double tile_ms_total;      /* SPGEMM_OPT_TIMING: sum over the plan's tile-kernel launches */
+    int64_t overflow_rows;     /* one pass: rows whose output did not fit the wave's staging
+                                  (capacity too small) and were computed again            */
+    int64_t tiles;             /* wave tiles of the current pass                           */
+    double tile_ms;            /* SPGEMM_OPT_TIMING: duration of the last pass's row kernels
+                                  (wave tiles and workgroup-tier rows, one event pair)      */
+    double tile_ms_total;      /* SPGEMM_OPT_TIMING: sum over the plan's passes            */
+    int64_t grid_retries;      /* one pass: times the persistent grid was found not resident
+                                  as a whole and the wave tiles ran again with a smaller one */
 } spgemm_info;
 
 typedef struct spgemm_plan spgemm_plan;

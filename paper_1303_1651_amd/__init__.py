@@ -66,7 +66,10 @@ def _bytes(n: int, device) -> torch.Tensor:
 
 def make_tuning(**kw) -> _lib.spgemm_tuning:
     t = _lib.spgemm_tuning()
+    names = {f for f, _ in t._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise KeyError("unknown tuning field %r (fields: %s)" % (k, ", ".join(sorted(names))))
         setattr(t, k, v)
     return t
 

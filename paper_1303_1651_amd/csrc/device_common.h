@@ -137,8 +137,11 @@ __device__ __forceinline__ uint64_t status_load(uint64_t *p) {
 // and raises *err so the host reports a failure.
 constexpr int64_t kSpinLimit = 1ll << 24;
 
+// abort_bit: give up at once when another workgroup has raised that flag in
+// *err (the result is then discarded by the host).
 __device__ inline int64_t lookback_exclusive(uint64_t *status, int64_t tile, int64_t aggregate,
-                                             int64_t *err = nullptr, int64_t err_bit = 0) {
+                                             int64_t *err = nullptr, int64_t err_bit = 0,
+                                             int64_t abort_bit = 0) {
   int l = lane_id();
   int64_t polls = 0;
   if (tile == 0) {
@@ -160,6 +163,11 @@ __device__ inline int64_t lookback_exclusive(uint64_t *status, int64_t tile, int
       if (++polls > kSpinLimit) {
         if (l == 0 && err) atomicOr((unsigned long long *)err, (unsigned long long)err_bit);
         break;
+      }
+      if (abort_bit && (polls & 255) == 0) {
+        const int64_t e = __shfl(l == 0 ? __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0, 0,
+                                 kWave);
+        if (e & abort_bit) break;
       }
       __builtin_amdgcn_s_sleep(1);
       continue;

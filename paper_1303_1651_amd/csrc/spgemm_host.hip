@@ -46,7 +46,7 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace carve-up: every array 256-byte aligned.
 struct Layout {
-  size_t counters, model, partials, keys, nnz_a, ub, maxb, lo, hi, pred, cnt, info, cap, cost, tile_row, status, scan_status, total;
+  size_t counters, model, partials, keys, nnz_a, ub, maxb, lo, hi, pred, cnt, info, cap, cost, tile_row, status, scan_status, big, total;
 };
 
 Layout layout_for(int64_t rows) {
@@ -77,18 +77,17 @@ Layout layout_for(int64_t rows) {
   L.tile_row = take(4 * (tiles_max + 1));
   L.status = take(8 * tiles_max);
   L.scan_status = take(8 * scan_tiles);
+  L.big = take(4 * R);
   L.total = o;
   return L;
 }
 
 spgemm_tuning default_tuning(const spgemm_csr *A, const spgemm_csr *B) {
+  (void)A;
+  (void)B;
   spgemm_tuning t{};
-  double avg_b = B->rows > 0 ? (double)B->nnz / (double)B->rows : 1.0;
-  int g = 4;
-  while (g < 64 && g < avg_b) g <<= 1;
-  t.hash_group = g;
-  t.pool_slots = 4096;
-  t.max_tile_rows = 256;
+  t.table_slots = 1024;
+  t.stage_slots = 1024;
   t.merge_max_nnz = 64;
   t.merge_lists = 8;
   t.dense_ratio = 2.0f;
@@ -100,9 +99,8 @@ spgemm_tuning default_tuning(const spgemm_csr *A, const spgemm_csr *B) {
 
 static void merge_tuning(spgemm_tuning *t, const spgemm_tuning *u) {
   if (!u) return;
-  if (u->hash_group) t->hash_group = u->hash_group;
-  if (u->pool_slots) t->pool_slots = u->pool_slots < 0 ? 0 : u->pool_slots;
-  if (u->max_tile_rows) t->max_tile_rows = u->max_tile_rows;
+  if (u->table_slots) t->table_slots = u->table_slots < 0 ? 0 : u->table_slots;
+  if (u->stage_slots) t->stage_slots = u->stage_slots;
   if (u->merge_max_nnz) t->merge_max_nnz = u->merge_max_nnz < 0 ? 0 : u->merge_max_nnz;
   if (u->merge_lists) t->merge_lists = u->merge_lists;
   if (u->dense_ratio > 0) t->dense_ratio = u->dense_ratio;
@@ -112,11 +110,11 @@ static void merge_tuning(spgemm_tuning *t, const spgemm_tuning *u) {
 }
 
 static bool tuning_ok(const spgemm_tuning &t) {
-  bool g_ok = t.hash_group == 4 || t.hash_group == 8 || t.hash_group == 16 || t.hash_group == 32 ||
-              t.hash_group == 64;
-  return g_ok && t.pool_slots >= 0 && t.pool_slots <= 12288 && t.max_tile_rows >= 1 &&
-         t.max_tile_rows <= kMaxTileRows && (t.merge_lists == 4 || t.merge_lists == 8) && t.merge_max_nnz >= 0 &&
-         t.dense_ratio >= 0 && t.margin >= 0 && t.slack >= 0 && t.blocks_per_cu >= 1 &&
+  const int ts = t.table_slots;
+  const bool t_ok = ts == 0 || ts == 256 || ts == 512 || ts == 1024 || ts == 2048 || ts == 4096;
+  return t_ok && t.stage_slots >= 256 && t.stage_slots <= 8192 &&
+         12 * ((int64_t)t.table_slots + t.stage_slots) <= 147456 && (t.merge_lists == 4 || t.merge_lists == 8) &&
+         t.merge_max_nnz >= 0 && t.dense_ratio >= 0 && t.margin >= 0 && t.slack >= 0 && t.blocks_per_cu >= 1 &&
          t.blocks_per_cu <= 16;
 }
 
@@ -145,11 +143,12 @@ struct spgemm_plan {
   int first_mode;      // kSymbolic (EXACT) or kOnePass
   int cur_mode;        // mode the current tiles were sized for
   int64_t ntiles;
+  int64_t nbig;            // workgroup-tier rows of the current sizing
   int64_t scratch_slots;   // per workgroup, current sizing
   int64_t scratch_slots_plan;
-  int grid;
-  int has_pool;
-  int has_hash;
+  int64_t scratch_rows;    // rows that may need a workgroup-tier table (plan sizing)
+  int table_launch;        // LDS table slots of the wave-tile launch
+  int stage_launch;        // LDS staging entries of the wave-tile launch
   int merge_only;      // every row takes the register-merge tier: row-per-thread kernels
   spgemm_info info;
   hipError_t last_err;
@@ -193,6 +192,7 @@ static spgemm_status lookback_failed(spgemm_plan *p) {
 // count that differs from the symbolic one, a look-back that gave up).
 static spgemm_status device_errors(spgemm_plan *p, const int64_t *h) {
   if (h[kCtrError] & kErrScratch) return SPGEMM_E_WORKSPACE;
+  if (h[kCtrError] & kErrResidency) return lookback_failed(p);
   if (h[kCtrError] & kErrLookback) return lookback_failed(p);
   if (h[kCtrError] & kErrInconsistent) return SPGEMM_E_STATE;
   return SPGEMM_OK;
@@ -217,14 +217,17 @@ static spgemm_status read_counters(spgemm_plan *p, hipStream_t s, int64_t **out)
 
 // Sizing of one pass (tiers, capacities, tile costs) plus tile bounds.
 static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
+  const int tvals = p->tune.table_slots;                   // values table (numeric, one pass)
+  const int tkeys = std::min(4 * tvals, 16384);            // keys-only table (symbolic): same bytes
+  const int stage = p->tune.stage_slots;
   SizeParams sp{};
   sp.mode = mode;
   sp.sizer = p->opts.sizer;
-  sp.pool_slots = p->tune.pool_slots;
-  sp.pad = 16;
+  sp.table_max = mode == kSymbolic ? tkeys : tvals;
+  sp.value_table_max = tvals;
+  sp.stage = stage;
   sp.merge_lists = p->tune.merge_lists;
-  sp.merge_max = p->tune.merge_max_nnz;
-  sp.tile_rows = p->tune.max_tile_rows;
+  sp.merge_max = std::min(p->tune.merge_max_nnz, stage / 2);
   sp.dense_ratio = p->tune.dense_ratio;
   sp.margin = p->tune.margin;
   sp.slack = p->tune.slack;
@@ -233,18 +236,22 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   Operands op = operands_of(p, nullptr, nullptr);
   HIPCK(p, launch_size_rows(op, p->pa, sp, s));
   const int64_t R = p->A.rows;
-  HIPCK(p, launch_scan_i64_inplace(p->pa.cost, R, p->pa.scan_status, ctr(p) + kCtrScanTicket,
-                                   ctr(p) + kCtrError, s));
-  HIPCK(p, launch_tile_bounds(p->pa.cost, R, tile_budget(p->tune.pool_slots, p->tune.max_tile_rows),
-                              p->pa.tile_row, ctr(p), s));
+  if (mode != kSymbolic) {
+    HIPCK(p, launch_scan_i64_inplace(p->pa.cost, R, p->pa.scan_status, ctr(p) + kCtrScanTicket,
+                                     ctr(p) + kCtrError, s));
+    HIPCK(p, launch_tile_bounds(p->pa.cost, R, stage / 2, p->pa.tile_row, ctr(p), s));
+  }
   int64_t *h;
   spgemm_status st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return st;
   if (h[kCtrError] & kErrLookback) return lookback_failed(p);
-  p->ntiles = h[kCtrTiles];
+  p->ntiles = mode == kSymbolic ? (R + 63) / 64 : h[kCtrTiles];
+  p->nbig = h[kCtrGlobal];
   p->scratch_slots = (h[kCtrScratch] + 1) & ~(int64_t)1;
-  p->has_pool = h[kCtrPoolRows] > 0;
-  p->has_hash = h[kCtrHash] + h[kCtrGlobal] > 0;
+  p->scratch_rows = h[kCtrScratchRows];
+  p->table_launch = (int)h[kCtrTable];
+  // staging: every row of a one-pass tile; merge rows only in the numeric pass
+  p->stage_launch = mode == kOnePass ? stage : (mode == kNumeric && h[kCtrMerge] > 0 ? stage : 0);
   p->cur_mode = mode;
   p->info.rows_merge = h[kCtrMerge];
   p->info.rows_hash = h[kCtrHash];
@@ -255,60 +262,109 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   return SPGEMM_OK;
 }
 
-static int tile_grid(const spgemm_plan *p, size_t scratch_bytes) {
-  int64_t g = (int64_t)device_cus() * p->tune.blocks_per_cu;
-  g = std::min<int64_t>(g, std::max<int64_t>(p->ntiles, 1));
-  if (p->scratch_slots > 0) {
-    int64_t by_scratch = (int64_t)(scratch_bytes / ((size_t)p->scratch_slots * 12));
-    g = std::min(g, by_scratch);
+static void timing_begin(spgemm_plan *p, hipStream_t s, hipError_t *e) {
+  if (p->ev0 && *e == hipSuccess) *e = hipEventRecord(p->ev0, s);
+}
+static void timing_end(spgemm_plan *p, hipStream_t s, hipError_t *e) {
+  if (p->ev1 && *e == hipSuccess) {
+    *e = hipEventRecord(p->ev1, s);
+    if (*e == hipSuccess) p->timing_pending = 1;
   }
-  return (int)g;
 }
 
-static size_t pool_bytes(const spgemm_plan *p) {
-  if (!p->has_pool) return 0;
-  return (((size_t)p->tune.pool_slots * 4 + 15) & ~(size_t)15) + (size_t)p->tune.pool_slots * 8;
+// Wave tiles of one pass (the caller has sized the pass).
+// Resident one-pass grid found by measurement, per LDS size (the occupancy
+// estimate can exceed what the hardware keeps resident together).
+struct GridMemo {
+  size_t lds;
+  int merge_lists;
+  int64_t grid;
+};
+static std::mutex g_grid_mu;
+static std::vector<GridMemo> g_grid_memo;
+
+static int64_t grid_memo_get(size_t lds, int merge_lists) {
+  std::lock_guard<std::mutex> lk(g_grid_mu);
+  for (const GridMemo &m : g_grid_memo)
+    if (m.lds == lds && m.merge_lists == merge_lists) return m.grid;
+  return 0;
 }
 
-static spgemm_status run_tiles(spgemm_plan *p, int mode, void *scratch, size_t scratch_bytes,
-                               const double *a_val, const double *b_val, int64_t *c_rp, int32_t *c_col,
-                               double *c_val, int64_t c_capacity, hipStream_t s) {
+static void grid_memo_put(size_t lds, int merge_lists, int64_t grid) {
+  std::lock_guard<std::mutex> lk(g_grid_mu);
+  for (GridMemo &m : g_grid_memo)
+    if (m.lds == lds && m.merge_lists == merge_lists) {
+      m.grid = grid;
+      return;
+    }
+  g_grid_memo.push_back({lds, merge_lists, grid});
+}
+
+static spgemm_status run_wave(spgemm_plan *p, int mode, const double *a_val, const double *b_val, int64_t *c_rp,
+                              int32_t *c_col, double *c_val, int64_t c_capacity, hipStream_t s, int64_t grid_cap = 0) {
   if (p->ntiles == 0) return SPGEMM_OK;
-  if (p->scratch_slots > 0 && (!scratch || scratch_bytes < (size_t)p->scratch_slots * 12))
-    return SPGEMM_E_WORKSPACE;
-  TileParams tp{};
-  tp.op = operands_of(p, a_val, b_val);
-  tp.info = p->pa.info;
-  tp.cap = p->pa.cap;
-  tp.ub = p->pa.f.ub;
-  tp.lo = p->pa.f.lo;
-  tp.hi = p->pa.f.hi;
-  tp.cost = p->pa.cost;
-  tp.tile_row = p->pa.tile_row;
-  tp.counters = ctr(p);
-  tp.status = p->pa.status;
-  tp.cnt_out = p->pa.cnt;
-  tp.c_rp = c_rp;
-  tp.c_col = c_col;
-  tp.c_val = c_val;
-  tp.c_capacity = c_capacity;
-  tp.scratch = static_cast<char *>(scratch);
-  tp.scratch_slots = p->scratch_slots;
-  tp.pool_slots = p->tune.pool_slots;
-  tp.pad = 16;
-  tp.fast = (p->opts.flags & SPGEMM_OPT_FAST) ? 1 : 0;
-  HIPCK(p, launch_fill_i64(ctr(p) + kCtrTicket, 0, 1, s));
+  WaveTileParams wp{};
+  wp.op = operands_of(p, a_val, b_val);
+  wp.info = p->pa.info;
+  wp.cap = p->pa.cap;
+  wp.maxb = p->pa.f.maxb;
+  wp.lo = p->pa.f.lo;
+  wp.tile_row = mode == kSymbolic ? nullptr : p->pa.tile_row;
+  wp.big_cnt = p->pa.cnt;
+  wp.ntiles = p->ntiles;
+  wp.counters = ctr(p);
+  wp.status = p->pa.status;
+  wp.cnt_out = p->pa.cnt;
+  wp.c_rp = c_rp;
+  wp.c_col = c_col;
+  wp.c_val = c_val;
+  wp.c_capacity = c_capacity;
+  wp.table_slots = p->table_launch;
+  wp.stage_slots = p->stage_launch;
+  if (mode == kOnePass) {
+    HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
+    HIPCK(p, launch_fill_i64(ctr(p) + kCtrResident, 0, 2, s));
+    if (grid_cap == 0) grid_cap = grid_memo_get(wave_tile_lds(mode, wp.table_slots, wp.stage_slots), p->tune.merge_lists);
+  }
+  HIPCK(p, launch_wave_tiles(wp, mode, p->tune.merge_lists, grid_cap, s));
+  return SPGEMM_OK;
+}
+
+// Workgroup-tier rows of one pass: one workgroup per row, device tables in
+// the caller's scratch.
+static spgemm_status run_big(spgemm_plan *p, int mode, void *scratch, size_t scratch_bytes, const double *a_val,
+                             const double *b_val, int64_t *c_rp, int32_t *c_col, double *c_val, int64_t c_capacity,
+                             hipStream_t s) {
+  if (p->nbig == 0) return SPGEMM_OK;
+  const size_t per = (size_t)p->scratch_slots * 12;
+  if (per > 0 && (!scratch || scratch_bytes < per)) return SPGEMM_E_WORKSPACE;
+  BigParams bp{};
+  bp.op = operands_of(p, a_val, b_val);
+  bp.list = p->pa.big;
+  bp.ub = p->pa.f.ub;
+  bp.maxb = p->pa.f.maxb;
+  bp.cnt = p->pa.cnt;
+  bp.lo = p->pa.f.lo;
+  bp.hi = p->pa.f.hi;
+  bp.counters = ctr(p);
+  bp.c_rp = c_rp;
+  bp.c_col = c_col;
+  bp.c_val = c_val;
+  bp.c_capacity = c_capacity;
+  bp.scratch = static_cast<char *>(scratch);
+  bp.scratch_slots = p->scratch_slots;
+  bp.fast = (p->opts.flags & SPGEMM_OPT_FAST) ? 1 : 0;
+  int64_t g = (int64_t)device_cus() * p->tune.blocks_per_cu;
+  g = std::min(g, p->nbig);
+  if (per > 0) g = std::min<int64_t>(g, (int64_t)(scratch_bytes / per));
+  HIPCK(p, launch_big_rows(bp, mode == kSymbolic ? kSymbolic : kNumeric, (int)g, s));
+  return SPGEMM_OK;
+}
+
+static spgemm_status clear_run_counters(spgemm_plan *p, hipStream_t s) {
   HIPCK(p, launch_fill_i64(ctr(p) + kCtrError, 0, 1, s));
   HIPCK(p, launch_fill_i64(ctr(p) + kCtrOverflow, 0, 1, s));
-  if (mode == kOnePass) HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
-  int grid = tile_grid(p, scratch_bytes);
-  if (p->ev0) HIPCK(p, hipEventRecord(p->ev0, s));
-  HIPCK(p, launch_tiles(tp, mode, p->tune.hash_group, p->tune.merge_lists, p->has_hash != 0, grid,
-                        pool_bytes(p), s));
-  if (p->ev1) {
-    HIPCK(p, hipEventRecord(p->ev1, s));
-    p->timing_pending = 1;
-  }
+  HIPCK(p, launch_fill_i64(ctr(p) + kCtrTicket, 0, 1, s));
   return SPGEMM_OK;
 }
 
@@ -399,6 +455,7 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   p->pa.status = (uint64_t *)(w + L.status);
   p->pa.scan_status = (uint64_t *)(w + L.scan_status);
   p->pa.partials = (int64_t *)(w + L.partials);
+  p->pa.big = (int32_t *)(w + L.big);
   p->keys = (uint64_t *)(w + L.keys);
   hipStream_t s = (hipStream_t)stream;
 
@@ -468,8 +525,9 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   }
   p->info.multiplications = h[kCtrMults];
   p->scratch_slots_plan = p->scratch_slots;
-  // room for one table per resident workgroup
-  int64_t groups = (int64_t)device_cus() * p->tune.blocks_per_cu;
+  // room for one table per resident workgroup of the workgroup-tier kernel
+  // (no more workgroups than rows that may need one)
+  int64_t groups = std::min<int64_t>((int64_t)device_cus() * p->tune.blocks_per_cu, std::max<int64_t>(p->scratch_rows, 1));
   p->info.scratch_bytes = (size_t)(p->scratch_slots * 12) * (size_t)groups;
   if (info) *info = p->info;
   *out = p;
@@ -481,15 +539,21 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
   if (!p || !c_row_ptr || !c_nnz) return SPGEMM_E_NULL;
   if (p->first_mode != kSymbolic || p->stage != 0) return SPGEMM_E_STATE;
   hipStream_t s = (hipStream_t)stream;
-  spgemm_status st = SPGEMM_OK;
+  spgemm_status st = clear_run_counters(p, s);
+  if (st != SPGEMM_OK) return st;
+  hipError_t e = hipSuccess;
+  timing_begin(p, s, &e);
+  HIPCK(p, e);
   if (p->merge_only) {
-    HIPCK(p, launch_fill_i64(ctr(p) + kCtrError, 0, 1, s));
     HIPCK(p, launch_wave_merge(operands_of(p, nullptr, nullptr), kSymbolic, p->tune.merge_lists, ctr(p),
                                p->pa.status, p->pa.cnt, nullptr, nullptr, nullptr, 0, s));
   } else {
-    st = run_tiles(p, kSymbolic, scratch, scratch_bytes, nullptr, nullptr, nullptr, nullptr, nullptr, 0, s);
+    st = run_wave(p, kSymbolic, nullptr, nullptr, nullptr, nullptr, nullptr, 0, s);
+    if (st == SPGEMM_OK) st = run_big(p, kSymbolic, scratch, scratch_bytes, nullptr, nullptr, nullptr, nullptr, nullptr, 0, s);
     if (st != SPGEMM_OK) return st;
   }
+  timing_end(p, s, &e);
+  HIPCK(p, e);
   HIPCK(p, launch_scan_i32(p->pa.cnt, c_row_ptr, p->A.rows, p->pa.scan_status, ctr(p) + kCtrScanTicket,
                            ctr(p) + kCtrNnz, ctr(p) + kCtrError, s));
   int64_t *h;
@@ -499,7 +563,6 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
   if (st != SPGEMM_OK) return st;
   int64_t nnz = p->A.rows > 0 ? h[kCtrNnz] : 0;
   p->info.c_nnz = nnz;
-  p->info.c_capacity_hint = nnz;
   *c_nnz = nnz;
   // size the numeric pass from the exact counts
   if (!p->merge_only) {
@@ -521,69 +584,71 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
   const double *bv = b_val ? b_val : p->B.val;
   if ((p->A.nnz > 0 && !av) || (p->B.nnz > 0 && !bv)) return SPGEMM_E_NULL;
   hipStream_t s = (hipStream_t)stream;
-  if (p->first_mode == kSymbolic) {
+  const bool two_pass = p->first_mode == kSymbolic;
+  if (two_pass) {
     if (p->stage < 1) return SPGEMM_E_STATE;
     if (p->info.c_nnz > c_capacity) {
       *c_nnz = p->info.c_nnz;
       return SPGEMM_E_CAPACITY;
     }
-    spgemm_status st = SPGEMM_OK;
-    if (p->merge_only) {
-      HIPCK(p, launch_fill_i64(ctr(p) + kCtrError, 0, 1, s));
-      if (p->ev0) HIPCK(p, hipEventRecord(p->ev0, s));
-      HIPCK(p, launch_wave_merge(operands_of(p, av, bv), kNumeric, p->tune.merge_lists, ctr(p), p->pa.status,
-                                 nullptr, c_row_ptr, c_col, c_val, c_capacity, s));
-      if (p->ev1) {
-        HIPCK(p, hipEventRecord(p->ev1, s));
-        p->timing_pending = 1;
-      }
-    } else {
-      st = run_tiles(p, kNumeric, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
-      if (st != SPGEMM_OK) return st;
-    }
-    int64_t *h;
-    st = read_counters(p, s, &h);
-    if (st != SPGEMM_OK) return st;
-    st = device_errors(p, h);
-    if (st != SPGEMM_OK) return st;
-    *c_nnz = p->info.c_nnz;
-    if (h[kCtrError] & kErrCapacity) return SPGEMM_E_CAPACITY;
-    p->stage = 2;
-    return SPGEMM_OK;
-  }
-  // one-pass sizers
-  if (p->A.rows == 0) {
+  } else if (p->A.rows == 0) {
     HIPCK(p, launch_fill_i64(c_row_ptr, 0, 1, s));
     HIPCK(p, hipStreamSynchronize(s));
     *c_nnz = 0;
     p->info.c_nnz = 0;
+    p->stage = 2;
     return SPGEMM_OK;
   }
-  spgemm_status st = SPGEMM_OK;
+  spgemm_status st = clear_run_counters(p, s);
+  if (st != SPGEMM_OK) return st;
+  const int mode = two_pass ? kNumeric : kOnePass;
+  if (p->merge_only && mode == kOnePass) HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
+  hipError_t e = hipSuccess;
+  timing_begin(p, s, &e);
+  HIPCK(p, e);
   if (p->merge_only) {
-    HIPCK(p, launch_fill_i64(ctr(p) + kCtrTicket, 0, 1, s));
-    HIPCK(p, launch_fill_i64(ctr(p) + kCtrError, 0, 1, s));
-    HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
-    if (p->ev0) HIPCK(p, hipEventRecord(p->ev0, s));
-    HIPCK(p, launch_wave_merge(operands_of(p, av, bv), kOnePass, p->tune.merge_lists, ctr(p), p->pa.status,
-                               nullptr, c_row_ptr, c_col, c_val, c_capacity, s));
-    if (p->ev1) {
-      HIPCK(p, hipEventRecord(p->ev1, s));
-      p->timing_pending = 1;
-    }
+    HIPCK(p, launch_wave_merge(operands_of(p, av, bv), mode, p->tune.merge_lists, ctr(p), p->pa.status, nullptr,
+                               c_row_ptr, c_col, c_val, c_capacity, s));
   } else {
-    st = run_tiles(p, kOnePass, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+    // one pass: workgroup-tier rows are counted first, the wave tiles then
+    // place every row, and those rows are written last
+    if (mode == kOnePass)
+      st = run_big(p, kSymbolic, scratch, scratch_bytes, av, bv, nullptr, nullptr, nullptr, 0, s);
+    if (st == SPGEMM_OK) st = run_wave(p, mode, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+    if (st == SPGEMM_OK)
+      st = run_big(p, kNumeric, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
     if (st != SPGEMM_OK) return st;
   }
+  timing_end(p, s, &e);
+  HIPCK(p, e);
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return st;
+  // a one-pass grid that was not resident as a whole stopped early: run the
+  // wave tiles (and the rows after them) again with a grid of 7/8 of the
+  // workgroups found resident together, and remember it for this LDS size
+  for (int round = 1; !p->merge_only && mode == kOnePass && (h[kCtrError] & kErrResidency) && round <= 4; ++round) {
+    const int64_t seen = h[kCtrResidentSeen];
+    const int64_t cap = std::max<int64_t>(1, seen > 8 ? seen - seen / 8 : seen / 2);
+    grid_memo_put(wave_tile_lds(kOnePass, p->table_launch, p->stage_launch), p->tune.merge_lists, cap);
+    p->info.grid_retries = round;
+    HIPCK(p, launch_fill_i64(ctr(p) + kCtrError, 0, 1, s));
+    HIPCK(p, launch_fill_i64(ctr(p) + kCtrOverflow, 0, 1, s));
+    st = run_wave(p, mode, av, bv, c_row_ptr, c_col, c_val, c_capacity, s, cap);
+    if (st == SPGEMM_OK)
+      st = run_big(p, kNumeric, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+    if (st == SPGEMM_OK) st = read_counters(p, s, &h);
+    if (st != SPGEMM_OK) return st;
+  }
   st = device_errors(p, h);
   if (st != SPGEMM_OK) return st;
-  int64_t nnz = h[kCtrNnz];
-  p->info.c_nnz = nnz;
-  p->info.overflow_rows = h[kCtrOverflow];
-  *c_nnz = nnz;
+  if (two_pass) {
+    *c_nnz = p->info.c_nnz;
+  } else {
+    p->info.c_nnz = h[kCtrNnz];
+    p->info.overflow_rows = h[kCtrOverflow];
+    *c_nnz = h[kCtrNnz];
+  }
   if (h[kCtrError] & kErrCapacity) return SPGEMM_E_CAPACITY;
   p->stage = 2;
   return SPGEMM_OK;

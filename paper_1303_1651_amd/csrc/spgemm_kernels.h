@@ -9,12 +9,12 @@
 namespace spg {
 
 // Per-row tier.  EMPTY rows produce nothing; MERGE rows are merged in
-// registers by one thread; HASH rows accumulate in a slice of the
-// workgroup's LDS pool, one group of lanes per row; GLOBAL rows (too large
-// for LDS) accumulate in a per-workgroup table in device memory.
+// registers by one lane; HASH rows accumulate in the LDS table of a wave,
+// the whole wave on one row; GLOBAL rows (too large for a wave's table)
+// accumulate in a per-workgroup table in device memory.
 enum Tier : uint32_t { kTierEmpty = 0, kTierMerge = 1, kTierHash = 2, kTierGlobal = 3 };
 
-// info word of a row: bits 0-1 tier, bit 2 dense window, bits 3-31 slots.
+// info word of a row: bits 0-1 tier, bit 2 dense window, bits 3-31 table slots.
 __host__ __device__ inline uint32_t pack_info(uint32_t tier, bool dense, uint32_t slots) {
   return tier | (dense ? 4u : 0u) | (slots << 3);
 }
@@ -31,19 +31,26 @@ enum Counter : int {
   kCtrTiles = 1,       // number of tiles
   kCtrMults = 2,       // sum of per-row multiplication counts (exact, int64)
   kCtrCapSum = 3,      // sum of per-row capacities (learned capacity hint)
-  kCtrMerge = 4, kCtrHash = 5, kCtrGlobal = 6, kCtrEmpty = 7,
+  kCtrMerge = 4, kCtrHash = 5,
+  kCtrGlobal = 6,      // workgroup-tier rows (length of the list in PlanArrays::big)
+  kCtrEmpty = 7,
   kCtrOverflow = 8,    // one-pass rows whose capacity was too small
   kCtrScratch = 9,     // largest device table (slots) a workgroup-level row needs
   kCtrError = 10,      // bit flags, see kErr*
   kCtrNnz = 11,        // nnz(C) after a one-pass numeric
   kCtrScanTicket = 12,
-  kCtrPoolRows = 13,   // rows that use the LDS pool
-  kCtrMaxCap = 14,
   kCtrMaxA = 15,       // longest row of A
   kCtrUnpacked = 16,   // summed bounds of rows whose feature triple does not pack
+  kCtrTable = 17,      // largest wave table (slots) a hashed row uses
+  kCtrScratchRows = 18,  // rows that may need a workgroup-tier device table
+  kCtrResident = 19,   // one-pass workgroups that have started
+  kCtrResidentSeen = 20,  // workgroups found resident together when a one-pass grid was too large
   kNumCounters = 32
 };
-enum : int64_t { kErrCapacity = 1, kErrNotCanonical = 2, kErrInconsistent = 4, kErrScratch = 8, kErrLookback = 16 };
+enum : int64_t {
+  kErrCapacity = 1, kErrNotCanonical = 2, kErrInconsistent = 4, kErrScratch = 8, kErrLookback = 16,
+  kErrResidency = 32   // a one-pass grid was not resident as a whole (the host retries smaller)
+};
 
 struct Operands {
   const int64_t *a_rp;
@@ -66,11 +73,11 @@ struct Features {
 struct SizeParams {
   int mode;             // Mode of the pass being sized
   int sizer;            // spgemm_sizer for kOnePass
-  int pool_slots;       // LDS pool of one workgroup (slots)
-  int pad;              // probe room after a hashed table
+  int table_max;        // largest wave table (slots); 0: no wave hash tier
+  int value_table_max;  // kSymbolic: the numeric pass's largest table (scratch sizing)
+  int stage;            // LDS staging entries of a wave tile
   int merge_lists;      // template M of the merge tier
   int merge_max;        // largest capacity the merge tier takes
-  int tile_rows;        // target rows per tile
   float dense_ratio;
   float margin;
   int slack;
@@ -90,35 +97,47 @@ struct PlanArrays {
   int32_t *cnt;         // exact per-row counts (symbolic output)
   float *pred;          // learned prediction
   int64_t *partials;    // per-workgroup partial sums of the sizing kernel (8 per workgroup)
+  int32_t *big;         // workgroup-tier rows (any order)
 };
 
-struct TileParams {
+constexpr int64_t kMinTable = 64;   // smallest hashed wave table (slots)
+
+struct WaveTileParams {
   Operands op;
   const uint32_t *info;
   const int32_t *cap;
-  const int32_t *ub;
-  const int32_t *lo, *hi;
-  const int64_t *cost;      // exclusive prefix of tile cost
-  const int32_t *tile_row;
+  const int32_t *maxb;
+  const int32_t *lo;
+  const int32_t *tile_row;  // tile bounds (ntiles + 1); null: tiles of 64 rows
+  const int32_t *big_cnt;   // kOnePass: exact counts of workgroup-tier rows
+  int64_t ntiles;
   int64_t *counters;
-  uint64_t *status;
+  uint64_t *status;         // kOnePass: look-back status, one per tile
   int32_t *cnt_out;         // kSymbolic
   int64_t *c_rp;            // kNumeric: input; kOnePass: output
   int32_t *c_col;
   double *c_val;
   int64_t c_capacity;
-  char *scratch;            // per-workgroup device tables
-  int64_t scratch_slots;    // slots per workgroup
-  int pool_slots;
-  int pad;
-  int fast;                 // reordered accumulation allowed in workgroup-level rows
+  int table_slots;          // LDS table of a wave (slots)
+  int stage_slots;          // LDS staging of a wave (entries), >= table_slots
 };
 
-constexpr int kMaxTileRows = 512;
-
-__host__ __device__ inline int64_t tile_budget(int pool_slots, int tile_rows) {
-  return pool_slots > 0 ? (int64_t)(pool_slots / 2) : (int64_t)tile_rows;
-}
+struct BigParams {
+  Operands op;
+  const int32_t *list;      // workgroup-tier rows, counters[kCtrGlobal] of them
+  const int32_t *ub;
+  const int32_t *maxb;
+  int32_t *cnt;             // kSymbolic: output; kNumeric: exact counts
+  const int32_t *lo, *hi;
+  int64_t *counters;
+  const int64_t *c_rp;
+  int32_t *c_col;
+  double *c_val;
+  int64_t c_capacity;
+  char *scratch;            // per-workgroup device tables
+  int64_t scratch_slots;    // slots per workgroup
+  int fast;                 // reordered accumulation allowed
+};
 
 // ---- launchers (spgemm_kernels.hip) ----
 hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
@@ -139,9 +158,10 @@ hipError_t launch_scan_i64_inplace(int64_t *inout, int64_t n, uint64_t *status, 
                                    int64_t *err, hipStream_t s);
 hipError_t launch_tile_bounds(const int64_t *cost, int64_t rows, int64_t half_pool,
                               int32_t *tile_row, int64_t *counters, hipStream_t s);
-hipError_t launch_tiles(const TileParams &tp, int mode, int group, int merge_lists, bool hash, int grid,
-                        size_t lds_bytes, hipStream_t s);
-size_t tile_static_lds(int mode);
+size_t wave_tile_lds(int mode, int table_slots, int stage_slots);
+// grid_cap > 0 bounds the one-pass grid (else: the occupancy estimate)
+hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, int64_t grid_cap, hipStream_t s);
+hipError_t launch_big_rows(const BigParams &bp, int mode, int grid, hipStream_t s);
 hipError_t launch_sum_partials(const int64_t *partials, int64_t nblocks, int n, int stride, const int32_t *dst,
                                const int32_t *is_max, int64_t *counters, hipStream_t s);
 // Row-per-thread merge kernels for matrices whose rows all take the merge tier.

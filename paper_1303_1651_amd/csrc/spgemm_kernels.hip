@@ -272,25 +272,11 @@ hipError_t launch_row_max(const int64_t *rp, int64_t rows, int64_t *counters, in
 }
 
 // ------------------------------------------------------------ sizing/tiers
-// Table of a hashed row: T slots for capacity c (load <= 1/2) plus `pad`
-// slots of probe room; a dense window when the column region is at most
-// dense_ratio * c (the paper's "Combined" rule of Section IV-B: MinMax when
-// the region is smaller than twice the row's entries, Sort otherwise).
-__device__ __forceinline__ void table_shape(int64_t span, int64_t c, float dense_ratio, int pad,
-                                            bool *dense, int64_t *slots, int64_t *alloc) {
-  if ((double)span <= (double)dense_ratio * (double)c) {
-    *dense = true;
-    *slots = span;
-    *alloc = span;
-  } else {
-    *dense = false;
-    *slots = max((int64_t)16, 2 * c);
-    *alloc = *slots + pad;
-  }
-}
-
-// Device table of a workgroup-level row: capacity c, load <= 1/2, and c
-// slots of probe room so that linear probing can never run off the end.
+// Device table of a workgroup-tier row: capacity c, load <= 1/2, and c
+// slots of probe room so that linear probing can never run off the end; a
+// dense window when the column region is at most twice the capacity (the
+// paper's "Combined" rule of Section IV-B: MinMax when the region is
+// smaller than twice the row's entries, Sort otherwise).
 __device__ __forceinline__ int64_t global_table_alloc(int64_t span, int64_t c, bool *dense,
                                                        int64_t *slots) {
   if (span <= 2 * c) {
@@ -303,92 +289,136 @@ __device__ __forceinline__ int64_t global_table_alloc(int64_t span, int64_t c, b
   return *slots + c;
 }
 
+// Slots global_table_alloc takes for any capacity up to c (a smaller exact
+// count may trade a dense window for a hashed table).
+__device__ __forceinline__ int64_t global_table_bound(int64_t c) { return 3 * c + 16; }
+
+constexpr int64_t kSortMax = 1024;   // keys a wave sorts in registers (64 lanes x 16)
+
+// Smallest power of two >= x, at least kMinTable.
+__device__ __forceinline__ int64_t table_pow2(int64_t x) {
+  int64_t t = kMinTable;
+  while (t < x) t <<= 1;
+  return t;
+}
+
+// Tier, capacity and tile cost of every row for one pass.
+//   capacity c: the multiplication count (symbolic, upper-bound sizer), the
+//     exact count (numeric pass of the two-pass path) or the learned
+//     capacity (learned sizer);
+//   EMPTY  when the row has no products;
+//   MERGE  when the A row has at most merge_lists entries and c <= merge_max;
+//   HASH   when the wave's LDS table holds the row: a dense window of the
+//          column region when it is at most dense_ratio * c (and fits), else
+//          a power-of-two table with load <= 1/2 (symbolic: 2 * bound;
+//          numeric: 2 * exact count; one pass: above the bound and at least
+//          2 * capacity, so it can never fill, or just above the bound when
+//          that is too large);
+//   GLOBAL otherwise (a workgroup per row, table in device memory); these
+//          rows are listed in pa.big.
+// Tile cost (staged entries) bounds what a wave tile stages in LDS:
+// min(c, HT) with HT = stage / 2, at least ceil(HT / 64) so a tile holds at
+// most 64 rows.  The symbolic pass stages nothing: cost 1, tiles of 64 rows.
+// The numeric pass stages merge rows only (hashed rows know their place in
+// C and go there directly).
 __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa, SizeParams sp) {
   __shared__ int64_t s_red[7][kWavesPerBlock];
-  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  // Tile budget HT (cost units): half the LDS pool when there is one, so a
-  // tile's hashed rows always fit the pool; every row costs at least
-  // ceil(HT / tile_rows), so a tile holds at most tile_rows rows.
-  const int64_t H = sp.pool_slots / 2;
-  const int64_t HT = tile_budget(sp.pool_slots, sp.tile_rows);
-  const int64_t mincost = H > 0 ? (H + sp.tile_rows - 1) / sp.tile_rows : 1;
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  const bool sym = sp.mode == kSymbolic;
+  const int64_t HT = sym ? kWave : sp.stage / 2;
+  const int64_t mincost = sym ? 1 : (HT + kWave - 1) / kWave;
   int64_t n_tier[4] = {0, 0, 0, 0};
-  int64_t capsum = 0, scratch = 0, pool_rows = 0;
+  int64_t capsum = 0, scratch = 0, tmax = 0;
+  bool big = false;
   if (i < op.rows) {
-    int32_t m = pa.f.nnz_a[i];
-    int64_t ub = pa.f.ub[i];
-    int64_t mx = pa.f.maxb[i];
+    const int32_t m = pa.f.nnz_a[i];
+    const int64_t ub = pa.f.ub[i];
+    const int64_t mx = pa.f.maxb[i];
     int64_t c;
-    if (sp.mode == kNumeric) {
-      c = sp.cnt[i];
-    } else if (sp.mode == kOnePass && sp.sizer == 2) {
-      c = learned_capacity(sp.pred[i], (int32_t)ub, (int32_t)mx, sp.margin, sp.slack);
-    } else {
-      c = ub;
-    }
+    if (sp.mode == kNumeric) c = sp.cnt[i];
+    else if (sp.mode == kOnePass && sp.sizer == 2) c = learned_capacity(sp.pred[i], (int32_t)ub, (int32_t)mx, sp.margin, sp.slack);
+    else c = ub;
     uint32_t tier, info;
-    int64_t use = 0, cost;
+    int64_t cost = mincost;
     if (m == 0 || ub == 0 || c == 0) {
       tier = kTierEmpty;
       c = 0;
       info = pack_info(kTierEmpty, false, 0);
-      cost = mincost;
-    } else if (m <= sp.merge_lists && c <= sp.merge_max && (sp.mode == kSymbolic || c <= H)) {
-      // register merge; the passes that write values stage the row in LDS
+    } else if (m <= sp.merge_lists && c <= sp.merge_max) {
       tier = kTierMerge;
       info = pack_info(kTierMerge, false, 0);
-      use = (sp.mode == kSymbolic) ? 0 : c;
-      cost = max(use, mincost);
+      if (!sym) cost = max(min(c, HT), mincost);
     } else {
-      int64_t span = (int64_t)pa.f.hi[i] - (int64_t)pa.f.lo[i] + 1;
-      bool dense;
-      int64_t slots, alloc;
-      table_shape(span, c, sp.dense_ratio, sp.pad, &dense, &slots, &alloc);
-      if (alloc <= H) {
+      const int64_t span = (int64_t)pa.f.hi[i] - (int64_t)pa.f.lo[i] + 1;
+      bool dense = false;
+      int64_t T;
+      if ((double)span <= (double)sp.dense_ratio * (double)c && span <= sp.table_max) {
+        dense = true;
+        T = span;
+      } else {
+        const int64_t need = sym ? 2 * ub : (sp.mode == kNumeric ? 2 * c : max(ub + 1, 2 * c));
+        T = table_pow2(need);
+        // one pass: a table just above the bound still never fills (the
+        // load is high only where the capacity is close to the bound)
+        if (sp.mode == kOnePass && T > sp.table_max) T = table_pow2(ub + 1);
+      }
+      // a hashed (not dense) row's keys are sorted in the wave's registers:
+      // at most kSortMax of them
+      const int64_t most = sym ? 0 : (sp.mode == kNumeric ? c : ub);
+      if (sp.table_max > 0 && T <= sp.table_max && (dense || most <= kSortMax)) {
         tier = kTierHash;
-        info = pack_info(kTierHash, dense, (uint32_t)slots);
-        use = alloc;
-        cost = max(use, mincost);
+        info = pack_info(kTierHash, dense, (uint32_t)T);
+        tmax = T;
+        // the numeric pass writes hashed rows straight to C (not staged)
+        if (sp.mode == kOnePass) cost = max(min(c, HT), mincost);
+        // the numeric pass has a smaller (values) table: a row it may send
+        // to the workgroup tier gets its device table counted already
+        if (sym && (table_pow2(2 * ub) > sp.value_table_max || ub > kSortMax) &&
+            !((double)span <= (double)sp.dense_ratio * (double)mx && span <= sp.value_table_max))
+          scratch = global_table_bound(ub);
       } else {
         tier = kTierGlobal;
         info = pack_info(kTierGlobal, false, 0);
-        cost = HT;
-      }
-      // device table for a workgroup-level pass over this row (a global row,
-      // or a hashed row whose probes ran past its LDS slice)
-      if (tier == kTierGlobal || !dense) {
-        int64_t cg = (sp.mode == kNumeric) ? c : ub;
-        bool dg;
-        int64_t sg;
-        scratch = global_table_alloc(span, cg, &dg, &sg);
+        big = true;
+        scratch = global_table_bound(sp.mode == kNumeric ? c : ub);
       }
     }
     pa.info[i] = info;
     pa.cap[i] = (int32_t)c;
     pa.cost[i] = cost;
-    pool_rows = use > 0 ? 1 : 0;
     n_tier[tier] = 1;
     capsum = c;
   }
-  int w = threadIdx.x / kWave;
-  int64_t v[7] = {n_tier[1], n_tier[2], n_tier[3], n_tier[0], capsum, pool_rows, scratch};
+  // workgroup-tier rows: appended to the list, one atomic per wave
+  const uint64_t bm = ballot(big);
+  if (bm) {
+    int64_t base = 0;
+    if (lane_id() == 0)
+      base = (int64_t)atomicAdd((unsigned long long *)&pa.counters[kCtrGlobal], (unsigned long long)__popcll(bm));
+    base = __shfl(base, 0, kWave);
+    if (big) pa.big[base + __popcll(bm & lanemask_lt())] = (int32_t)i;
+  }
+  const int w = threadIdx.x / kWave;
+  int64_t v[7] = {n_tier[kTierMerge], n_tier[kTierHash], n_tier[kTierEmpty], capsum, scratch > 0 ? 1 : 0,
+                  scratch, tmax};
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    int64_t t = wave_sum(v[j]);
+  for (int j = 0; j < 5; ++j) {
+    const int64_t t = wave_sum(v[j]);
     if (lane_id() == 0) s_red[j][w] = t;
   }
-  {
-    int64_t t = v[6];
+#pragma unroll
+  for (int j = 5; j < 7; ++j) {
+    int64_t t = v[j];
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) t = max(t, __shfl_xor(t, d, kWave));
-    if (lane_id() == 0) s_red[6][w] = t;
+    if (lane_id() == 0) s_red[j][w] = t;
   }
   __syncthreads();
   // one partial per workgroup; k_sum_partials adds them (no hot atomics)
   if (threadIdx.x < 7) {
-    int j = threadIdx.x;
+    const int j = threadIdx.x;
     int64_t t = 0;
-    for (int q = 0; q < kWavesPerBlock; ++q) t = (j == 6) ? max(t, s_red[j][q]) : t + s_red[j][q];
+    for (int q = 0; q < kWavesPerBlock; ++q) t = (j >= 5) ? max(t, s_red[j][q]) : t + s_red[j][q];
     pa.partials[(int64_t)blockIdx.x * 8 + j] = t;
   }
 }
@@ -398,13 +428,15 @@ hipError_t launch_size_rows(const Operands &op, const PlanArrays &pa, const Size
   PartialSpec ps{};
   ps.n = 7;
   ps.stride = 8;
-  const int32_t dst[7] = {kCtrMerge, kCtrHash, kCtrGlobal, kCtrEmpty, kCtrCapSum, kCtrPoolRows, kCtrScratch};
+  const int32_t dst[7] = {kCtrMerge, kCtrHash, kCtrEmpty, kCtrCapSum, kCtrScratchRows, kCtrScratch, kCtrTable};
   for (int j = 0; j < 7; ++j) {
     ps.dst[j] = dst[j];
-    ps.is_max[j] = (j == 6);
+    ps.is_max[j] = (j >= 5);
   }
+  hipError_t e = launch_fill_i64(pa.counters + kCtrGlobal, 0, 1, s);
+  if (e != hipSuccess) return e;
   if (op.rows <= 0) {
-    hipError_t e = launch_fill_i64(pa.partials, 0, 8, s);
+    e = launch_fill_i64(pa.partials, 0, 8, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, (const int64_t *)pa.partials, (int64_t)1, ps,
                        pa.counters);
@@ -416,6 +448,7 @@ hipError_t launch_size_rows(const Operands &op, const PlanArrays &pa, const Size
                      pa.counters);
   return hipGetLastError();
 }
+
 
 // ------------------------------------------------------------------- scan
 // Single-pass exclusive scan with decoupled look-back: each workgroup takes
@@ -524,7 +557,7 @@ hipError_t launch_tile_bounds(const int64_t *cost, int64_t rows, int64_t HT, int
   return hipGetLastError();
 }
 
-// ============================================================ tile kernel
+// ============================================================ row kernels
 // Monotone hash: home slot of column j in a row whose columns lie in
 // [lo, lo + span).  Dense window: slot = j - lo.  Hashed: slot =
 // floor((j - lo) * scale / 2^32) with scale = floor(T * 2^32 / span), which
@@ -622,139 +655,6 @@ __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, 
 // the whole table sorted in slot order, so a key's rank is the number of
 // occupied slots before it.  Tables where no key was displaced are sorted
 // already.
-template <int G, bool VALUES>
-__device__ void lds_sort_runs(int32_t *keys, double *vals, int32_t alloc) {
-  const int gl = lane_id() & (G - 1);
-  for (int32_t s = gl; s < alloc; s += G) {
-    if (keys[s] == kEmpty || (s > 0 && keys[s - 1] != kEmpty)) continue;
-    for (int32_t q = s + 1; q < alloc; ++q) {
-      const int32_t k = keys[q];
-      if (k == kEmpty) break;
-      const double v = VALUES ? vals[q] : 0.0;
-      int32_t at = q;
-      while (at > s && keys[at - 1] > k) {
-        keys[at] = keys[at - 1];
-        if (VALUES) vals[at] = vals[at - 1];
-        --at;
-      }
-      keys[at] = k;
-      if (VALUES) vals[at] = v;
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
-
-// Insert column j with the product a*b into an LDS table (G-lane tier).
-template <bool VALUES>
-__device__ __forceinline__ void lds_insert(int32_t *keys, double *vals, int32_t alloc, const RowHash &hs,
-                                           int32_t j, double a, double b, int32_t &cnt, int32_t &dmax,
-                                           bool &ovf) {
-  const int32_t h = hs.home(j);
-  int32_t s = h;
-  while (true) {
-    if (s >= alloc) {
-      ovf = true;
-      break;
-    }
-    int32_t old = atomicCAS(&keys[s], kEmpty, j);
-    if (old == kEmpty) {
-      ++cnt;
-      if (VALUES) vals[s] = first_add_rn(a, b);
-      break;
-    }
-    if (old == j) {
-      if (VALUES) vals[s] = mul_add_rn(vals[s], a, b);
-      break;
-    }
-    ++s;
-  }
-  dmax = max(dmax, s - h);
-}
-
-// --- LDS hash tier: G lanes per row.  A entries are taken in stored order;
-// for each, the G lanes cover the B row.  Columns of one B row are distinct,
-// so within a step no two lanes touch the same slot, and steps run in
-// program order inside the wave: every slot is updated in A's column order
-// with plain loads and stores (no floating-point atomics).  The first G
-// entries of the next kPrefetch B rows are loaded before any of them is
-// inserted, so a row waits for one gather round trip per kPrefetch entries
-// of A instead of one per entry.
-constexpr int kPrefetch = 8;
-
-template <int G, bool VALUES>
-__device__ void hash_row(const Operands &op, int64_t row, int32_t *keys, double *vals, int32_t alloc,
-                         const RowHash &hs, int32_t *cnt_out, int32_t *dmax_out, int32_t *ovf_out) {
-  const int gl = lane_id() & (G - 1);
-  const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
-  int32_t cnt = 0, dmax = 0;
-  bool ovf = false;
-  for (int64_t eb = as; eb < ae; eb += G) {
-    const int64_t e = eb + gl;
-    int64_t bs = 0;
-    int32_t bl = 0;
-    double av = 0.0;
-    if (e < ae) {
-      int32_t k = op.a_col[e];
-      if (VALUES) av = op.a_val[e];
-      bs = op.b_rp[k];
-      bl = (int32_t)(op.b_rp[k + 1] - bs);
-    }
-    const int ne = (int)min((int64_t)G, ae - eb);
-    for (int i0 = 0; i0 < ne; i0 += kPrefetch) {
-      int32_t jj[kPrefetch];
-      double bb[kPrefetch];
-#pragma unroll
-      for (int u = 0; u < kPrefetch; ++u) {
-        const int i = i0 + u;
-        const int64_t bsi = __shfl(bs, i & (G - 1), G);
-        const int32_t bli = __shfl(bl, i & (G - 1), G);
-        const bool live = i < ne && gl < bli;
-        jj[u] = live ? op.b_col[bsi + gl] : kEmpty;
-        bb[u] = (VALUES && live) ? op.b_val[bsi + gl] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < kPrefetch; ++u) {
-        const int i = i0 + u;
-        if (i >= ne) break;
-        const double avi = VALUES ? __shfl(av, i & (G - 1), G) : 0.0;
-        if (jj[u] != kEmpty)
-          lds_insert<VALUES>(keys, vals, alloc, hs, jj[u], avi, bb[u], cnt, dmax, ovf);
-        // B rows longer than G: the rest of this row, still before entry i + 1
-        const int32_t bli = __shfl(bl, i & (G - 1), G);
-        if (bli > G) {
-          const int64_t bsi = __shfl(bs, i & (G - 1), G);
-          for (int32_t f = G + gl; f < bli; f += G) {
-            const int32_t j = op.b_col[bsi + f];
-            const double b = VALUES ? op.b_val[bsi + f] : 0.0;
-            lds_insert<VALUES>(keys, vals, alloc, hs, j, avi, b, cnt, dmax, ovf);
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      }
-    }
-  }
-  // every lane takes part in every shuffle (no short-circuit around them)
-  int32_t of = ovf ? 1 : 0;
-#pragma unroll
-  for (int d = G / 2; d > 0; d >>= 1) {
-    cnt += __shfl_xor(cnt, d, G);
-    dmax = max(dmax, __shfl_xor(dmax, d, G));
-    of |= __shfl_xor(of, d, G);
-  }
-  if (gl == 0) {
-    *cnt_out = cnt;
-    *dmax_out = dmax;
-    *ovf_out = of;
-  }
-  if (VALUES && dmax > 0 && !of) lds_sort_runs<G, VALUES>(keys, vals, alloc);
-}
-
-// The per-workgroup tables live in device memory and are written by
-// several waves: initial stores, atomic claims (performed in L2) and value
-// updates.  Reads go around the L1 cache (agent-scope atomic loads), and
-// phases are separated by agent-scope fences on both sides of the barrier,
-// so a late initial store can never land on a claimed slot and no wave
-// reads a stale L1 line.
 __device__ __forceinline__ int32_t gload(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -771,30 +671,6 @@ __device__ __forceinline__ void wg_sync_global() {
 }
 
 // Write the sorted row held by an LDS table (G lanes).
-template <int G, bool VALUES>
-__device__ void hash_extract(const int32_t *keys, const double *vals, int32_t alloc, int32_t *out_col,
-                             double *out_val, int64_t lim) {
-  const int gl = lane_id() & (G - 1);
-  const uint64_t gm = group_mask<G>();
-  const uint64_t lt = lanemask_lt();
-  int64_t run = 0;
-  for (int32_t c = 0; c < alloc; c += G) {
-    const int32_t s = c + gl;
-    const int32_t key = s < alloc ? keys[s] : kEmpty;
-    const bool occ = key != kEmpty;
-    const uint64_t bal = ballot(occ) & gm;
-    if (occ) {
-      const int64_t rank = run + __popcll(bal & lt);
-      if (rank < lim) {
-        out_col[rank] = key;
-        if (VALUES) out_val[rank] = vals[s];
-      }
-    }
-    run += __popcll(bal);
-  }
-}
-
-// --- workgroup-level rows in a per-workgroup device table.
 struct WgScratch {
   int64_t pref[kBlock + 1];
   int64_t bs[kBlock];
@@ -891,12 +767,23 @@ __device__ int32_t wg_global_keys(const Operands &op, int64_t row, int32_t *keys
   return ws.cnt;
 }
 
-// Values of the row into the table built by wg_global_keys.  Ordered: one
-// wave takes the A entries in stored order, lanes over the B row (distinct
-// columns, so distinct slots), and every entry's updates complete before
-// the next entry's begin.  Fast: every product at once with atomic adds.
-__device__ void wg_global_values(const Operands &op, int64_t row, const int32_t *keys, double *vals,
-                                 int64_t alloc, const RowHash &hs, WgScratch &ws, bool fast) {
+// Waits until this wave's outstanding memory operations have completed (no
+// cache write-back or invalidation): the device-table updates of one
+// sub-step are in L2 before the next sub-step reads them.
+__device__ __forceinline__ void wave_mem_wait() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Values of the row into the table built by wg_global_keys.  Ordered: the
+// first wave takes 64 / W entries of A per step (W lanes over each B row,
+// W the next power of two >= the longest selected B row, 16..64), loads a
+// few steps ahead, and the entries of one step update their slots in A's
+// stored order (one sub-step each), so every slot is accumulated in A's
+// column order.  Fast: every product at once with atomic adds.
+__device__ void wg_global_values(const Operands &op, int64_t row, int32_t maxb, const int32_t *keys,
+                                 double *vals, int64_t alloc, const RowHash &hs, WgScratch &ws, bool fast) {
   if (fast) {
     wg_for_products(op, row, ws, [&](int64_t bpos, double av) {
       int32_t j = op.b_col[bpos];
@@ -909,17 +796,52 @@ __device__ void wg_global_values(const Operands &op, int64_t row, const int32_t 
       if (s >= 0) atomicAdd(&vals[s], p);
     });
   } else if (threadIdx.x < kWave) {
+    constexpr int PF = 4;
+    const int lane = threadIdx.x;
     const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
-    for (int64_t e = as; e < ae; ++e) {
-      int32_t k = op.a_col[e];
-      double av = op.a_val[e];
-      int64_t bs = op.b_rp[k], be = op.b_rp[k + 1];
-      for (int64_t f = bs + threadIdx.x; f < be; f += kWave) {
-        int32_t j = op.b_col[f];
-        int64_t s = global_find(keys, alloc, hs, j);
-        if (s >= 0) gstored(vals + s, mul_add_rn(gloadd(vals + s), av, op.b_val[f]));
+    int lw = 4;
+    while ((1 << lw) < maxb && lw < 6) ++lw;
+    const int W = 1 << lw, per = kWave >> lw, sub = lane >> lw, bp = lane & (W - 1);
+    for (int64_t e0 = as; e0 < ae; e0 += (int64_t)per * PF) {
+      int64_t bs[PF];
+      int32_t bl[PF], jj[PF];
+      double av[PF], bb[PF];
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int64_t e = e0 + (int64_t)u * per + sub;
+        bs[u] = 0;
+        bl[u] = 0;
+        av[u] = 0.0;
+        if (e < ae) {
+          const int32_t k = op.a_col[e];
+          av[u] = op.a_val[e];
+          bs[u] = op.b_rp[k];
+          bl[u] = (int32_t)(op.b_rp[k + 1] - bs[u]);
+        }
       }
-      __threadfence();
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const bool live = bp < bl[u];
+        jj[u] = live ? op.b_col[bs[u] + bp] : kEmpty;
+        bb[u] = live ? op.b_val[bs[u] + bp] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        if (e0 + (int64_t)u * per >= ae) continue;   // uniform
+        const int64_t s = jj[u] != kEmpty ? global_find(keys, alloc, hs, jj[u]) : -1;
+        for (int q = 0; q < per; ++q) {
+          if (sub == q && s >= 0) gstored(vals + s, mul_add_rn(gloadd(vals + s), av[u], bb[u]));
+          wave_mem_wait();
+        }
+        if (W == kWave && bl[u] > kWave) {
+          for (int32_t f = kWave + lane; f < bl[u]; f += kWave) {
+            const int32_t j = op.b_col[bs[u] + f];
+            const int64_t sl = global_find(keys, alloc, hs, j);
+            if (sl >= 0) gstored(vals + sl, mul_add_rn(gloadd(vals + sl), av[u], op.b_val[bs[u] + f]));
+          }
+          wave_mem_wait();
+        }
+      }
     }
   }
   wg_sync_global();
@@ -975,305 +897,511 @@ __device__ void wg_global_extract(int32_t *keys, double *vals, int64_t alloc, in
   __syncthreads();
 }
 
-struct TileShared {
-  int32_t off[kMaxTileRows];      // LDS pool offset of a row (hash table or merge staging)
-  int32_t cnt[kMaxTileRows];
-  int32_t dmax[kMaxTileRows];
-  int32_t flag[kMaxTileRows];     // 1: the row did not fit its LDS slice
-  int64_t out[kMaxTileRows];      // where the row starts in C
-  int16_t list[3][kMaxTileRows];  // merge, hash, workgroup-level rows, each in row order
-  int32_t nlist[3];
-  int64_t tile, tile_excl, tile_total, used;
-  int64_t wtot[kWavesPerBlock + 1];
-  WgScratch ws;
+// ============================================================ wave tiles
+// A wave tile is a run of at most 64 consecutive rows handled by one wave
+// (one 64-lane workgroup).  Merge rows take one lane each; hashed rows take
+// the whole wave one after another, accumulating in the wave's LDS table;
+// workgroup-tier rows are left to k_big.  Numeric and one-pass tiles stage
+// their sorted rows in LDS and copy them to C with contiguous, coalesced
+// stores once the tile's offset in C is known.
+
+// Home slot of column j.  Dense window: j - lo (the MinMax storing of
+// Section IV-B, sorted by construction).  Otherwise a multiplicative
+// (Fibonacci) hash into a power-of-two table with linear probing; the keys
+// come out unsorted and the extraction sorts them (the Sort storing).
+struct WaveTable {
+  int32_t *keys;
+  double *vals;
+  int32_t T;       // slots (power of two unless dense)
+  int32_t lo;
+  uint32_t shift;  // 32 - log2(T)
+  bool dense;
+  __device__ __forceinline__ int32_t home(int32_t j) const {
+    return dense ? j - lo : (int32_t)(((uint32_t)j * 0x9E3779B1u) >> shift);
+  }
 };
 
-size_t tile_static_lds(int mode) { return sizeof(TileShared); }
+__device__ __forceinline__ WaveTable wave_table(int32_t *keys, double *vals, uint32_t inf, int32_t lo) {
+  WaveTable t;
+  t.keys = keys;
+  t.vals = vals;
+  t.T = (int32_t)info_slots(inf);
+  t.dense = info_dense(inf);
+  t.lo = lo;
+  t.shift = t.dense ? 0u : (uint32_t)(32 - __builtin_ctz((unsigned)t.T));
+  return t;
+}
 
-// Tile kernel.  A tile is a run of consecutive rows; its rows are tiered
-// (merge / LDS hash / workgroup-level) and processed in phases:
-//   A  merge rows, one thread each, into LDS staging (or counted only)
-//   B  hashed rows, G lanes each, into their LDS tables
-//   C  workgroup-level rows and hashed rows that ran out of LDS room,
-//      one at a time by the whole workgroup in a device table
-//   D  output offsets: from row_ptr (numeric pass) or a workgroup scan plus
-//      a decoupled look-back over tiles (one pass)
-//   E  write-out: staged merge rows copied by 16-lane groups (contiguous,
-//      coalesced), hashed rows extracted in column order by their groups.
-// HASH = false compiles phases B/C out for tiles that only hold merge and
-// empty rows (fewer registers, more waves per CU).
-template <int G, int M, int MODE, bool HASH>
-__global__ void __launch_bounds__(kBlock) k_tile(TileParams p) {
+// Orders the LDS accesses of the lanes of one wave (the workgroup is one
+// wave, and a wave's LDS instructions execute in issue order): a fence at
+// wavefront scope keeps the compiler from moving memory operations across,
+// without waiting for outstanding global loads.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Claim or find column j; returns its slot.  A table sized by the rules of
+// k_size_rows never fills, so the probe always ends; a probe that would run
+// past T (an inconsistent call) raises kErrInconsistent and drops the key.
+template <bool VALUES>
+__device__ __forceinline__ int32_t wave_probe(const WaveTable &tb, int32_t j, int32_t &cnt, int64_t *err) {
+  int32_t h = tb.home(j);
+  for (int32_t it = 0;; ++it) {
+    const int32_t old = atomicCAS(&tb.keys[h], kEmpty, j);
+    if (old == kEmpty) {
+      ++cnt;
+      if (VALUES) tb.vals[h] = 0.0;
+      return h;
+    }
+    if (old == j) return h;
+    if (tb.dense || it >= tb.T) {
+      atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
+      return -1;
+    }
+    h = (h + 1) & (tb.T - 1);
+  }
+}
+
+// Lanes per A entry: the next power of two >= the longest selected B row,
+// at least kMinLanes (so at most 64 / kMinLanes ordered sub-steps) and at
+// most 64 (longer B rows loop).
+constexpr int kMinLanes = 16;
+constexpr int kWavePrefetch = 4;
+
+// Inserts every product of the row into the wave's table, the whole wave
+// taking 64 / W entries of A per step and W lanes over each B row.  Values:
+// a slot starts at +0.0 when claimed, and the entries of one step add their
+// products in A's stored order (one sub-step per entry), so every slot is
+// accumulated exactly in A's column order, as in the row-major kernel of
+// Section IV-A.  Returns the number of distinct columns (wave-uniform).
+template <bool VALUES>
+__device__ int32_t wave_insert_row(const Operands &op, int64_t row, int32_t maxb, const WaveTable &tb,
+                                   int64_t *err) {
+  const int lane = threadIdx.x;
+  const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
+  int lw = __builtin_ctz((unsigned)kMinLanes);
+  while ((1 << lw) < maxb && lw < 6) ++lw;
+  const int W = 1 << lw;
+  const int per = kWave >> lw;
+  const int sub = lane >> lw;
+  const int bp = lane & (W - 1);
+  int32_t cnt = 0;
+  for (int64_t e0 = as; e0 < ae; e0 += (int64_t)per * kWavePrefetch) {
+    int64_t bs[kWavePrefetch];
+    int32_t bl[kWavePrefetch], jj[kWavePrefetch];
+    double av[kWavePrefetch], bb[kWavePrefetch];
+#pragma unroll
+    for (int u = 0; u < kWavePrefetch; ++u) {
+      const int64_t e = e0 + (int64_t)u * per + sub;
+      bs[u] = 0;
+      bl[u] = 0;
+      av[u] = 0.0;
+      if (e < ae) {
+        const int32_t k = op.a_col[e];
+        if (VALUES) av[u] = op.a_val[e];
+        bs[u] = op.b_rp[k];
+        bl[u] = (int32_t)(op.b_rp[k + 1] - bs[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kWavePrefetch; ++u) {
+      const bool live = bp < bl[u];
+      jj[u] = live ? op.b_col[bs[u] + bp] : kEmpty;
+      bb[u] = (VALUES && live) ? op.b_val[bs[u] + bp] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kWavePrefetch; ++u) {
+      if (e0 + (int64_t)u * per >= ae) continue;   // uniform: no entries left
+      int32_t s = -1;
+      if (jj[u] != kEmpty) s = wave_probe<VALUES>(tb, jj[u], cnt, err);
+      if (VALUES) {
+        for (int q = 0; q < per; ++q) {
+          wave_sync();
+          if (sub == q && s >= 0) tb.vals[s] = mul_add_rn(tb.vals[s], av[u], bb[u]);
+        }
+      }
+      if (W == kWave && bl[u] > kWave) {
+        // one A entry per step here: the rest of its B row, 64 columns at a time
+        for (int32_t f = kWave + lane; f < bl[u]; f += kWave) {
+          const int32_t j = op.b_col[bs[u] + f];
+          const int32_t sl = wave_probe<VALUES>(tb, j, cnt, err);
+          if (VALUES && sl >= 0) tb.vals[sl] = mul_add_rn(tb.vals[sl], av[u], op.b_val[bs[u] + f]);
+        }
+      }
+      wave_sync();
+    }
+  }
+  return (int32_t)wave_sum(cnt);
+}
+
+__device__ __forceinline__ void wave_clear(const WaveTable &tb) {
+  for (int32_t q = threadIdx.x; q < tb.T; q += kWave) tb.keys[q] = kEmpty;
+  wave_sync();
+}
+
+// Ascending bitonic sort of 64 * E keys held lane-major (element i = lane *
+// E + e): partners within a lane are exchanged in registers, partners in
+// other lanes through a lane shuffle.  One instantiation per (block size K,
+// partner distance J) stage, so every register index is a constant.
+template <int E, int K, int J>
+__device__ __forceinline__ void wave_bitonic_stage(int32_t (&x)[E]) {
+  const int lane = threadIdx.x;
+  if constexpr (J >= E) {
+    constexpr int lm = J / E;
+    const bool up = ((lane * E) & K) == 0;
+    const bool lower = (lane & lm) == 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int32_t y = __shfl_xor(x[e], lm, kWave);
+      x[e] = (lower == up) ? min(x[e], y) : max(x[e], y);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if ((e & J) == 0) {
+        const bool up = ((lane * E + e) & K) == 0;
+        const int32_t a = x[e], b = x[e ^ J];
+        const bool sw = up ? (a > b) : (a < b);
+        x[e] = sw ? b : a;
+        x[e ^ J] = sw ? a : b;
+      }
+    }
+  }
+  if constexpr (J > 1) wave_bitonic_stage<E, K, J / 2>(x);
+  else if constexpr (K < kWave * E) wave_bitonic_stage<E, 2 * K, K>(x);
+}
+
+template <int E>
+__device__ __forceinline__ void wave_bitonic(int32_t (&x)[E]) {
+  wave_bitonic_stage<E, 2, 1>(x);
+}
+
+// Sorted write-out of a hashed row whose n keys were compacted (in slot
+// order) to buf[0..n) in LDS: sort them there, then look every key up again
+// for its value and write (column, value) at positions 0..n-1 of ocol/oval
+// (at most lim), and empty the table.  ocol may be buf itself.
+template <int E>
+__device__ void wave_sort_out(const WaveTable &tb, int32_t n, int32_t *buf, int32_t *ocol, double *oval,
+                              int64_t lim) {
+  const int lane = threadIdx.x;
+  int32_t x[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int32_t pos = lane * E + e;
+    x[e] = pos < n ? buf[pos] : kColMax;
+  }
+  wave_sync();
+  wave_bitonic<E>(x);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int32_t pos = lane * E + e;
+    if (pos < n) buf[pos] = x[e];
+  }
+  wave_sync();
+  const int32_t m = (int32_t)min((int64_t)n, lim);
+  for (int32_t pos = lane; pos < m; pos += kWave) {
+    const int32_t key = buf[pos];
+    int32_t h = tb.home(key);
+    for (int32_t it = 0; it < tb.T && tb.keys[h] != key; ++it) h = (h + 1) & (tb.T - 1);
+    ocol[pos] = key;
+    oval[pos] = tb.vals[h];
+  }
+  wave_sync();
+  wave_clear(tb);
+}
+
+// Writes the row held by the table in column order to ocol/oval (at most
+// lim entries) and leaves the table empty.  buf: LDS room for n keys (may be
+// ocol itself when that is in LDS).
+__device__ void wave_extract(const WaveTable &tb, int32_t n, int32_t *buf, int32_t *ocol, double *oval,
+                             int64_t lim) {
+  const int lane = threadIdx.x;
+  const uint64_t lt = lanemask_lt();
+  int32_t run = 0;
+  if (tb.dense) {
+    // slot order is column order
+    for (int32_t c0 = 0; c0 < tb.T; c0 += kWave) {
+      const int32_t q = c0 + lane;
+      const int32_t key = q < tb.T ? tb.keys[q] : kEmpty;
+      const bool occ = key != kEmpty;
+      const uint64_t bal = ballot(occ);
+      if (occ) {
+        const int32_t rank = run + __popcll(bal & lt);
+        if (rank < lim) {
+          ocol[rank] = key;
+          oval[rank] = tb.vals[q];
+        }
+        tb.keys[q] = kEmpty;
+      }
+      run += __popcll(bal);
+    }
+    wave_sync();
+    return;
+  }
+  for (int32_t c0 = 0; c0 < tb.T; c0 += kWave) {
+    const int32_t q = c0 + lane;
+    const int32_t key = q < tb.T ? tb.keys[q] : kEmpty;
+    const bool occ = key != kEmpty;
+    const uint64_t bal = ballot(occ);
+    if (occ) buf[run + __popcll(bal & lt)] = key;
+    run += __popcll(bal);
+  }
+  wave_sync();
+  // n <= kSortMax (k_size_rows sends larger hashed rows to the workgroup tier)
+  if (n <= 64) wave_sort_out<1>(tb, n, buf, ocol, oval, lim);
+  else if (n <= 128) wave_sort_out<2>(tb, n, buf, ocol, oval, lim);
+  else if (n <= 256) wave_sort_out<4>(tb, n, buf, ocol, oval, lim);
+  else if (n <= 512) wave_sort_out<8>(tb, n, buf, ocol, oval, lim);
+  else wave_sort_out<16>(tb, n, buf, ocol, oval, lim);
+}
+
+// Tile kernel.  MODE kSymbolic: per-row counts (merge rows and hashed rows;
+// workgroup-tier rows are counted by k_big).  kNumeric: row_ptr known, rows
+// staged and copied.  kOnePass: counts found on chip, the tile's offset by a
+// decoupled look-back over tiles, rows staged and copied; rows whose output
+// does not fit the staging left (learned capacity too small) are computed
+// again after the offset is known and written straight to C.
+// One-pass tiles are taken in the order t = blockIdx.x + k * gridDim.x by a
+// grid that is resident as a whole, so every tile waits only on tiles that
+// are running or done.
+constexpr int64_t kResidentPolls = 1ll << 14;
+constexpr int32_t kNotStaged = -1;   // row not (yet) in the stage
+constexpr int32_t kWritten = -2;     // row written to C directly
+
+// LDS of a wave tile: table keys, table values, the compaction buffer of a
+// hashed row (kSortMax keys at most), stage columns, stage values.
+struct WaveLds {
+  size_t vals, buf, scol, sval, total;
+};
+__host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots, int stage_slots) {
+  auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
+  WaveLds L;
+  L.vals = a16((size_t)table_slots * 4);
+  if (!values) {
+    L.buf = L.scol = L.sval = L.total = L.vals;
+    return L;
+  }
+  const size_t nbuf = (size_t)(table_slots < kSortMax ? table_slots : kSortMax);
+  L.buf = L.vals + (size_t)table_slots * 8;
+  L.scol = a16(L.buf + nbuf * 4);
+  L.sval = a16(L.scol + (size_t)stage_slots * 4);
+  L.total = L.sval + (size_t)stage_slots * 8;
+  return L;
+}
+
+template <int MODE, int M>
+__global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
   constexpr bool VALUES = (MODE != kSymbolic);
-  constexpr int CG = 16;   // lanes per staged row in the copy-out
-  extern __shared__ __align__(16) unsigned char pool_raw[];
-  __shared__ TileShared sh;
-  int32_t *pkeys = reinterpret_cast<int32_t *>(pool_raw);
-  double *pvals = reinterpret_cast<double *>(pool_raw + (((size_t)p.pool_slots * 4 + 15) & ~(size_t)15));
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int lane = threadIdx.x;
   const Operands &op = p.op;
-  const int64_t ntiles = p.counters[kCtrTiles];
+  int64_t *err = p.counters + kCtrError;
+  const WaveLds L = wave_lds_layout(VALUES, p.table_slots, p.stage_slots);
+  int32_t *tkeys = reinterpret_cast<int32_t *>(lds);
+  double *tvals = reinterpret_cast<double *>(lds + L.vals);
+  int32_t *buf = reinterpret_cast<int32_t *>(lds + L.buf);
+  int32_t *scol = reinterpret_cast<int32_t *>(lds + L.scol);
+  double *sval = reinterpret_cast<double *>(lds + L.sval);
+  for (int32_t q = lane; q < p.table_slots; q += kWave) tkeys[q] = kEmpty;
+  wave_sync();
+  if (MODE == kOnePass) {
+    // tiles wait on lower tiles of other workgroups, so the whole grid must
+    // be resident: count the workgroups in and wait (boundedly) for all of
+    // them; if they do not all arrive, raise kErrResidency and stop (the
+    // host runs the pass again with a smaller grid)
+    int64_t e = 0;
+    if (lane == 0) {
+      unsigned long long *ctr_res = (unsigned long long *)&p.counters[kCtrResident];
+      __hip_atomic_fetch_add(ctr_res, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int64_t polls = 0;; ++polls) {
+        if (__hip_atomic_load(ctr_res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (unsigned long long)gridDim.x)
+          break;
+        if (polls > kResidentPolls) {
+          // workgroups resident together (none has left before this point)
+          atomicMax((unsigned long long *)&p.counters[kCtrResidentSeen],
+                    __hip_atomic_load(ctr_res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          atomicOr((unsigned long long *)err, (unsigned long long)kErrResidency);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    e = __shfl(e, 0, kWave);
+    if (e & kErrResidency) return;
+  }
+
+  for (int64_t t = blockIdx.x; t < p.ntiles; t += gridDim.x) {
+    const int64_t r0 = p.tile_row ? (int64_t)p.tile_row[t] : t * kWave;
+    const int64_t r1 = p.tile_row ? (int64_t)p.tile_row[t + 1] : min(r0 + kWave, op.rows);
+    const int nr = (int)(r1 - r0);
+    const bool valid = lane < nr;
+    const int64_t row = r0 + lane;
+    const uint32_t inf = valid ? p.info[row] : 0u;
+    const uint32_t tier = valid ? info_tier(inf) : (uint32_t)kTierEmpty;
+    const int32_t capr = valid ? p.cap[row] : 0;
+    int64_t n = 0;
+    int32_t soff = kNotStaged;   // or the row's stage offset, or kWritten
+
+    // merge rows, one lane each, staged at their reserved capacity
+    int32_t sp = 0;
+    if (VALUES) {
+      const int32_t res = tier == kTierMerge ? capr : 0;
+      const int32_t inc = wave_inclusive_sum32(res);
+      sp = __shfl(inc, kWave - 1, kWave);
+      if (tier == kTierMerge) {
+        const int32_t o = inc - res;
+        n = merge_row<M, true>(op, row, scol + o, sval + o, capr);
+        if (n <= capr) soff = o;
+      }
+    } else if (tier == kTierMerge) {
+      n = merge_row<M, false>(op, row, nullptr, nullptr, 0);
+    }
+    wave_sync();
+
+    // hashed rows, the whole wave on one row at a time
+    uint64_t hm = ballot(tier == kTierHash);
+    while (hm) {
+      const int r = __ffsll((unsigned long long)hm) - 1;
+      hm &= hm - 1;
+      const int64_t hrow = r0 + r;
+      const WaveTable tb = wave_table(tkeys, tvals, p.info[hrow], p.lo[hrow]);
+      const int32_t c = wave_insert_row<VALUES>(op, hrow, p.maxb[hrow], tb, err);
+      if (!VALUES) {
+        wave_clear(tb);
+      } else if (MODE == kNumeric) {
+        // the row's place in C is known: sorted entries go straight there
+        const int64_t o = p.c_rp[hrow];
+        const int64_t rl = max((int64_t)0, min((int64_t)c, p.c_capacity - o));
+        wave_extract(tb, c, buf, p.c_col + o, p.c_val + o, rl);
+        if (lane == r) soff = kWritten;
+      } else if (sp + c <= p.stage_slots) {
+        wave_extract(tb, c, buf, scol + sp, sval + sp, c);
+        if (lane == r) soff = sp;
+        sp += c;
+      } else {
+        wave_clear(tb);
+      }
+      if (lane == r) n = c;
+    }
+
+    if (MODE == kSymbolic) {
+      if (valid && tier != kTierGlobal) p.cnt_out[row] = (int32_t)n;
+      continue;
+    }
+    if (tier == kTierGlobal) n = (MODE == kNumeric) ? (int64_t)capr : (int64_t)p.big_cnt[row];
+    if (MODE == kNumeric && valid && tier != kTierGlobal && n != capr)
+      atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
+
+    // offsets of the tile's rows in C
+    const int64_t inc = wave_inclusive_sum(n);
+    const int64_t total = __shfl(inc, kWave - 1, kWave);
+    const int64_t ex = inc - n;
+    int64_t base;
+    if (MODE == kNumeric) {
+      base = p.c_rp[r0];
+    } else {
+      base = lookback_exclusive(p.status, t, total, err, kErrLookback, kErrResidency);
+      if (valid) p.c_rp[row] = base + ex;
+      if (t == p.ntiles - 1 && lane == 0) {
+        p.c_rp[op.rows] = base + total;
+        p.counters[kCtrNnz] = base + total;
+      }
+    }
+    if (lane == 0 && base + total > p.c_capacity)
+      atomicOr((unsigned long long *)err, (unsigned long long)kErrCapacity);
+
+    // copy-out of the staged rows: one contiguous copy when the stage is in
+    // C order (every row with entries sits at its C offset), else row by row
+    const bool in_order = ballot(valid && n > 0 && soff != ex) == 0ull;
+    if (in_order) {
+      const int64_t lim = max((int64_t)0, min(total, p.c_capacity - base));
+      for (int64_t q = lane; q < lim; q += kWave) {
+        p.c_col[base + q] = scol[q];
+        p.c_val[base + q] = sval[q];
+      }
+    } else {
+      uint64_t sm = ballot(valid && n > 0 && soff >= 0);
+      while (sm) {
+        const int r = __ffsll((unsigned long long)sm) - 1;
+        sm &= sm - 1;
+        const int32_t so = __shfl(soff, r, kWave);
+        const int64_t o = base + __shfl(ex, r, kWave);
+        const int64_t lim = max((int64_t)0, min(__shfl(n, r, kWave), p.c_capacity - o));
+        for (int64_t q = lane; q < lim; q += kWave) {
+          p.c_col[o + q] = scol[so + q];
+          p.c_val[o + q] = sval[so + q];
+        }
+      }
+    }
+    wave_sync();
+
+    // rows that were not staged (learned capacity too small): again, into C
+    const bool redo = valid && n > 0 && soff == kNotStaged && tier != kTierGlobal;
+    if (MODE == kOnePass) {
+      const uint64_t rb = ballot(redo);
+      if (lane == 0 && rb)
+        atomicAdd((unsigned long long *)&p.counters[kCtrOverflow], (unsigned long long)__popcll(rb));
+    }
+    if (redo && tier == kTierMerge) {
+      const int64_t o = base + ex;
+      const int64_t rl = max((int64_t)0, min(n, p.c_capacity - o));
+      merge_row<M, true>(op, row, p.c_col + o, p.c_val + o, rl);
+    }
+    uint64_t hr = ballot(redo && tier == kTierHash);
+    while (hr) {
+      const int r = __ffsll((unsigned long long)hr) - 1;
+      hr &= hr - 1;
+      const int64_t hrow = r0 + r;
+      const WaveTable tb = wave_table(tkeys, tvals, p.info[hrow], p.lo[hrow]);
+      const int32_t c = wave_insert_row<true>(op, hrow, p.maxb[hrow], tb, err);
+      const int64_t o = base + __shfl(ex, r, kWave);
+      const int64_t rl = max((int64_t)0, min((int64_t)c, p.c_capacity - o));
+      wave_extract(tb, c, buf, p.c_col + o, p.c_val + o, rl);
+    }
+    wave_sync();
+  }
+}
+
+// Workgroup-tier rows: one workgroup per listed row, the table in the
+// workgroup's slice of device scratch (sized by the plan).
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
+  __shared__ WgScratch ws;
+  const Operands &op = p.op;
+  const int64_t nbig = p.counters[kCtrGlobal];
   int32_t *gkeys = reinterpret_cast<int32_t *>(p.scratch + (size_t)blockIdx.x * (size_t)p.scratch_slots * 12);
   double *gvals = reinterpret_cast<double *>(p.scratch + (size_t)blockIdx.x * (size_t)p.scratch_slots * 12 +
                                              (size_t)p.scratch_slots * 4);
-  const int gid = threadIdx.x / G;
-  constexpr int NG = kBlock / G;
-
-  while (true) {
-    if (threadIdx.x == 0)
-      sh.tile = (int64_t)__hip_atomic_fetch_add((unsigned long long *)&p.counters[kCtrTicket], 1ull, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int64_t t = sh.tile;
-    if (t >= ntiles) break;
-    const int64_t r0 = p.tile_row[t], r1 = p.tile_row[t + 1];
-    const int nr = (int)(r1 - r0);
-
-    // ---- classify rows: ordered tier lists and LDS offsets, one packed scan
-    // (bits 0-9 merge rows, 10-19 hashed rows, 20-29 workgroup rows, 32-
-    // pool slots)
-    uint32_t tier2[2];
-    int64_t use[2];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int r = 2 * threadIdx.x + k;
-      tier2[k] = kTierEmpty;
-      use[k] = 0;
-      if (r < nr) {
-        const int64_t row = r0 + r;
-        const uint32_t inf = p.info[row];
-        tier2[k] = info_tier(inf);
-        sh.cnt[r] = 0;
-        sh.dmax[r] = 0;
-        sh.flag[r] = 0;
-        if (tier2[k] == kTierHash) use[k] = info_dense(inf) ? info_slots(inf) : info_slots(inf) + p.pad;
-        else if (tier2[k] == kTierMerge && VALUES) use[k] = p.cap[row];
-        if (MODE == kNumeric) sh.out[r] = p.c_rp[row];
-      }
-    }
-    auto pack = [&](int k) -> int64_t {
-      int64_t v = use[k] << 32;
-      if (tier2[k] != kTierEmpty) v += (int64_t)1 << (10 * (tier2[k] - 1));
-      return v;
-    };
-    int64_t tot;
-    const int64_t ex = block_exclusive_sum(pack(0) + pack(1), sh.wtot, &tot);
-    int64_t run = ex;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int r = 2 * threadIdx.x + k;
-      if (r < nr) {
-        sh.off[r] = (int32_t)(run >> 32);
-        if (tier2[k] != kTierEmpty) {
-          const int sh10 = 10 * (tier2[k] - 1);
-          sh.list[tier2[k] - 1][(run >> sh10) & 1023] = (int16_t)r;
-        }
-      }
-      run += pack(k);
-    }
-    if (threadIdx.x == 0) {
-      sh.nlist[0] = (int32_t)(tot & 1023);
-      sh.nlist[1] = (int32_t)((tot >> 10) & 1023);
-      sh.nlist[2] = (int32_t)((tot >> 20) & 1023);
-      sh.used = tot >> 32;
-    }
-    __syncthreads();
-    if (HASH && sh.nlist[1] > 0) {
-      // empty markers for the hashed rows' tables (merge staging needs none)
-      for (int i = gid; i < sh.nlist[1]; i += NG) {
-        const int r = sh.list[1][i];
-        const uint32_t inf = p.info[r0 + r];
-        const int32_t alloc = info_dense(inf) ? (int32_t)info_slots(inf) : (int32_t)info_slots(inf) + p.pad;
-        for (int32_t q = lane_id() & (G - 1); q < alloc; q += G) pkeys[sh.off[r] + q] = kEmpty;
-      }
-      __syncthreads();
-    }
-
-    // ---- phase A: register-merge rows, one thread each
-    for (int i = threadIdx.x; i < sh.nlist[0]; i += kBlock) {
-      const int r = sh.list[0][i];
-      const int64_t row = r0 + r;
-      if (VALUES) {
-        const int64_t capr = p.cap[row];
-        const int64_t n = merge_row<M, true>(op, row, pkeys + sh.off[r], pvals + sh.off[r], capr);
-        sh.cnt[r] = (int32_t)n;
-        if (n > capr) {
-          sh.flag[r] = 1;   // staging too small (one pass): recomputed at write-out
-          if (MODE == kOnePass) atomicAdd((unsigned long long *)&p.counters[kCtrOverflow], 1ull);
-        }
-        if (MODE == kNumeric && n != capr)
-          atomicOr((unsigned long long *)&p.counters[kCtrError], (unsigned long long)kErrInconsistent);
-      } else {
-        sh.cnt[r] = (int32_t)merge_row<M, false>(op, row, nullptr, nullptr, 0);
-      }
-    }
-
-    if constexpr (HASH) {
-      // ---- phase B: LDS hash rows, G lanes each
-      for (int i = gid; i < sh.nlist[1]; i += NG) {
-        const int r = sh.list[1][i];
-        const int64_t row = r0 + r;
-        const uint32_t inf = p.info[row];
-        const bool dense = info_dense(inf);
-        const int32_t slots = (int32_t)info_slots(inf);
-        const int32_t alloc = dense ? slots : slots + p.pad;
-        const RowHash hs = make_hash(p.lo[row], p.hi[row], slots, dense);
-        hash_row<G, VALUES>(op, row, pkeys + sh.off[r], pvals + sh.off[r], alloc, hs, &sh.cnt[r],
-                            &sh.dmax[r], &sh.flag[r]);
-      }
-      __syncthreads();
-
-      // hashed rows whose LDS probes ran out join the workgroup-level list
-      if (threadIdx.x == 0) {
-        for (int i = 0; i < sh.nlist[1]; ++i) {
-          const int r = sh.list[1][i];
-          if (sh.flag[r]) {
-            sh.list[2][sh.nlist[2]++] = (int16_t)r;
-            atomicAdd((unsigned long long *)&p.counters[kCtrOverflow], 1ull);
-          }
-        }
-      }
-      __syncthreads();
-
-      // ---- phase C: workgroup-level rows (count; the numeric pass writes them)
-      for (int i = 0; i < sh.nlist[2]; ++i) {
-        const int r = sh.list[2][i];
-        const int64_t row = r0 + r;
-        const int64_t c = (MODE == kNumeric) ? (p.c_rp[row + 1] - p.c_rp[row]) : (int64_t)p.ub[row];
-        const int64_t span = (int64_t)p.hi[row] - (int64_t)p.lo[row] + 1;
-        bool dense;
-        int64_t slots;
-        const int64_t alloc = global_table_alloc(span, c, &dense, &slots);
-        if (alloc > p.scratch_slots) {
-          if (threadIdx.x == 0)
-            atomicOr((unsigned long long *)&p.counters[kCtrError], (unsigned long long)kErrScratch);
-          continue;
-        }
-        const RowHash hs = make_hash(p.lo[row], p.hi[row], slots, dense);
-        const int32_t n = wg_global_keys(op, row, gkeys, alloc, hs, sh.ws, MODE == kNumeric ? gvals : nullptr,
-                                         p.counters + kCtrError);
-        if (threadIdx.x == 0) {
-          sh.cnt[r] = n;
-          sh.dmax[r] = sh.ws.dmax;
-        }
-        if (MODE == kNumeric) {
-          wg_global_values(op, row, gkeys, gvals, alloc, hs, sh.ws, p.fast != 0);
-          const int64_t o = sh.out[r];
-          const int64_t lim = max((int64_t)0, min((int64_t)n, p.c_capacity - o));
-          if (threadIdx.x == 0 && lim < n)
-            atomicOr((unsigned long long *)&p.counters[kCtrError], (unsigned long long)kErrCapacity);
-          wg_global_extract(gkeys, gvals, alloc, sh.ws.dmax, sh.ws, p.c_col + o, p.c_val + o, lim);
-        }
-        __syncthreads();
-      }
-    }
-    __syncthreads();
-
-    if (MODE == kSymbolic) {
-      for (int r = threadIdx.x; r < nr; r += kBlock) p.cnt_out[r0 + r] = sh.cnt[r];
-      __syncthreads();
+  int64_t *err = p.counters + kCtrError;
+  for (int64_t i = blockIdx.x; i < nbig; i += gridDim.x) {
+    const int64_t row = p.list[i];
+    const int64_t c = (MODE == kNumeric) ? (int64_t)p.cnt[row] : (int64_t)p.ub[row];
+    const int64_t span = (int64_t)p.hi[row] - (int64_t)p.lo[row] + 1;
+    bool dense;
+    int64_t slots;
+    const int64_t alloc = global_table_alloc(span, c, &dense, &slots);
+    if (alloc > p.scratch_slots) {
+      if (threadIdx.x == 0) atomicOr((unsigned long long *)err, (unsigned long long)kErrScratch);
       continue;
     }
-
-    // ---- phase D: output offsets of the one-pass kernel
-    if (MODE == kOnePass) {
-      int64_t c0 = 0, c1 = 0;
-      if (2 * threadIdx.x < nr) c0 = sh.cnt[2 * threadIdx.x];
-      if (2 * threadIdx.x + 1 < nr) c1 = sh.cnt[2 * threadIdx.x + 1];
-      int64_t agg;
-      int64_t lex = block_exclusive_sum(c0 + c1, sh.wtot, &agg);
-      if (threadIdx.x < kWave) {
-        int64_t pre = lookback_exclusive(p.status, t, agg, p.counters + kCtrError, kErrLookback);
-        if (threadIdx.x == 0) {
-          sh.tile_excl = pre;
-          sh.tile_total = pre + agg;
-        }
-      }
-      __syncthreads();
-      const int64_t base = sh.tile_excl;
-      if (2 * threadIdx.x < nr) {
-        sh.out[2 * threadIdx.x] = base + lex;
-        p.c_rp[r0 + 2 * threadIdx.x] = base + lex;
-      }
-      if (2 * threadIdx.x + 1 < nr) {
-        sh.out[2 * threadIdx.x + 1] = base + lex + c0;
-        p.c_rp[r0 + 2 * threadIdx.x + 1] = base + lex + c0;
-      }
-      if (t == ntiles - 1 && threadIdx.x == 0) {
-        p.c_rp[op.rows] = sh.tile_total;
-        p.counters[kCtrNnz] = sh.tile_total;
-        if (sh.tile_total > p.c_capacity)
-          atomicOr((unsigned long long *)&p.counters[kCtrError], (unsigned long long)kErrCapacity);
-      }
-      __syncthreads();
-    }
-
-    // ---- phase E: staged merge rows, copied contiguously by 16-lane groups
-    for (int i = threadIdx.x / CG; i < sh.nlist[0]; i += kBlock / CG) {
-      const int r = sh.list[0][i];
-      if (sh.flag[r]) continue;
-      const int64_t o = sh.out[r];
-      const int64_t n = sh.cnt[r];
-      const int64_t lim = max((int64_t)0, min(n, p.c_capacity - o));
-      if (MODE == kNumeric && lim < n && (threadIdx.x % CG) == 0)
-        atomicOr((unsigned long long *)&p.counters[kCtrError], (unsigned long long)kErrCapacity);
-      const int32_t so = sh.off[r];
-      for (int64_t q = threadIdx.x % CG; q < lim; q += CG) {
-        p.c_col[o + q] = pkeys[so + q];
-        p.c_val[o + q] = pvals[so + q];
-      }
-    }
-    if (MODE == kOnePass) {
-      // merge rows whose staging was too small: merge again, straight into C
-      for (int i = threadIdx.x; i < sh.nlist[0]; i += kBlock) {
-        const int r = sh.list[0][i];
-        if (!sh.flag[r]) continue;
-        const int64_t o = sh.out[r];
-        const int64_t lim = max((int64_t)0, min((int64_t)sh.cnt[r], p.c_capacity - o));
-        if (lim > 0) merge_row<M, true>(op, r0 + r, p.c_col + o, p.c_val + o, lim);
-      }
-    }
-
-    if constexpr (HASH) {
-      // ---- phase E: hashed rows
-      for (int i = gid; i < sh.nlist[1]; i += NG) {
-        const int r = sh.list[1][i];
-        if (sh.flag[r]) continue;
-        const int64_t row = r0 + r;
-        const uint32_t inf = p.info[row];
-        const bool dense = info_dense(inf);
-        const int32_t slots = (int32_t)info_slots(inf);
-        const int32_t alloc = dense ? slots : slots + p.pad;
-        const int64_t o = sh.out[r];
-        const int64_t lim = max((int64_t)0, min((int64_t)sh.cnt[r], p.c_capacity - o));
-        if (MODE == kNumeric && lim < sh.cnt[r] && lane_id() % G == 0)
-          atomicOr((unsigned long long *)&p.counters[kCtrError], (unsigned long long)kErrCapacity);
-        hash_extract<G, true>(pkeys + sh.off[r], pvals + sh.off[r], alloc, p.c_col + o, p.c_val + o, lim);
-      }
-
-      // ---- workgroup-level rows of the one-pass kernel: values and write-out
-      if (MODE == kOnePass) {
-        __syncthreads();
-        for (int i = 0; i < sh.nlist[2]; ++i) {
-          const int r = sh.list[2][i];
-          const int64_t row = r0 + r;
-          const int64_t c = (int64_t)p.ub[row];
-          const int64_t span = (int64_t)p.hi[row] - (int64_t)p.lo[row] + 1;
-          bool dense;
-          int64_t slots;
-          const int64_t alloc = global_table_alloc(span, c, &dense, &slots);
-          if (alloc > p.scratch_slots) continue;
-          const RowHash hs = make_hash(p.lo[row], p.hi[row], slots, dense);
-          wg_global_keys(op, row, gkeys, alloc, hs, sh.ws, gvals, p.counters + kCtrError);
-          wg_global_values(op, row, gkeys, gvals, alloc, hs, sh.ws, p.fast != 0);
-          const int64_t o = sh.out[r];
-          const int64_t lim = max((int64_t)0, min((int64_t)sh.cnt[r], p.c_capacity - o));
-          wg_global_extract(gkeys, gvals, alloc, sh.ws.dmax, sh.ws, p.c_col + o, p.c_val + o, lim);
-        }
-      }
+    const RowHash hs = make_hash(p.lo[row], p.hi[row], slots, dense);
+    const int32_t n = wg_global_keys(op, row, gkeys, alloc, hs, ws, MODE == kNumeric ? gvals : nullptr, err);
+    if (MODE == kSymbolic) {
+      if (threadIdx.x == 0) p.cnt[row] = n;
+    } else {
+      if (threadIdx.x == 0 && n != c) atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
+      wg_global_values(op, row, p.maxb[row], gkeys, gvals, alloc, hs, ws, p.fast != 0);
+      const int64_t o = p.c_rp[row];
+      const int64_t lim = max((int64_t)0, min((int64_t)n, p.c_capacity - o));
+      if (threadIdx.x == 0 && lim < n) atomicOr((unsigned long long *)err, (unsigned long long)kErrCapacity);
+      wg_global_extract(gkeys, gvals, alloc, ws.dmax, ws, p.c_col + o, p.c_val + o, lim);
     }
     __syncthreads();
   }
 }
+
 
 // ===================================================== register-merge rows
 // Matrices whose every row is a register-merge row need no tiles and no
@@ -1422,43 +1550,58 @@ hipError_t launch_wave_merge(const Operands &op, int mode, int merge_lists, int6
   return hipGetLastError();
 }
 
-template <int G, int M, bool HASH>
-static hipError_t launch_tiles_ghm(const TileParams &tp, int mode, int grid, size_t lds, hipStream_t s) {
-  switch (mode) {
-    case kSymbolic:
-      hipLaunchKernelGGL((k_tile<G, M, kSymbolic, HASH>), dim3(grid), dim3(kBlock), lds, s, tp);
-      break;
-    case kNumeric:
-      hipLaunchKernelGGL((k_tile<G, M, kNumeric, HASH>), dim3(grid), dim3(kBlock), lds, s, tp);
-      break;
-    default:
-      hipLaunchKernelGGL((k_tile<G, M, kOnePass, HASH>), dim3(grid), dim3(kBlock), lds, s, tp);
-      break;
+size_t wave_tile_lds(int mode, int table_slots, int stage_slots) {
+  return wave_lds_layout(mode != kSymbolic, table_slots, stage_slots).total;
+}
+
+template <int MODE, int M>
+static hipError_t launch_wt_mm(const WaveTileParams &wp, size_t lds, int64_t grid_cap, hipStream_t s) {
+  const void *fn = reinterpret_cast<const void *>(&k_wt<MODE, M>);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
   }
+  int64_t grid = wp.ntiles;
+  if (MODE == kOnePass) {
+    // the whole grid must be resident: tiles wait on lower-numbered tiles
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWave, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    per_cu = std::min(per_cu, 16);
+    grid = std::min<int64_t>(grid, (int64_t)per_cu * device_cus());
+    if (grid_cap > 0) grid = std::min(grid, grid_cap);
+  }
+  grid = std::min<int64_t>(grid, 0x7fffffff);
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_wt<MODE, M>), dim3((unsigned)grid), dim3(kWave), lds, s, wp);
   return hipGetLastError();
 }
 
 template <int M>
-static hipError_t launch_tiles_m(const TileParams &tp, int mode, int group, bool hash, int grid, size_t lds,
-                                 hipStream_t s) {
-  if (!hash) return launch_tiles_ghm<8, M, false>(tp, mode, grid, lds, s);
-  switch (group) {
-    case 4: return launch_tiles_ghm<4, M, true>(tp, mode, grid, lds, s);
-    case 8: return launch_tiles_ghm<8, M, true>(tp, mode, grid, lds, s);
-    case 16: return launch_tiles_ghm<16, M, true>(tp, mode, grid, lds, s);
-    case 32: return launch_tiles_ghm<32, M, true>(tp, mode, grid, lds, s);
-    case 64: return launch_tiles_ghm<64, M, true>(tp, mode, grid, lds, s);
+static hipError_t launch_wt_m(const WaveTileParams &wp, int mode, size_t lds, int64_t grid_cap, hipStream_t s) {
+  switch (mode) {
+    case kSymbolic: return launch_wt_mm<kSymbolic, M>(wp, lds, grid_cap, s);
+    case kNumeric: return launch_wt_mm<kNumeric, M>(wp, lds, grid_cap, s);
+    default: return launch_wt_mm<kOnePass, M>(wp, lds, grid_cap, s);
+  }
+}
+
+hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, int64_t grid_cap, hipStream_t s) {
+  const size_t lds = wave_tile_lds(mode, wp.table_slots, wp.stage_slots);
+  switch (merge_lists) {
+    case 4: return launch_wt_m<4>(wp, mode, lds, grid_cap, s);
+    case 8: return launch_wt_m<8>(wp, mode, lds, grid_cap, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_tiles(const TileParams &tp, int mode, int group, int merge_lists, bool hash, int grid,
-                        size_t lds_bytes, hipStream_t s) {
-  switch (merge_lists) {
-    case 4: return launch_tiles_m<4>(tp, mode, group, hash, grid, lds_bytes, s);
-    case 8: return launch_tiles_m<8>(tp, mode, group, hash, grid, lds_bytes, s);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_big_rows(const BigParams &bp, int mode, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (mode == kSymbolic) hipLaunchKernelGGL(k_big<kSymbolic>, dim3(grid), dim3(kBlock), 0, s, bp);
+  else hipLaunchKernelGGL(k_big<kNumeric>, dim3(grid), dim3(kBlock), 0, s, bp);
+  return hipGetLastError();
 }
 
 }  // namespace spg
+

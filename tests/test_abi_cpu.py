@@ -77,12 +77,14 @@ def test_learned_sizer_without_model_is_rejected():
 def test_invalid_tuning_is_rejected():
     from paper_1303_1651_amd import _lib as L
     A = L.spgemm_csr(4, 4, 0, 1, None, None)
-    t = L.spgemm_tuning(hash_group=12)
-    opts = L.spgemm_options(0, 0, None, ctypes.pointer(t))
-    plan = ctypes.c_void_p()
-    code = L.spgemm_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(opts), 1, 1 << 20, None,
-                                ctypes.byref(plan), None)
-    assert code == 10
+    for bad in (dict(table_slots=300), dict(stage_slots=100), dict(stage_slots=9000),
+                dict(merge_lists=6)):
+        t = L.spgemm_tuning(**bad)
+        opts = L.spgemm_options(0, 0, None, ctypes.pointer(t))
+        plan = ctypes.c_void_p()
+        code = L.spgemm_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(opts), 1, 1 << 20, None,
+                                    ctypes.byref(plan), None)
+        assert code == 10, bad
 
 
 def test_model_file_round_trip(tmp_path):

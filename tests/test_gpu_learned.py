@@ -131,7 +131,7 @@ def test_learned_product_equals_oracle(trained, case):
     else:
         A = B = synth.stencil(14, 3, 27)
     want = oracle.spgemm(A, B)
-    for tier in [None, {"merge_max_nnz": -1}, {"merge_max_nnz": -1, "pool_slots": 512, "max_tile_rows": 64}]:
+    for tier in [None, {"merge_max_nnz": -1}, {"merge_max_nnz": -1, "table_slots": 256, "stage_slots": 256}]:
         got = gpu_product(A, B, "learned", model=trained, tuning=tier)
         assert_bit_exact(got, want)
 

@@ -22,12 +22,12 @@ SIZERS = ["exact", "upper_bound"]
 TIERS = {
     "default": None,
     "hash_only": {"merge_max_nnz": -1},
-    "global_only": {"merge_max_nnz": -1, "pool_slots": -1},
+    "global_only": {"merge_max_nnz": -1, "table_slots": -1},
     "hash_dense": {"merge_max_nnz": -1, "dense_ratio": 1e9},
     "hash_sparse": {"merge_max_nnz": -1, "dense_ratio": 1e-9},
-    "small_pool": {"merge_max_nnz": -1, "pool_slots": 256, "max_tile_rows": 64},
-    "group4": {"merge_max_nnz": -1, "hash_group": 4},
-    "group64": {"merge_max_nnz": -1, "hash_group": 64},
+    "small_table": {"merge_max_nnz": -1, "table_slots": 256, "stage_slots": 256},
+    "big_table": {"merge_max_nnz": -1, "table_slots": 4096, "stage_slots": 4096},
+    "merge4": {"merge_lists": 4, "merge_max_nnz": 128},
 }
 
 
@@ -78,14 +78,15 @@ def test_wider_stencils(n, dim, points):
     A = synth.stencil(n, dim, points)
     want = oracle.spgemm(A, A)
     for sizer in SIZERS:
-        assert_bit_exact(gpu_product(A, A, sizer), want)
+        for tier in ["default", "small_table", "global_only", "hash_sparse"]:
+            assert_bit_exact(gpu_product(A, A, sizer, tuning=TIERS[tier]), want)
 
 
 def test_power_law_rows():
     A = synth.zipf_matrix(30000, 11)
     want = oracle.spgemm(A, A)
     for sizer in SIZERS:
-        for tier in ["default", "small_pool"]:
+        for tier in ["default", "small_table", "big_table"]:
             assert_bit_exact(gpu_product(A, A, sizer, tuning=TIERS[tier]), want)
 
 
