@@ -174,14 +174,22 @@ void spgemm_plan_destroy(spgemm_plan *plan);
 const char *spgemm_status_string(spgemm_status s);
 
 /* ---------------------------------------------------------------- batched
- * Many independent products C_i = A_i * B_i in one persistent launch.
- * A, B: host arrays of `count` descriptors (device data).  The outputs of
- * product i are placed at c_row_base[i] (row pointers, rows_i + 1 entries,
- * relative to the product's own first entry) and c_nnz_base[i] (entries) of
- * the pools; the caller takes both from spgemm_batched_plan.
- * First, size query: spgemm_batched_plan fills row bases (host, count + 1),
- * capacity bases (host, count + 1), and the workspace and scratch it needs.
- * It reads only descriptors (no device data) and does not synchronise. */
+ * Many independent products C_i = A_i * B_i (each as in spgemm_plan_create:
+ * Section II's C = A * B row by row) computed together: the instances are
+ * laid side by side in one row space (A_i's columns shifted past the B rows
+ * of the instances before it, the B_i stacked), so one plan and one
+ * persistent numeric launch cover every row of every instance, and C comes
+ * out as the concatenation of the C_i.  Not part of the paper.
+ *
+ * spgemm_batched_plan: A, B are host arrays of `count` descriptors (device
+ * data; the data must stay unchanged in structure until the batch is
+ * destroyed, values may change between runs).  Writes c_row_base (host,
+ * count + 1): product i's row pointers go to c_row_pool[c_row_base[i] ..
+ * c_row_base[i] + rows_i] (rows_i + 1 entries, relative to the product's
+ * first entry).  *workspace_bytes: device workspace the batch needs.  Reads
+ * descriptors only, no device work.  Errors: SPGEMM_E_DIM (A_i.cols !=
+ * B_i.rows), SPGEMM_E_INDEX_OVERFLOW (total rows of A or B >= 2^31),
+ * SPGEMM_E_NO_MODEL, SPGEMM_E_INVALID. */
 typedef struct spgemm_batch spgemm_batch;
 
 spgemm_status spgemm_batched_plan(int64_t count, const spgemm_csr *A, const spgemm_csr *B,
@@ -189,22 +197,30 @@ spgemm_status spgemm_batched_plan(int64_t count, const spgemm_csr *A, const spge
                                   int64_t *c_row_base, size_t *workspace_bytes,
                                   spgemm_batch **out);
 
-/* Runs the whole batch: features, sizing, tiling and the persistent tiled
- * numeric kernel over all products, captured in a HIP graph on first use and
- * replayed afterwards (same batch object, same pointers).  c_nnz_base
- * (host, count + 1) receives the entry bases chosen from the capacities; the
- * pools must hold c_capacity entries in total.  c_nnz (host, count) receives
- * each product's nnz.  Returns SPGEMM_E_CAPACITY (and the required total in
- * *c_required) when the pools are too small.  Synchronises `stream`. */
-spgemm_status spgemm_batched(spgemm_batch *batch, void *workspace, size_t workspace_bytes,
+/* Binds the workspace (kept until destroy or the next reserve), builds the
+ * concatenated operands in it, and plans them (features, learned or bound
+ * sizing, tiers, tiles).  *c_capacity (host): entries the pools must hold
+ * (sum of multiplication counts for EXACT and UPPER_BOUND, of learned
+ * capacities for LEARNED); *scratch_bytes (host): device scratch the runs
+ * need.  Synchronises `stream`. */
+spgemm_status spgemm_batched_reserve(spgemm_batch *batch, void *workspace, size_t workspace_bytes,
+                                     int64_t *c_capacity, size_t *scratch_bytes, void *stream);
+
+/* Runs every product.  Entries of product i are written at c_col_pool /
+ * c_val_pool[c_nnz_base[i] .. c_nnz_base[i] + c_nnz[i]) (c_nnz_base: host,
+ * count + 1, c_nnz_base[count] = total; c_nnz: host, count).  The first run
+ * (and any run with other pointers) takes the checked path and captures its
+ * launches in a HIP graph; later runs with the same pointers replay it.
+ * If the pools are too small: SPGEMM_E_CAPACITY with the total needed in
+ * *c_required (may be NULL).  Synchronises `stream`. */
+spgemm_status spgemm_batched(spgemm_batch *batch, void *scratch, size_t scratch_bytes,
                              int64_t *c_row_pool, int32_t *c_col_pool, double *c_val_pool,
                              int64_t c_capacity, int64_t *c_nnz_base, int64_t *c_nnz,
                              int64_t *c_required, void *stream);
 
-/* Capacity the batch needs (host, after one spgemm_batched_reserve call):
- * runs the feature and sizing kernels and returns the total capacity. */
-spgemm_status spgemm_batched_reserve(spgemm_batch *batch, void *workspace, size_t workspace_bytes,
-                                     int64_t *c_capacity, void *stream);
+/* 1 when the next spgemm_batched call with the same pointers replays a
+ * captured graph. */
+int spgemm_batched_uses_graph(const spgemm_batch *batch);
 void spgemm_batched_destroy(spgemm_batch *batch);
 
 /* ------------------------------------------------------------- learned sizer

@@ -283,3 +283,79 @@ def spgemm(A: DeviceCSR, B: DeviceCSR, sizer="exact", model: Model | None = None
         return Result(rp, col[:got], val[:got], info)
     finally:
         plan.close()
+
+
+class Batch:
+    """Many independent products C_i = A_i * B_i in one plan and one
+    persistent launch (graph-replayed after the first run).  Argument
+    marshalling only: every step runs in the library."""
+
+    def __init__(self, As, Bs, sizer="upper_bound", model: Model | None = None, tuning: dict | None = None,
+                 stream=None, timing=False):
+        assert len(As) == len(Bs)
+        self.As, self.Bs = list(As), list(Bs)
+        self.count = len(self.As)
+        self.stream = stream
+        self.device = self.As[0].row_ptr.device if self.count else torch.device("cuda")
+        self._da = (_lib.spgemm_csr * max(self.count, 1))(*[a.descriptor() for a in self.As])
+        self._db = (_lib.spgemm_csr * max(self.count, 1))(*[b.descriptor() for b in self.Bs])
+        self._tuning = make_tuning(**tuning) if tuning else None
+        flags = _lib.OPT_TIMING if timing else 0
+        self._opts = _lib.spgemm_options(SIZERS[sizer] if isinstance(sizer, str) else int(sizer), flags,
+                                         model.handle if model is not None else None,
+                                         ctypes.pointer(self._tuning) if self._tuning is not None else None)
+        self.row_base = np.zeros(self.count + 1, dtype=np.int64)
+        ws = _lib.SZ()
+        self.handle = ctypes.c_void_p()
+        check(_lib.spgemm_batched_plan(self.count, self._da, self._db, ctypes.byref(self._opts),
+                                       self.row_base.ctypes.data_as(_lib.I64_P), ctypes.byref(ws),
+                                       ctypes.byref(self.handle)), "spgemm_batched_plan")
+        self.workspace = _bytes(ws.value, self.device)
+        cap, sb = ctypes.c_int64(), _lib.SZ()
+        check(_lib.spgemm_batched_reserve(self.handle, self.workspace.data_ptr(), self.workspace.numel(),
+                                          ctypes.byref(cap), ctypes.byref(sb), _stream_ptr(stream)),
+              "spgemm_batched_reserve")
+        self.capacity = int(cap.value)
+        self.scratch = _bytes(sb.value, self.device) if sb.value else None
+        self.row_pool = torch.empty(int(self.row_base[-1]), dtype=torch.int64, device=self.device)
+        self.col_pool = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=self.device)
+        self.val_pool = torch.empty(max(self.capacity, 1), dtype=torch.float64, device=self.device)
+
+    def uses_graph(self) -> bool:
+        return bool(_lib.spgemm_batched_uses_graph(self.handle))
+
+    def run(self):
+        """Runs every product; returns (nnz_base, nnz) as host arrays."""
+        base = np.zeros(self.count + 1, dtype=np.int64)
+        nnz = np.zeros(max(self.count, 1), dtype=np.int64)
+        req = ctypes.c_int64()
+        sp = self.scratch.data_ptr() if self.scratch is not None else None
+        sb = self.scratch.numel() if self.scratch is not None else 0
+        for _ in range(2):
+            code = _lib.spgemm_batched(self.handle, sp, sb, self.row_pool.data_ptr(), self.col_pool.data_ptr(),
+                                       self.val_pool.data_ptr(), self.capacity,
+                                       base.ctypes.data_as(_lib.I64_P), nnz.ctypes.data_as(_lib.I64_P),
+                                       ctypes.byref(req), _stream_ptr(self.stream))
+            if code == 6:   # pools too small (learned capacities): grow and run again
+                self.capacity = int(req.value)
+                self.col_pool = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=self.device)
+                self.val_pool = torch.empty(max(self.capacity, 1), dtype=torch.float64, device=self.device)
+                continue
+            check(code, "spgemm_batched")
+            break
+        self.nnz_base, self.nnz = base, nnz[:self.count]
+        return self.nnz_base, self.nnz
+
+    def product(self, i: int):
+        """Host copy (row_ptr, col, val) of product i after run()."""
+        rp = self.row_pool[int(self.row_base[i]):int(self.row_base[i + 1])].cpu().numpy()
+        b, n = int(self.nnz_base[i]), int(self.nnz[i])
+        return rp, self.col_pool[b:b + n].cpu().numpy(), self.val_pool[b:b + n].cpu().numpy()
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.spgemm_batched_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()

@@ -119,16 +119,14 @@ EXPORTED = [
     "spgemm_model_loss_grad", "spgemm_model_train_scratch", "spgemm_model_train", "spgemm_model_predict",
 ]
 
-# batched entry points are bound when the library exports them
-for _name, _res, _args in [
-    ("spgemm_batched_plan", ctypes.c_int, [I64, CSR_P, CSR_P, OPT_P, I64_P, I64_P, SZ_P, SZ_P, ctypes.POINTER(P)]),
-    ("spgemm_batched", ctypes.c_int, [P, P, SZ, P, SZ, P, P, P, I64, I64_P, I64_P, P]),
-    ("spgemm_batched_info", ctypes.c_int, [P, I64_P, I64_P]),
-    ("spgemm_batched_destroy", None, [P]),
-]:
-    if hasattr(lib, _name):
-        globals()[_name] = _sig(_name, _res, _args)
-        EXPORTED.append(_name)
+spgemm_batched_plan = _sig("spgemm_batched_plan", ctypes.c_int,
+                           [I64, CSR_P, CSR_P, OPT_P, I64_P, SZ_P, ctypes.POINTER(P)])
+spgemm_batched_reserve = _sig("spgemm_batched_reserve", ctypes.c_int, [P, P, SZ, I64_P, SZ_P, P])
+spgemm_batched = _sig("spgemm_batched", ctypes.c_int, [P, P, SZ, P, P, P, I64, I64_P, I64_P, I64_P, P])
+spgemm_batched_uses_graph = _sig("spgemm_batched_uses_graph", ctypes.c_int, [P])
+spgemm_batched_destroy = _sig("spgemm_batched_destroy", None, [P])
+EXPORTED += ["spgemm_batched_plan", "spgemm_batched_reserve", "spgemm_batched", "spgemm_batched_uses_graph",
+             "spgemm_batched_destroy"]
 
 
 class SpgemmError(RuntimeError):

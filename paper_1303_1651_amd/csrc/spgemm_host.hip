@@ -368,6 +368,39 @@ static spgemm_status clear_run_counters(spgemm_plan *p, hipStream_t s) {
   return SPGEMM_OK;
 }
 
+namespace spg {
+
+// Kernel launches of the numeric pass (two-pass numeric or one pass), in
+// stream order and without any synchronisation, so that a caller may
+// capture them in a HIP graph.  The caller has checked the arguments.
+spgemm_status numeric_enqueue(spgemm_plan *p, void *scratch, size_t scratch_bytes, const double *av,
+                              const double *bv, int64_t *c_row_ptr, int32_t *c_col, double *c_val,
+                              int64_t c_capacity, hipStream_t s) {
+  spgemm_status st = clear_run_counters(p, s);
+  if (st != SPGEMM_OK) return st;
+  const int mode = p->first_mode == kSymbolic ? kNumeric : kOnePass;
+  if (p->merge_only) {
+    if (mode == kOnePass) HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
+    HIPCK(p, launch_wave_merge(operands_of(p, av, bv), mode, p->tune.merge_lists, ctr(p), p->pa.status, nullptr,
+                               c_row_ptr, c_col, c_val, c_capacity, s));
+    return SPGEMM_OK;
+  }
+  // one pass: workgroup-tier rows are counted first, the wave tiles then
+  // place every row, and those rows are written last
+  if (mode == kOnePass) st = run_big(p, kSymbolic, scratch, scratch_bytes, av, bv, nullptr, nullptr, nullptr, 0, s);
+  if (st == SPGEMM_OK) st = run_wave(p, mode, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+  if (st == SPGEMM_OK) st = run_big(p, kNumeric, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+  return st;
+}
+
+int64_t *plan_counters(spgemm_plan *p) { return p->pa.counters; }
+int plan_is_one_pass(const spgemm_plan *p) { return p->first_mode != kSymbolic; }
+size_t plan_workspace_bytes(int64_t rows) { return layout_for(rows).total; }
+
+spgemm_status plan_check_counters(spgemm_plan *p, const int64_t *h) { return device_errors(p, h); }
+
+}  // namespace spg
+
 extern "C" {
 
 const char *spgemm_status_string(spgemm_status s) {
@@ -599,26 +632,12 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
     p->stage = 2;
     return SPGEMM_OK;
   }
-  spgemm_status st = clear_run_counters(p, s);
-  if (st != SPGEMM_OK) return st;
   const int mode = two_pass ? kNumeric : kOnePass;
-  if (p->merge_only && mode == kOnePass) HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
   hipError_t e = hipSuccess;
   timing_begin(p, s, &e);
   HIPCK(p, e);
-  if (p->merge_only) {
-    HIPCK(p, launch_wave_merge(operands_of(p, av, bv), mode, p->tune.merge_lists, ctr(p), p->pa.status, nullptr,
-                               c_row_ptr, c_col, c_val, c_capacity, s));
-  } else {
-    // one pass: workgroup-tier rows are counted first, the wave tiles then
-    // place every row, and those rows are written last
-    if (mode == kOnePass)
-      st = run_big(p, kSymbolic, scratch, scratch_bytes, av, bv, nullptr, nullptr, nullptr, 0, s);
-    if (st == SPGEMM_OK) st = run_wave(p, mode, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
-    if (st == SPGEMM_OK)
-      st = run_big(p, kNumeric, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
-    if (st != SPGEMM_OK) return st;
-  }
+  spgemm_status st = numeric_enqueue(p, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+  if (st != SPGEMM_OK) return st;
   timing_end(p, s, &e);
   HIPCK(p, e);
   int64_t *h;

@@ -15,6 +15,16 @@ constexpr int kMlpDevFloats = kMlpParams + 6;   // theta, mu[3], sd[3]
 int device_cus();
 int64_t *host_counters();
 
+// Numeric pass of a plan as kernel launches only (no synchronisation), for
+// graph capture; and access to the plan's device counters.
+spgemm_status numeric_enqueue(spgemm_plan *p, void *scratch, size_t scratch_bytes, const double *av,
+                              const double *bv, int64_t *c_row_ptr, int32_t *c_col, double *c_val,
+                              int64_t c_capacity, hipStream_t s);
+int64_t *plan_counters(spgemm_plan *p);
+int plan_is_one_pass(const spgemm_plan *p);
+size_t plan_workspace_bytes(int64_t rows);
+spgemm_status plan_check_counters(spgemm_plan *p, const int64_t *h);
+
 // Predicted nnz(C_row) for n rows; dev_params holds kMlpDevFloats floats
 // (theta, mu, sd) already on the device.
 hipError_t launch_mlp_predict(const float *dev_params, const int32_t *f1, const int32_t *f2,

@@ -15,8 +15,8 @@ LIB = os.path.join(ROOT, "paper_1303_1651_amd", "libspgemm.so")
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        from paper_1303_1651_amd import build
-        build.build()
+        import __graft_entry__
+        __graft_entry__.build()
     return ctypes.CDLL(LIB)
 
 
@@ -103,3 +103,19 @@ def test_model_file_round_trip(tmp_path):
     bad.write_bytes(b"not a model")
     with pytest.raises(Exception):
         Model.load(str(bad))
+
+
+def test_batched_plan_checks_descriptors_without_a_device():
+    from paper_1303_1651_amd import _lib as L
+    opts = L.spgemm_options(1, 0, None, None)
+    A = (L.spgemm_csr * 2)(L.spgemm_csr(4, 3, 0, 1, None, None), L.spgemm_csr(2, 5, 0, 1, None, None))
+    B = (L.spgemm_csr * 2)(L.spgemm_csr(3, 4, 0, 1, None, None), L.spgemm_csr(4, 2, 0, 1, None, None))
+    rb = (ctypes.c_int64 * 3)()
+    ws = L.SZ()
+    h = ctypes.c_void_p()
+    # instance 1: A.cols (5) != B.rows (4)
+    assert L.spgemm_batched_plan(2, A, B, ctypes.byref(opts), rb, ctypes.byref(ws), ctypes.byref(h)) == 2
+    assert not h.value
+    # learned sizing without a model
+    lo = L.spgemm_options(2, 0, None, None)
+    assert L.spgemm_batched_plan(1, A, B, ctypes.byref(lo), rb, ctypes.byref(ws), ctypes.byref(h)) == 7
