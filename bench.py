@@ -1,23 +1,31 @@
 """Throughput of C = A * B (FP64 CSR) on one MI355X.
 
-Workload (the roofline study configuration): the five-point Laplacian on a
-2048 x 2048 grid squared (N = 4,194,304), plus a random N = 2^21 matrix with
+Default workload (the roofline study): the five-point Laplacian on a
+2048 x 2048 grid squared (N = 4,194,304), and a random N = 2^21 matrix with
 exactly 16 distinct uniform columns per row and values U(-1, 1) times an
-independent matrix drawn the same way.  One step is one full product of each
-(plan with features, sizing and tiling, then the numeric pass writing C).
+independent matrix drawn the same way.  One step is one full product of
+each on the plain two-pass path (plan, symbolic pass, scan, numeric pass);
+inputs are resident in HBM before the timed region.  Other workloads:
+--workload zipf (power-law rows, N = 2^20, the learned-sizer study), st9,
+st27, batched.
 
-Metric: GFLOP/s with the paper's flop count (Section III: twice the number of
-multiplications), and achieved HBM GB/s against a minimum-traffic model
-|A| + |B| + |C|, |X| = 12 nnz(X) + 8 (rows(X) + 1) (int32 columns, FP64
-values, int64 row pointers), as a fraction of the 8 TB/s HBM3E peak.
+Metric: GFLOP/s with the paper's flop count (Section III: twice the number
+of multiplications).  The roofline object is for the step's dominant kernel
+(the numeric wave-tile pass of the random product): algorithmic bytes per
+launch (|A| + |B| + |C| with |X| = 12 nnz(X) + 8 (rows(X) + 1): int32
+columns, FP64 values, int64 row pointers) over its average launch time,
+measured with HIP events on the stream the kernel runs on, against the
+8 TB/s HBM3E peak.  `traffic` comes from the committed rocprofv3 counter
+summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel's reading)
+when that summary was taken on the current kernel source, else null.
 
 Prints ONE JSON line.  Only one GPU is used: --gpus above 1 exits.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -26,6 +34,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1303_1651_amd", "csrc", "spgemm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_wave_tile_numeric_random16.json")
 
 
 def model_bytes(A, B, nnz_c):
@@ -36,12 +46,31 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def make_workloads():
+def kernel_source_sha1():
+    return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
+
+
+def make_workloads(name):
     import synth
-    S = synth.stencil(2048)
-    R1 = synth.random_fixed(1 << 21, 16, 1)
-    R2 = synth.random_fixed(1 << 21, 16, 2)
-    return [("stencil5_2048sq", S, S), ("random16_2pow21", R1, R2)]
+    if name == "roofline":
+        S = synth.stencil(2048)
+        return [("stencil5_2048sq", S, S),
+                ("random16_2pow21", synth.random_fixed(1 << 21, 16, 1), synth.random_fixed(1 << 21, 16, 2))]
+    if name == "stencil":
+        S = synth.stencil(2048)
+        return [("stencil5_2048sq", S, S)]
+    if name == "random":
+        return [("random16_2pow21", synth.random_fixed(1 << 21, 16, 1), synth.random_fixed(1 << 21, 16, 2))]
+    if name == "zipf":
+        Z = synth.zipf_matrix(1 << 20, 3)
+        return [("zipf2_2pow20", Z, Z)]
+    if name == "st9":
+        S = synth.stencil(2048, 2, 9)
+        return [("stencil9_2048sq", S, S)]
+    if name == "st27":
+        S = synth.stencil(160, 3, 27)
+        return [("stencil27_160cube", S, S)]
+    raise ValueError(name)
 
 
 def train_sizer(P, torch, seed_base=1001):
@@ -49,11 +78,9 @@ def train_sizer(P, torch, seed_base=1001):
     Training rows: power-law matrices (seeds disjoint from any evaluation
     seed), small stencils and small fixed-length random matrices; labels are
     the exact row sizes from the symbolic pass."""
-    import numpy as np
     import synth
     feats, labels = [], []
-    mats = [synth.zipf_matrix(1 << 18, seed_base + i) for i in range(4)]
-    pairs = [(M, M) for M in mats]
+    pairs = [(synth.zipf_matrix(1 << 18, seed_base + i),) * 2 for i in range(4)]
     for g in (64, 96, 128):
         S = synth.stencil(g)
         pairs.append((S, S))
@@ -85,53 +112,193 @@ def train_sizer(P, torch, seed_base=1001):
     return model, {"train_rows": int(f1.numel()), "loss_first": float(curve[0]), "loss_last": float(curve[-1])}
 
 
-def run_product(P, torch, dA, dB, sizer, model, timing=True):
-    plan = P.Plan(dA, dB, sizer, model, timing=timing)
-    dev = dA.row_ptr.device
-    if sizer == "exact":
-        rp, nnz = plan.symbolic()
-        cap = nnz
-    else:
-        rp = torch.empty(dA.rows + 1, dtype=torch.int64, device=dev)
-        cap = max(int(plan.info["c_capacity_hint"]), 1)
-    col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-    val = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
-    code, got = plan.numeric(rp, col, val, capacity=cap)
-    if code == 6:
-        col = torch.empty(got, dtype=torch.int32, device=dev)
-        val = torch.empty(got, dtype=torch.float64, device=dev)
-        code, got = plan.numeric(rp, col, val, capacity=got)
-    P.check(code, "spgemm_numeric")
-    info = dict(plan.info)
-    plan.close()
-    return got, info, (rp, col, val)
+class Product:
+    """One product on the device with its output buffers allocated once."""
+
+    def __init__(self, P, torch, name, A, B, dA, dB):
+        self.P, self.torch = P, torch
+        self.name, self.A, self.B, self.dA, self.dB = name, A, B, dA, dB
+        self.out = {}
+
+    def run(self, sizer, model):
+        P, torch = self.P, self.torch
+        plan = P.Plan(self.dA, self.dB, sizer, model, timing=True)
+        dev = self.dA.row_ptr.device
+        sym_ms = 0.0
+        if sizer == "exact":
+            rp, nnz = plan.symbolic(self.out.get("rp"))
+            sym_ms = plan.info["tile_ms"]
+            cap = nnz
+        else:
+            rp = self.out.get("rp")
+            if rp is None:
+                rp = torch.empty(self.dA.rows + 1, dtype=torch.int64, device=dev)
+            cap = max(int(plan.info["c_capacity_hint"]), 1)
+        self.out["rp"] = rp
+        col, val = self.out.get("col"), self.out.get("val")
+        if col is None or col.numel() < cap:
+            col = torch.empty(cap, dtype=torch.int32, device=dev)
+            val = torch.empty(cap, dtype=torch.float64, device=dev)
+            self.out["col"], self.out["val"] = col, val
+        code, got = plan.numeric(rp, col, val, capacity=cap)
+        if code == 6:
+            col = torch.empty(got, dtype=torch.int32, device=dev)
+            val = torch.empty(got, dtype=torch.float64, device=dev)
+            self.out["col"], self.out["val"] = col, val
+            code, got = plan.numeric(rp, col, val, capacity=got)
+        P.check(code, "spgemm_numeric")
+        info = dict(plan.info)
+        info["symbolic_ms"] = sym_ms
+        info["numeric_ms"] = info["tile_ms"]
+        plan.close()
+        return got, info
 
 
-def cpu_baseline(workloads, budget_s=12.0):
+def time_steps(torch, products, sizer, model, steps, warmup):
+    for _ in range(warmup):
+        for p in products:
+            p.run(sizer, model)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    per = []
+    torch.cuda.synchronize()
+    e0.record()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        per.append([p.run(sizer, model) for p in products])
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall * 1e3 / steps, per
+
+
+def cpu_baseline(workloads, random_rows=1 << 19):
     """The oracle (single-threaded C Gustavson) on a bounded sample: the whole
-    stencil square and as many leading rows of the random product as fit the
-    budget.  Reported in GFLOP/s with the same flop convention."""
-    import numpy as np
+    stencil square and the leading rows of the random product.  Reported in
+    GFLOP/s with the same flop convention."""
     import oracle
     flops = 0
     t_tot = 0.0
     parts = []
     for name, A, B in workloads:
         f1, ub, mx = oracle.features(A, B)
-        rows = A.rows
-        if name.startswith("stencil"):
-            r1 = rows
-        else:
-            # about a quarter of the budget per random sample
-            r1 = min(rows, 1 << 18)
+        r1 = A.rows if A.rows <= (1 << 22) and not name.startswith("random") else min(A.rows, random_rows)
         t0 = time.perf_counter()
         oracle.spgemm(A, B, 0, r1)
         dt = time.perf_counter() - t0
         flops += 2 * int(ub[:r1].sum())
         t_tot += dt
         parts.append("%s rows 0..%d (%.2f s)" % (name, r1, dt))
-    return {"value": flops / t_tot / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": "; ".join(parts) + "; single-threaded C oracle, one run each"}
+    return {"value": round(flops / t_tot / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": "; ".join(parts) + "; single-threaded C oracle, one run each, on the host of the GPU"}
+
+
+def traffic_from_profile(launch_bytes_alg):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it is missing or was taken on other kernel source."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha1") != kernel_source_sha1():
+        return None
+    return int(d["traffic_bytes_per_launch"])
+
+
+def calibrate_copy(torch, nbytes=1 << 30):
+    """A plain device copy of known size, for scaling the HBM counters."""
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    return nbytes
+
+
+def pmc_summary(fetch_csv, write_csv, kernel_substr, copy_bytes, out_json, command):
+    """Writes the traffic summary from two rocprofv3 --pmc runs (FETCH_SIZE,
+    then WRITE_SIZE; counter_collection.csv files): per-dispatch KiB of the
+    kernel, scaled by what the same counters read for the calibration copy
+    (the largest device copy dispatch of the run, copy_bytes each way)."""
+    import csv
+
+    def rows(path, counter):
+        return [(r["Kernel_Name"], float(r["Counter_Value"]))
+                for r in csv.DictReader(open(path)) if r.get("Counter_Name", "") == counter]
+
+    def mean_of(rs, sub):
+        v = [x for n, x in rs if sub in n]
+        return sum(v) / len(v) if v else None
+
+    def copy_of(rs):
+        v = [x for n, x in rs if "copyBuffer" in n or "copy" in n.lower()]
+        return max(v) if v else None
+
+    f = rows(fetch_csv, "FETCH_SIZE")
+    w = rows(write_csv, "WRITE_SIZE")
+    fk, wk = mean_of(f, kernel_substr), mean_of(w, kernel_substr)
+    fc, wc = copy_of(f), copy_of(w)
+    if None in (fk, wk, fc, wc):
+        raise SystemExit("kernel %r or the calibration copy is missing from the counter files" % kernel_substr)
+    ff = (copy_bytes / 1024.0) / fc
+    wf = (copy_bytes / 1024.0) / wc
+    traffic = (fk * ff + wk * wf) * 1024.0
+    d = {"kernel": kernel_substr, "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
+         "copy_bytes": copy_bytes, "copy_fetch_kib": fc, "copy_write_kib": wc,
+         "fetch_factor": ff, "write_factor": wf, "traffic_bytes_per_launch": traffic,
+         "source_sha1": kernel_source_sha1(), "command": command}
+    json.dump(d, open(out_json, "w"), indent=1)
+    print(json.dumps(d))
+
+
+def stats_summary(stats_csv, out_txt, command, top=16):
+    """Text summary of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = ["command: " + command, "",
+             "%-64s %6s %14s %12s %7s" % ("kernel", "calls", "total_ms", "avg_ms", "pct")]
+    for r in rows[:top]:
+        lines.append("%-64s %6s %14.3f %12.4f %7.2f" % (r["Name"][:64], r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+                                                        float(r["AverageNs"]) / 1e6, float(r["Percentage"])))
+    open(out_txt, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def run_batched(P, torch, args):
+    """Batched products vs a per-instance loop (scaled instance sizes)."""
+    import synth
+    insts = synth.batch_mix(args.batch_count, 7, lo=args.batch_lo, hi=args.batch_hi)
+    As, Bs = [], []
+    for it in insts:
+        dA = P.DeviceCSR.from_host(it.A)
+        As.append(dA)
+        Bs.append(dA if it.B is it.A else P.DeviceCSR.from_host(it.B))
+    batch = P.Batch(As, Bs, "upper_bound")
+    batch.run()
+    for _ in range(args.warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run()
+    torch.cuda.synchronize()
+    bms = (time.perf_counter() - t0) * 1e3 / args.steps
+    import numpy as np
+    mults = 0
+    for it in insts:
+        # Section III count: sum over k of nnz(A column k) * nnz(B row k)
+        acol = np.bincount(np.asarray(it.A.col), minlength=it.A.cols)
+        mults += int(np.dot(acol.astype(np.int64), np.diff(np.asarray(it.B.row_ptr)).astype(np.int64)))
+    t0 = time.perf_counter()
+    for a, b in zip(As, Bs):
+        P.spgemm(a, b, "upper_bound")
+    torch.cuda.synchronize()
+    lms = (time.perf_counter() - t0) * 1e3
+    return {"instances": len(insts), "rows": int(sum(it.A.rows for it in insts)), "multiplications": mults,
+            "nnz_c": int(batch.nnz.sum()), "batched_ms": round(bms, 3), "loop_ms": round(lms, 3),
+            "batched_gflops": round(2 * mults / (bms * 1e-3) / 1e9, 3), "loop_gflops": round(2 * mults / (lms * 1e-3) / 1e9, 3),
+            "graph_replay": batch.uses_graph()}
 
 
 def main():
@@ -139,11 +306,28 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--sizer", default="learned", choices=["learned", "upper_bound", "exact"])
+    ap.add_argument("--sizer", default="exact", choices=["learned", "upper_bound", "exact"])
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--compare", action="store_true", help="also time the other sizers")
-    ap.add_argument("--workload", default="all", choices=["all", "stencil", "random"])
+    ap.add_argument("--no-compare", action="store_true", help="skip timing the other sizers")
+    ap.add_argument("--workload", default="roofline",
+                    choices=["roofline", "stencil", "random", "zipf", "st9", "st27", "batched"])
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--batch-lo", type=int, default=256)
+    ap.add_argument("--batch-hi", type=int, default=4096)
+    ap.add_argument("--calibrate", action="store_true", help="also run a 1 GiB device copy (counter scaling)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
+                    help="write the traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--pmc-command", default="")
+    ap.add_argument("--stats-summary", nargs=2, metavar=("KERNEL_STATS_CSV", "OUT_TXT"),
+                    help="write a text summary of a rocprofv3 --stats run and exit (command: --pmc-command)")
     args = ap.parse_args()
+    if args.stats_summary:
+        stats_summary(args.stats_summary[0], args.stats_summary[1], args.pmc_command)
+        return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], "k_wt<1,", 1 << 30, args.pmc_summary[2],
+                    args.pmc_command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the product runs on a single MI355X and "
               "multi-GPU row sharding is not built (--gpus must be 1).", file=sys.stderr)
@@ -154,89 +338,73 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
+    if args.workload == "batched":
+        res = run_batched(P, torch, args)
+        print(json.dumps({"metric": "SpGEMM GFLOP/s, batched launch vs per-instance loop", "value": res["batched_gflops"],
+                          "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": res["batched_ms"], "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "batched: %d products, N log-uniform [%d, %d], half 5-point stencils, "
+                                                 "half random 4-32/row" % (args.batch_count, args.batch_lo, args.batch_hi)},
+                          "batched": res}), flush=True)
+        return
+
     log("generating inputs")
-    workloads = make_workloads()
-    if args.workload != "all":
-        workloads = [w for w in workloads if w[0].startswith(args.workload)]
-    dev = []
+    workloads = make_workloads(args.workload)
+    products = []
     for name, A, B in workloads:
         dA = P.DeviceCSR.from_host(A)
         dB = dA if B is A else P.DeviceCSR.from_host(B)
-        dev.append((name, A, B, dA, dB))
+        products.append(Product(P, torch, name, A, B, dA, dB))
+    if args.calibrate:
+        calibrate_copy(torch)
 
     model = None
     train_info = None
-    if args.sizer == "learned" or args.compare:
+    need_model = args.sizer == "learned" or not args.no_compare
+    if need_model:
         log("training the row-size network on the GPU")
         t0 = time.time()
         model, train_info = train_sizer(P, torch)
         train_info["seconds"] = round(time.time() - t0, 2)
 
-    def step(sizer):
-        per = []
-        for name, A, B, dA, dB in dev:
-            got, info, _ = run_product(P, torch, dA, dB, sizer, model)
-            per.append((name, got, info))
-        return per
+    log("timed steps (%s)" % args.sizer)
+    ms, wall_ms, per = time_steps(torch, products, args.sizer, model, args.steps, args.warmup)
 
-    log("warmup")
-    for _ in range(args.warmup):
-        step(args.sizer)
-    torch.cuda.synchronize()
-    log("timed steps")
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    per_step = []
-    torch.cuda.synchronize()
-    ev0.record()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        per_step.append(step(args.sizer))
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1) / args.steps
-
-    flops_step = 0
-    bytes_step = 0
-    tile_ms_step = 0.0
     details = {}
-    for i, (name, A, B, dA, dB) in enumerate(dev):
-        got = per_step[-1][i][1]
-        mults = per_step[-1][i][2]["multiplications"]
-        mb = model_bytes(A, B, got)
-        tms = sum(s[i][2]["tile_ms_total"] for s in per_step) / args.steps
+    flops_step = 0
+    dominant = None
+    for i, p in enumerate(products):
+        got, info = per[-1][i]
+        mults = info["multiplications"]
+        mb = model_bytes(p.A, p.B, got)
+        num_ms = sum(s[i][1]["numeric_ms"] for s in per) / len(per)
+        sym_ms = sum(s[i][1]["symbolic_ms"] for s in per) / len(per)
         flops_step += 2 * mults
-        bytes_step += mb
-        tile_ms_step += tms
-        details[name] = {"nnz_c": got, "multiplications": mults, "model_bytes": mb,
-                         "tile_kernel_ms": round(tms, 4),
-                         "tile_kernel_GBps": round(mb / tms / 1e6, 1),
-                         "tile_kernel_frac_hbm": round(mb / tms / 1e6 / HBM_PEAK_GBS, 4),
-                         "tiers": {k: per_step[-1][i][2][k] for k in ("rows_merge", "rows_hash", "rows_global", "rows_empty")},
-                         "overflow_rows": per_step[-1][i][2]["overflow_rows"]}
+        details[p.name] = {"nnz_c": got, "multiplications": mults, "model_bytes": mb,
+                           "numeric_pass_ms": round(num_ms, 4), "symbolic_pass_ms": round(sym_ms, 4),
+                           "numeric_pass_GBps": round(mb / num_ms / 1e6, 1),
+                           "tiers": {k: info[k] for k in ("rows_merge", "rows_hash", "rows_global", "rows_empty")},
+                           "overflow_rows": info["overflow_rows"]}
+        if dominant is None or num_ms > dominant[1]:
+            dominant = (p.name, num_ms, mb, info)
     gflops = flops_step / (ms * 1e-3) / 1e9
 
-    if args.compare:
+    if not args.no_compare:
         for other in ("exact", "upper_bound", "learned"):
             if other == args.sizer:
                 continue
-            for _ in range(args.warmup):
-                step(other)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            outs = [step(other) for _ in range(args.steps)]
-            e1.record()
-            torch.cuda.synchronize()
-            oms = e0.elapsed_time(e1) / args.steps
-            for i, (name, A, B, dA, dB) in enumerate(dev):
-                tms = sum(s[i][2]["tile_ms_total"] for s in outs) / args.steps
-                details[name]["tile_kernel_ms_" + other] = round(tms, 4)
+            oms, _, oper = time_steps(torch, products, other, model, args.steps, args.warmup)
             details["step_ms_" + other] = round(oms, 4)
+            for i, p in enumerate(products):
+                details[p.name]["numeric_pass_ms_" + other] = round(
+                    sum(s[i][1]["numeric_ms"] for s in oper) / len(oper), 4)
+                details[p.name]["overflow_rows_" + other] = oper[-1][i][1]["overflow_rows"]
+        details["step_ms_" + args.sizer] = round(ms, 4)
 
-    achieved = bytes_step / (tile_ms_step * 1e-3) / 1e9
+    name, dms, dbytes, dinfo = dominant
+    achieved = dbytes / (dms * 1e-3) / 1e9
+    traffic = traffic_from_profile(dbytes) if name.startswith("random16") and args.sizer == "exact" else None
     out = {
         "metric": "SpGEMM GFLOP/s & HBM GB/s vs roofline; learned-sized vs plain two-pass",
         "value": round(gflops, 3),
@@ -250,19 +418,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "5-point Laplacian 2048x2048 squared + random 2^21 x 16/row A*B (FP64 CSR)",
-                   "sizer": args.sizer, "products_per_step": len(dev)},
-        "gbps_model": round(bytes_step / (ms * 1e-3) / 1e9, 1),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
-        "wall_ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "config": {"workload": {"roofline": "5-point Laplacian 2048x2048 squared + random 2^21 x 16/row times an "
+                                            "independent one (FP64 CSR), one full product of each per step",
+                                "stencil": "5-point Laplacian 2048x2048 squared",
+                                "random": "random 2^21 x 16/row times an independent one",
+                                "zipf": "power-law rows Zipf(2) clipped to [1, 4096], N = 2^20, squared",
+                                "st9": "9-point stencil 2048x2048 squared",
+                                "st27": "27-point stencil 160^3 squared"}[args.workload],
+                   "sizer": args.sizer, "products_per_step": len(products)},
+        "roofline": {"bound": "hbm", "kernel": "numeric pass of %s (%s sizer)" % (name, args.sizer),
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": dbytes, "launch_ms": round(dms, 4)},
+        "wall_ms_per_step": round(wall_ms, 3),
         "workloads": details,
     }
     if train_info:
         out["sizer_training"] = train_info
     if not args.no_cpu:
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline([(n, A, B) for n, A, B, _, _ in dev])
+        out["cpu_baseline"] = cpu_baseline([(p.name, p.A, p.B) for p in products])
     print(json.dumps(out), flush=True)
 
 

@@ -215,6 +215,11 @@ static spgemm_status read_counters(spgemm_plan *p, hipStream_t s, int64_t **out)
   return SPGEMM_OK;
 }
 
+// Hashed rows of at most this many entries are staged in LDS by the numeric
+// pass (copied out with the tile's other rows); larger rows are written to C
+// by their own wave directly.
+constexpr int kStageRowMax = 128;
+
 // Sizing of one pass (tiers, capacities, tile costs) plus tile bounds.
 static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   const int tvals = p->tune.table_slots;                   // values table (numeric, one pass)
@@ -226,6 +231,7 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   sp.table_max = mode == kSymbolic ? tkeys : tvals;
   sp.value_table_max = tvals;
   sp.stage = stage;
+  sp.stage_row_max = kStageRowMax;
   sp.merge_lists = p->tune.merge_lists;
   sp.merge_max = std::min(p->tune.merge_max_nnz, stage / 2);
   sp.dense_ratio = p->tune.dense_ratio;
@@ -251,7 +257,7 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   p->scratch_rows = h[kCtrScratchRows];
   p->table_launch = (int)h[kCtrTable];
   // staging: every row of a one-pass tile; merge rows only in the numeric pass
-  p->stage_launch = mode == kOnePass ? stage : (mode == kNumeric && h[kCtrMerge] > 0 ? stage : 0);
+  p->stage_launch = (mode != kSymbolic && h[kCtrStaged] > 0) ? stage : 0;
   p->cur_mode = mode;
   p->info.rows_merge = h[kCtrMerge];
   p->info.rows_hash = h[kCtrHash];
@@ -321,12 +327,15 @@ static spgemm_status run_wave(spgemm_plan *p, int mode, const double *a_val, con
   wp.c_capacity = c_capacity;
   wp.table_slots = p->table_launch;
   wp.stage_slots = p->stage_launch;
+  wp.stage_row_max = kStageRowMax;
   if (mode == kOnePass) {
     HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
     HIPCK(p, launch_fill_i64(ctr(p) + kCtrResident, 0, 2, s));
-    if (grid_cap == 0) grid_cap = grid_memo_get(wave_tile_lds(mode, wp.table_slots, wp.stage_slots), p->tune.merge_lists);
+    if (grid_cap == 0)
+      grid_cap = grid_memo_get(wave_tile_lds(mode, wp.table_slots, wp.stage_slots),
+                               p->info.rows_merge > 0 ? p->tune.merge_lists : 0);
   }
-  HIPCK(p, launch_wave_tiles(wp, mode, p->tune.merge_lists, grid_cap, s));
+  HIPCK(p, launch_wave_tiles(wp, mode, p->tune.merge_lists, p->info.rows_merge > 0, grid_cap, s));
   return SPGEMM_OK;
 }
 
@@ -516,27 +525,31 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
     st = spgemm_model_upload(p->model, dev, stream);
     if (st != SPGEMM_OK) return fail(st);
   }
-  // Row sums (multiplications, longest A row, empty rows) and, for the
-  // learned sizer, the packed feature triple of every row and the learned
-  // capacity; one synchronisation.
-  if (launch_features(op, p->pa.f, p->keys, p->pa.counters, p->pa.partials, learned ? 1 : 0, s) != hipSuccess)
+  // Longest row of A (row pointers only) decides the path.  Every row
+  // merges in registers when no row of A has more stored entries than the
+  // merge tier's lists (and the tier is not switched off); then no per-row
+  // plan arrays are needed.
+  if (launch_row_max(A->row_ptr, A->rows, p->pa.counters, p->pa.partials, s) != hipSuccess)
     return fail(SPGEMM_E_HIP);
-  if (learned) {
-    if (launch_mlp_capacity(dev, p->keys, A->rows, s, p->tune.margin, p->tune.slack, p->pa.partials) != hipSuccess)
-      return fail(SPGEMM_E_HIP);
-    const int32_t dst[1] = {kCtrCapSum};
-    if (launch_sum_partials(p->pa.partials, std::max<int64_t>(1, mlp_predict_blocks(A->rows)), 1, 1, dst, nullptr,
-                            p->pa.counters, s) != hipSuccess)
-      return fail(SPGEMM_E_HIP);
-  }
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return fail(st);
-  // Every row merges in registers when no row of A has more stored entries
-  // than the merge tier's lists (and the tier is not switched off); then no
-  // per-row plan arrays are needed.
   p->merge_only = A->rows > 0 && h[kCtrMaxA] <= p->tune.merge_lists && p->tune.merge_max_nnz > 0;
   if (p->merge_only) {
+    // row sums (multiplications, empty rows) and, for the learned sizer, the
+    // packed feature triple of every row and the learned capacity
+    if (launch_features(op, p->pa.f, p->keys, p->pa.counters, p->pa.partials, learned ? 1 : 0, s) != hipSuccess)
+      return fail(SPGEMM_E_HIP);
+    if (learned) {
+      if (launch_mlp_capacity(dev, p->keys, A->rows, s, p->tune.margin, p->tune.slack, p->pa.partials) != hipSuccess)
+        return fail(SPGEMM_E_HIP);
+      const int32_t dst[1] = {kCtrCapSum};
+      if (launch_sum_partials(p->pa.partials, std::max<int64_t>(1, mlp_predict_blocks(A->rows)), 1, 1, dst, nullptr,
+                              p->pa.counters, s) != hipSuccess)
+        return fail(SPGEMM_E_HIP);
+    }
+    st = read_counters(p, s, &h);
+    if (st != SPGEMM_OK) return fail(st);
     p->info.rows_empty = h[kCtrEmpty];
     p->info.rows_merge = A->rows - h[kCtrEmpty];
     p->info.tiles = (A->rows + 63) / 64;
@@ -544,6 +557,7 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
     p->ntiles = p->info.tiles;
     p->cur_mode = p->first_mode;
   } else {
+    // per-row features (and their sums), the learned prediction, tiers
     if (launch_features(op, p->pa.f, p->keys, p->pa.counters, p->pa.partials, 2, s) != hipSuccess)
       return fail(SPGEMM_E_HIP);
     if (learned) {
@@ -649,13 +663,19 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
   for (int round = 1; !p->merge_only && mode == kOnePass && (h[kCtrError] & kErrResidency) && round <= 4; ++round) {
     const int64_t seen = h[kCtrResidentSeen];
     const int64_t cap = std::max<int64_t>(1, seen > 8 ? seen - seen / 8 : seen / 2);
-    grid_memo_put(wave_tile_lds(kOnePass, p->table_launch, p->stage_launch), p->tune.merge_lists, cap);
+    grid_memo_put(wave_tile_lds(kOnePass, p->table_launch, p->stage_launch),
+                  p->info.rows_merge > 0 ? p->tune.merge_lists : 0, cap);
     p->info.grid_retries = round;
+    p->info.tile_ms_total -= p->info.tile_ms;   // the attempt that stopped early does not count
     HIPCK(p, launch_fill_i64(ctr(p) + kCtrError, 0, 1, s));
     HIPCK(p, launch_fill_i64(ctr(p) + kCtrOverflow, 0, 1, s));
+    timing_begin(p, s, &e);
+    HIPCK(p, e);
     st = run_wave(p, mode, av, bv, c_row_ptr, c_col, c_val, c_capacity, s, cap);
     if (st == SPGEMM_OK)
       st = run_big(p, kNumeric, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+    timing_end(p, s, &e);
+    HIPCK(p, e);
     if (st == SPGEMM_OK) st = read_counters(p, s, &h);
     if (st != SPGEMM_OK) return st;
   }

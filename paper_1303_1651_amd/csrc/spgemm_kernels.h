@@ -39,6 +39,7 @@ enum Counter : int {
   kCtrError = 10,      // bit flags, see kErr*
   kCtrNnz = 11,        // nnz(C) after a one-pass numeric
   kCtrScanTicket = 12,
+  kCtrStaged = 13,     // rows a numeric or one-pass tile stages in LDS
   kCtrMaxA = 15,       // longest row of A
   kCtrUnpacked = 16,   // summed bounds of rows whose feature triple does not pack
   kCtrTable = 17,      // largest wave table (slots) a hashed row uses
@@ -76,6 +77,7 @@ struct SizeParams {
   int table_max;        // largest wave table (slots); 0: no wave hash tier
   int value_table_max;  // kSymbolic: the numeric pass's largest table (scratch sizing)
   int stage;            // LDS staging entries of a wave tile
+  int stage_row_max;    // kNumeric: hashed rows up to this size are staged
   int merge_lists;      // template M of the merge tier
   int merge_max;        // largest capacity the merge tier takes
   float dense_ratio;
@@ -119,7 +121,8 @@ struct WaveTileParams {
   double *c_val;
   int64_t c_capacity;
   int table_slots;          // LDS table of a wave (slots)
-  int stage_slots;          // LDS staging of a wave (entries), >= table_slots
+  int stage_slots;          // LDS staging of a wave (entries)
+  int stage_row_max;        // kNumeric: hashed rows up to this size are staged (larger ones go to C directly)
 };
 
 struct BigParams {
@@ -160,7 +163,9 @@ hipError_t launch_tile_bounds(const int64_t *cost, int64_t rows, int64_t half_po
                               int32_t *tile_row, int64_t *counters, hipStream_t s);
 size_t wave_tile_lds(int mode, int table_slots, int stage_slots);
 // grid_cap > 0 bounds the one-pass grid (else: the occupancy estimate)
-hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, int64_t grid_cap, hipStream_t s);
+// has_merge: some row of the pass takes the merge tier
+hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, int64_t grid_cap,
+                             hipStream_t s);
 hipError_t launch_big_rows(const BigParams &bp, int mode, int grid, hipStream_t s);
 hipError_t launch_sum_partials(const int64_t *partials, int64_t nblocks, int n, int stride, const int32_t *dst,
                                const int32_t *is_max, int64_t *counters, hipStream_t s);

@@ -322,14 +322,14 @@ __device__ __forceinline__ int64_t table_pow2(int64_t x) {
 // The numeric pass stages merge rows only (hashed rows know their place in
 // C and go there directly).
 __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa, SizeParams sp) {
-  __shared__ int64_t s_red[7][kWavesPerBlock];
+  __shared__ int64_t s_red[8][kWavesPerBlock];
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   const bool sym = sp.mode == kSymbolic;
   const int64_t HT = sym ? kWave : sp.stage / 2;
   const int64_t mincost = sym ? 1 : (HT + kWave - 1) / kWave;
   int64_t n_tier[4] = {0, 0, 0, 0};
   int64_t capsum = 0, scratch = 0, tmax = 0;
-  bool big = false;
+  bool big = false, staged = false;
   if (i < op.rows) {
     const int32_t m = pa.f.nnz_a[i];
     const int64_t ub = pa.f.ub[i];
@@ -347,7 +347,10 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
     } else if (m <= sp.merge_lists && c <= sp.merge_max) {
       tier = kTierMerge;
       info = pack_info(kTierMerge, false, 0);
-      if (!sym) cost = max(min(c, HT), mincost);
+      if (!sym) {
+        cost = max(min(c, HT), mincost);
+        staged = true;
+      }
     } else {
       const int64_t span = (int64_t)pa.f.hi[i] - (int64_t)pa.f.lo[i] + 1;
       bool dense = false;
@@ -369,8 +372,12 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
         tier = kTierHash;
         info = pack_info(kTierHash, dense, (uint32_t)T);
         tmax = T;
-        // the numeric pass writes hashed rows straight to C (not staged)
-        if (sp.mode == kOnePass) cost = max(min(c, HT), mincost);
+        // the numeric pass stages small hashed rows and writes larger ones
+        // straight to C
+        if (sp.mode == kOnePass || (sp.mode == kNumeric && c <= sp.stage_row_max)) {
+          cost = max(min(c, HT), mincost);
+          staged = true;
+        }
         // the numeric pass has a smaller (values) table: a row it may send
         // to the workgroup tier gets its device table counted already
         if (sym && (table_pow2(2 * ub) > sp.value_table_max || ub > kSortMax) &&
@@ -399,15 +406,15 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
     if (big) pa.big[base + __popcll(bm & lanemask_lt())] = (int32_t)i;
   }
   const int w = threadIdx.x / kWave;
-  int64_t v[7] = {n_tier[kTierMerge], n_tier[kTierHash], n_tier[kTierEmpty], capsum, scratch > 0 ? 1 : 0,
-                  scratch, tmax};
+  int64_t v[8] = {n_tier[kTierMerge], n_tier[kTierHash], n_tier[kTierEmpty], capsum, scratch > 0 ? 1 : 0,
+                  staged ? 1 : 0, scratch, tmax};
 #pragma unroll
-  for (int j = 0; j < 5; ++j) {
+  for (int j = 0; j < 6; ++j) {
     const int64_t t = wave_sum(v[j]);
     if (lane_id() == 0) s_red[j][w] = t;
   }
 #pragma unroll
-  for (int j = 5; j < 7; ++j) {
+  for (int j = 6; j < 8; ++j) {
     int64_t t = v[j];
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) t = max(t, __shfl_xor(t, d, kWave));
@@ -415,10 +422,10 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
   }
   __syncthreads();
   // one partial per workgroup; k_sum_partials adds them (no hot atomics)
-  if (threadIdx.x < 7) {
+  if (threadIdx.x < 8) {
     const int j = threadIdx.x;
     int64_t t = 0;
-    for (int q = 0; q < kWavesPerBlock; ++q) t = (j >= 5) ? max(t, s_red[j][q]) : t + s_red[j][q];
+    for (int q = 0; q < kWavesPerBlock; ++q) t = (j >= 6) ? max(t, s_red[j][q]) : t + s_red[j][q];
     pa.partials[(int64_t)blockIdx.x * 8 + j] = t;
   }
 }
@@ -426,12 +433,13 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
 hipError_t launch_size_rows(const Operands &op, const PlanArrays &pa, const SizeParams &sp,
                             hipStream_t s) {
   PartialSpec ps{};
-  ps.n = 7;
+  ps.n = 8;
   ps.stride = 8;
-  const int32_t dst[7] = {kCtrMerge, kCtrHash, kCtrEmpty, kCtrCapSum, kCtrScratchRows, kCtrScratch, kCtrTable};
-  for (int j = 0; j < 7; ++j) {
+  const int32_t dst[8] = {kCtrMerge, kCtrHash, kCtrEmpty, kCtrCapSum, kCtrScratchRows, kCtrStaged, kCtrScratch,
+                          kCtrTable};
+  for (int j = 0; j < 8; ++j) {
     ps.dst[j] = dst[j];
-    ps.is_max[j] = (j >= 5);
+    ps.is_max[j] = (j >= 6);
   }
   hipError_t e = launch_fill_i64(pa.counters + kCtrGlobal, 0, 1, s);
   if (e != hipSuccess) return e;
@@ -967,70 +975,113 @@ __device__ __forceinline__ int32_t wave_probe(const WaveTable &tb, int32_t j, in
 // at least kMinLanes (so at most 64 / kMinLanes ordered sub-steps) and at
 // most 64 (longer B rows loop).
 constexpr int kMinLanes = 16;
-constexpr int kWavePrefetch = 4;
-
-// Inserts every product of the row into the wave's table, the whole wave
-// taking 64 / W entries of A per step and W lanes over each B row.  Values:
-// a slot starts at +0.0 when claimed, and the entries of one step add their
-// products in A's stored order (one sub-step per entry), so every slot is
-// accumulated exactly in A's column order, as in the row-major kernel of
-// Section IV-A.  Returns the number of distinct columns (wave-uniform).
+// Steps of A entries loaded ahead: four for the counting pass; two when
+// values come along (fewer registers, more waves resident).
 template <bool VALUES>
-__device__ int32_t wave_insert_row(const Operands &op, int64_t row, int32_t maxb, const WaveTable &tb,
-                                   int64_t *err) {
-  const int lane = threadIdx.x;
-  const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
+constexpr int wave_prefetch() {
+  return VALUES ? 2 : 4;
+}
+
+// log2 of the lanes per A entry for a row whose longest selected B row has
+// maxb entries.
+__device__ __forceinline__ int lanes_log2(int32_t maxb) {
   int lw = __builtin_ctz((unsigned)kMinLanes);
   while ((1 << lw) < maxb && lw < 6) ++lw;
-  const int W = 1 << lw;
-  const int per = kWave >> lw;
-  const int sub = lane >> lw;
-  const int bp = lane & (W - 1);
+  return lw;
+}
+
+// One batch of a row: 64 / W entries of A per step, wave_prefetch() steps.
+// First level: the lane's A entry (column, value) and its B row's bounds.
+template <int PF>
+struct Batch1 {
+  int64_t bs[PF];
+  int32_t bl[PF];
+  double av[PF];
+};
+// Second level: the lane's B entry (column, value) of each step.
+template <int PF>
+struct Batch2 {
+  int32_t jj[PF];
+  double bb[PF];
+};
+
+template <bool VALUES, int PF = wave_prefetch<VALUES>()>
+__device__ __forceinline__ void load_batch1(const Operands &op, int64_t e0, int64_t ae, int lw, Batch1<PF> &b) {
+  const int per = kWave >> lw, sub = (int)threadIdx.x >> lw;
+#pragma unroll
+  for (int u = 0; u < PF; ++u) {
+    const int64_t e = e0 + (int64_t)u * per + sub;
+    b.bs[u] = 0;
+    b.bl[u] = 0;
+    b.av[u] = 0.0;
+    if (e < ae) {
+      const int32_t k = op.a_col[e];
+      if (VALUES) b.av[u] = op.a_val[e];
+      b.bs[u] = op.b_rp[k];
+      b.bl[u] = (int32_t)(op.b_rp[k + 1] - b.bs[u]);
+    }
+  }
+}
+
+template <bool VALUES, int PF = wave_prefetch<VALUES>()>
+__device__ __forceinline__ void load_batch2(const Operands &op, int lw, const Batch1<PF> &b1, Batch2<PF> &b2) {
+  const int bp = (int)threadIdx.x & ((1 << lw) - 1);
+#pragma unroll
+  for (int u = 0; u < PF; ++u) {
+    const bool live = bp < b1.bl[u];
+    b2.jj[u] = live ? op.b_col[b1.bs[u] + bp] : kEmpty;
+    b2.bb[u] = (VALUES && live) ? op.b_val[b1.bs[u] + bp] : 0.0;
+  }
+}
+
+// Inserts the products of one batch into the wave's table.  Values: a slot
+// starts at +0.0 when claimed, and the entries of one step add their
+// products in A's stored order (one sub-step per entry), so every slot is
+// accumulated exactly in A's column order, as in the row-major kernel of
+// Section IV-A.  cnt counts this lane's new columns.
+template <bool VALUES, int PF = wave_prefetch<VALUES>()>
+__device__ __forceinline__ void insert_batch(const Operands &op, int64_t e0, int64_t ae, int lw, const Batch1<PF> &b1,
+                                             const Batch2<PF> &b2, const WaveTable &tb, int32_t &cnt, int64_t *err) {
+  const int lane = threadIdx.x;
+  const int per = kWave >> lw, sub = lane >> lw;
+#pragma unroll
+  for (int u = 0; u < PF; ++u) {
+    if (e0 + (int64_t)u * per >= ae) continue;   // uniform: no entries left
+    int32_t s = -1;
+    if (b2.jj[u] != kEmpty) s = wave_probe<VALUES>(tb, b2.jj[u], cnt, err);
+    if (VALUES) {
+      for (int q = 0; q < per; ++q) {
+        wave_sync();
+        if (sub == q && s >= 0) tb.vals[s] = mul_add_rn(tb.vals[s], b1.av[u], b2.bb[u]);
+      }
+    }
+    if (lw == 6 && b1.bl[u] > kWave) {
+      // one A entry per step here: the rest of its B row, 64 columns at a time
+      for (int32_t f = kWave + lane; f < b1.bl[u]; f += kWave) {
+        const int32_t j = op.b_col[b1.bs[u] + f];
+        const int32_t sl = wave_probe<VALUES>(tb, j, cnt, err);
+        if (VALUES && sl >= 0) tb.vals[sl] = mul_add_rn(tb.vals[sl], b1.av[u], op.b_val[b1.bs[u] + f]);
+      }
+    }
+    wave_sync();
+  }
+}
+
+// Inserts every product of row [as, ae) (longest selected B row maxb) into
+// the wave's table; returns the number of distinct columns (wave-uniform).
+template <bool VALUES>
+__device__ int32_t wave_insert_row(const Operands &op, int64_t as, int64_t ae, int32_t maxb, const WaveTable &tb,
+                                   int64_t *err) {
+  const int lw = lanes_log2(maxb);
+  constexpr int PF = wave_prefetch<VALUES>();
+  const int64_t step = (int64_t)(kWave >> lw) * PF;
   int32_t cnt = 0;
-  for (int64_t e0 = as; e0 < ae; e0 += (int64_t)per * kWavePrefetch) {
-    int64_t bs[kWavePrefetch];
-    int32_t bl[kWavePrefetch], jj[kWavePrefetch];
-    double av[kWavePrefetch], bb[kWavePrefetch];
-#pragma unroll
-    for (int u = 0; u < kWavePrefetch; ++u) {
-      const int64_t e = e0 + (int64_t)u * per + sub;
-      bs[u] = 0;
-      bl[u] = 0;
-      av[u] = 0.0;
-      if (e < ae) {
-        const int32_t k = op.a_col[e];
-        if (VALUES) av[u] = op.a_val[e];
-        bs[u] = op.b_rp[k];
-        bl[u] = (int32_t)(op.b_rp[k + 1] - bs[u]);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kWavePrefetch; ++u) {
-      const bool live = bp < bl[u];
-      jj[u] = live ? op.b_col[bs[u] + bp] : kEmpty;
-      bb[u] = (VALUES && live) ? op.b_val[bs[u] + bp] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kWavePrefetch; ++u) {
-      if (e0 + (int64_t)u * per >= ae) continue;   // uniform: no entries left
-      int32_t s = -1;
-      if (jj[u] != kEmpty) s = wave_probe<VALUES>(tb, jj[u], cnt, err);
-      if (VALUES) {
-        for (int q = 0; q < per; ++q) {
-          wave_sync();
-          if (sub == q && s >= 0) tb.vals[s] = mul_add_rn(tb.vals[s], av[u], bb[u]);
-        }
-      }
-      if (W == kWave && bl[u] > kWave) {
-        // one A entry per step here: the rest of its B row, 64 columns at a time
-        for (int32_t f = kWave + lane; f < bl[u]; f += kWave) {
-          const int32_t j = op.b_col[bs[u] + f];
-          const int32_t sl = wave_probe<VALUES>(tb, j, cnt, err);
-          if (VALUES && sl >= 0) tb.vals[sl] = mul_add_rn(tb.vals[sl], av[u], op.b_val[bs[u] + f]);
-        }
-      }
-      wave_sync();
-    }
+  for (int64_t e0 = as; e0 < ae; e0 += step) {
+    Batch1<PF> b1;
+    Batch2<PF> b2;
+    load_batch1<VALUES>(op, e0, ae, lw, b1);
+    load_batch2<VALUES>(op, lw, b1, b2);
+    insert_batch<VALUES>(op, e0, ae, lw, b1, b2, tb, cnt, err);
   }
   return (int32_t)wave_sum(cnt);
 }
@@ -1190,7 +1241,7 @@ __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots,
   return L;
 }
 
-template <int MODE, int M>
+template <int MODE, int M, bool MERGE>
 __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
   constexpr bool VALUES = (MODE != kSymbolic);
   extern __shared__ __align__(16) unsigned char lds[];
@@ -1246,7 +1297,7 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
 
     // merge rows, one lane each, staged at their reserved capacity
     int32_t sp = 0;
-    if (VALUES) {
+    if (VALUES && MERGE) {
       const int32_t res = tier == kTierMerge ? capr : 0;
       const int32_t inc = wave_inclusive_sum32(res);
       sp = __shfl(inc, kWave - 1, kWave);
@@ -1255,7 +1306,7 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
         n = merge_row<M, true>(op, row, scol + o, sval + o, capr);
         if (n <= capr) soff = o;
       }
-    } else if (tier == kTierMerge) {
+    } else if (MERGE && tier == kTierMerge) {
       n = merge_row<M, false>(op, row, nullptr, nullptr, 0);
     }
     wave_sync();
@@ -1266,20 +1317,20 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
       const int r = __ffsll((unsigned long long)hm) - 1;
       hm &= hm - 1;
       const int64_t hrow = r0 + r;
-      const WaveTable tb = wave_table(tkeys, tvals, p.info[hrow], p.lo[hrow]);
-      const int32_t c = wave_insert_row<VALUES>(op, hrow, p.maxb[hrow], tb, err);
+      const WaveTable tb = wave_table(tkeys, tvals, __shfl(inf, r, kWave), p.lo[hrow]);
+      const int32_t c = wave_insert_row<VALUES>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], tb, err);
       if (!VALUES) {
         wave_clear(tb);
+      } else if (sp + c <= p.stage_slots && (MODE == kOnePass || c <= p.stage_row_max)) {
+        wave_extract(tb, c, buf, scol + sp, sval + sp, c);
+        if (lane == r) soff = sp;
+        sp += c;
       } else if (MODE == kNumeric) {
         // the row's place in C is known: sorted entries go straight there
         const int64_t o = p.c_rp[hrow];
         const int64_t rl = max((int64_t)0, min((int64_t)c, p.c_capacity - o));
         wave_extract(tb, c, buf, p.c_col + o, p.c_val + o, rl);
         if (lane == r) soff = kWritten;
-      } else if (sp + c <= p.stage_slots) {
-        wave_extract(tb, c, buf, scol + sp, sval + sp, c);
-        if (lane == r) soff = sp;
-        sp += c;
       } else {
         wave_clear(tb);
       }
@@ -1344,7 +1395,7 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
       if (lane == 0 && rb)
         atomicAdd((unsigned long long *)&p.counters[kCtrOverflow], (unsigned long long)__popcll(rb));
     }
-    if (redo && tier == kTierMerge) {
+    if (MERGE && redo && tier == kTierMerge) {
       const int64_t o = base + ex;
       const int64_t rl = max((int64_t)0, min(n, p.c_capacity - o));
       merge_row<M, true>(op, row, p.c_col + o, p.c_val + o, rl);
@@ -1355,7 +1406,7 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
       hr &= hr - 1;
       const int64_t hrow = r0 + r;
       const WaveTable tb = wave_table(tkeys, tvals, p.info[hrow], p.lo[hrow]);
-      const int32_t c = wave_insert_row<true>(op, hrow, p.maxb[hrow], tb, err);
+      const int32_t c = wave_insert_row<true>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], tb, err);
       const int64_t o = base + __shfl(ex, r, kWave);
       const int64_t rl = max((int64_t)0, min((int64_t)c, p.c_capacity - o));
       wave_extract(tb, c, buf, p.c_col + o, p.c_val + o, rl);
@@ -1554,9 +1605,9 @@ size_t wave_tile_lds(int mode, int table_slots, int stage_slots) {
   return wave_lds_layout(mode != kSymbolic, table_slots, stage_slots).total;
 }
 
-template <int MODE, int M>
+template <int MODE, int M, bool MERGE>
 static hipError_t launch_wt_mm(const WaveTileParams &wp, size_t lds, int64_t grid_cap, hipStream_t s) {
-  const void *fn = reinterpret_cast<const void *>(&k_wt<MODE, M>);
+  const void *fn = reinterpret_cast<const void *>(&k_wt<MODE, M, MERGE>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -1574,24 +1625,26 @@ static hipError_t launch_wt_mm(const WaveTileParams &wp, size_t lds, int64_t gri
   }
   grid = std::min<int64_t>(grid, 0x7fffffff);
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_wt<MODE, M>), dim3((unsigned)grid), dim3(kWave), lds, s, wp);
+  hipLaunchKernelGGL((k_wt<MODE, M, MERGE>), dim3((unsigned)grid), dim3(kWave), lds, s, wp);
   return hipGetLastError();
 }
 
-template <int M>
+template <int M, bool MERGE>
 static hipError_t launch_wt_m(const WaveTileParams &wp, int mode, size_t lds, int64_t grid_cap, hipStream_t s) {
   switch (mode) {
-    case kSymbolic: return launch_wt_mm<kSymbolic, M>(wp, lds, grid_cap, s);
-    case kNumeric: return launch_wt_mm<kNumeric, M>(wp, lds, grid_cap, s);
-    default: return launch_wt_mm<kOnePass, M>(wp, lds, grid_cap, s);
+    case kSymbolic: return launch_wt_mm<kSymbolic, M, MERGE>(wp, lds, grid_cap, s);
+    case kNumeric: return launch_wt_mm<kNumeric, M, MERGE>(wp, lds, grid_cap, s);
+    default: return launch_wt_mm<kOnePass, M, MERGE>(wp, lds, grid_cap, s);
   }
 }
 
-hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, int64_t grid_cap, hipStream_t s) {
+hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, int64_t grid_cap,
+                             hipStream_t s) {
   const size_t lds = wave_tile_lds(mode, wp.table_slots, wp.stage_slots);
+  if (!has_merge) return launch_wt_m<4, false>(wp, mode, lds, grid_cap, s);
   switch (merge_lists) {
-    case 4: return launch_wt_m<4>(wp, mode, lds, grid_cap, s);
-    case 8: return launch_wt_m<8>(wp, mode, lds, grid_cap, s);
+    case 4: return launch_wt_m<4, true>(wp, mode, lds, grid_cap, s);
+    case 8: return launch_wt_m<8, true>(wp, mode, lds, grid_cap, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -148,3 +148,38 @@ def test_bad_model_still_gives_exact_product():
     got = gpu_product(A, A, "learned", model=model, tuning={"merge_max_nnz": -1})
     assert_bit_exact(got, want)
     assert got[3]["overflow_rows"] > 0
+
+
+def test_trained_network_gains_over_the_bound():
+    # what the network buys: on wide stencils the multiplication count
+    # overestimates nnz(C_i) several times; the learned capacities stay close
+    # to it, so C is allocated and staged at about its real size, while the
+    # product stays exact
+    import paper_1303_1651_amd as P
+    import torch
+    train = [synth.stencil(40, 2, 9), synth.stencil(10, 3, 27), synth.stencil(48), synth.zipf_matrix(1 << 14, 70)]
+    fs, ls = [], []
+    for M in train:
+        f1, f2, f3, n = _features_labels(M, M)
+        fs.append(np.stack([f1, f2, f3]))
+        ls.append(n)
+    F = np.concatenate(fs, axis=1)
+    L = np.concatenate(ls)
+    perm = np.random.default_rng(1).permutation(F.shape[1])
+    d1, d2, d3, dn = _to_dev(F[0][perm], F[1][perm], F[2][perm], L[perm])
+    mu, sd = P.feature_stats(d1, d2, d3)
+    model, _ = P.train_model(synth.mlp_init(12), mu, sd, d1, d2, d3, dn, epochs=40, batch_size=2048, lr=3e-3)
+    for A in (synth.stencil(64, 2, 9), synth.stencil(14, 3, 27)):
+        want = oracle.spgemm(A, A)
+        nnz = int(want[0][-1])
+        dA = P.DeviceCSR.from_host(A)
+        ub_plan = P.Plan(dA, dA, "upper_bound")
+        lr_plan = P.Plan(dA, dA, "learned", model)
+        ub_cap, lr_cap = ub_plan.info["c_capacity_hint"], lr_plan.info["c_capacity_hint"]
+        ub_plan.close()
+        lr_plan.close()
+        assert ub_cap >= 2.5 * nnz
+        assert 0.9 * nnz <= lr_cap <= 1.3 * nnz, (lr_cap, nnz)
+        got = gpu_product(A, A, "learned", model=model)
+        assert_bit_exact(got, want)
+        assert got[3]["overflow_rows"] <= 0.05 * A.rows

@@ -228,3 +228,19 @@ def test_random_2pow21_sampled_blocks():
         # every row has between 16 and 256 entries
         lens = np.diff(got[0])
         assert lens.min() >= 16 and lens.max() <= 256
+
+
+def test_autotuner_picks_a_valid_tuning(tmp_path):
+    import json
+    import paper_1303_1651_amd as P
+    from paper_1303_1651_amd.autotune import autotune
+    A = synth.zipf_matrix(20000, 31)
+    dA = P.DeviceCSR.from_host(A)
+    grid = {"table_slots": [256, 1024], "stage_slots": [512, 1024], "merge_max_nnz": [32, 64]}
+    cache = str(tmp_path / "tune.json")
+    best = autotune(dA, dA, "exact", grid=grid, reps=1, cache=cache)
+    assert set(best) == set(grid)
+    assert json.load(open(cache))
+    # cached on the second call, and the tuned product is still exact
+    assert autotune(dA, dA, "exact", grid=grid, reps=1, cache=cache) == best
+    assert_bit_exact(gpu_product(A, A, "exact", tuning=best), oracle.spgemm(A, A))
