@@ -150,6 +150,8 @@ struct spgemm_plan {
   int table_launch;        // LDS table slots of the wave-tile launch
   int stage_launch;        // LDS staging entries of the wave-tile launch
   int merge_only;      // every row takes the register-merge tier: row-per-thread kernels
+  int merge_m;         // lists of the row-per-thread merge (4, 8 or 16)
+  int merge_stage;     // staged entries per merge wave
   spgemm_info info;
   hipError_t last_err;
   const spgemm_model *model;
@@ -214,6 +216,12 @@ static spgemm_status read_counters(spgemm_plan *p, hipStream_t s, int64_t **out)
   *out = h;
   return SPGEMM_OK;
 }
+
+// The row-per-thread merge path takes matrices whose A rows have at most this
+// many entries; its per-wave staging holds at most kMergeStageMax entries
+// (waves with more output write their rows directly).
+constexpr int kMergeOnlyLists = 16;
+constexpr int64_t kMergeStageMax = 2048;
 
 // Hashed rows of at most this many entries are staged in LDS by the numeric
 // pass (copied out with the tile's other rows); larger rows are written to C
@@ -390,7 +398,7 @@ spgemm_status numeric_enqueue(spgemm_plan *p, void *scratch, size_t scratch_byte
   const int mode = p->first_mode == kSymbolic ? kNumeric : kOnePass;
   if (p->merge_only) {
     if (mode == kOnePass) HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
-    HIPCK(p, launch_wave_merge(operands_of(p, av, bv), mode, p->tune.merge_lists, ctr(p), p->pa.status, nullptr,
+    HIPCK(p, launch_wave_merge(operands_of(p, av, bv), mode, p->merge_m, p->merge_stage, ctr(p), p->pa.status, nullptr,
                                c_row_ptr, c_col, c_val, c_capacity, s));
     return SPGEMM_OK;
   }
@@ -534,7 +542,11 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return fail(st);
-  p->merge_only = A->rows > 0 && h[kCtrMaxA] <= p->tune.merge_lists && p->tune.merge_max_nnz > 0;
+  p->merge_only = A->rows > 0 && h[kCtrMaxA] <= kMergeOnlyLists && p->tune.merge_max_nnz > 0;
+  p->merge_m = h[kCtrMaxA] <= 4 ? 4 : (h[kCtrMaxA] <= 8 ? 8 : 16);
+  // one pass: staging for 64 rows of up to 2 x 16 entries each (8-list rows)
+  // or 2 x 32 (16-list rows); the numeric pass sizes it from the exact counts
+  p->merge_stage = p->merge_m == 16 ? 2048 : 1024;
   if (p->merge_only) {
     // row sums (multiplications, empty rows) and, for the learned sizer, the
     // packed feature triple of every row and the learned capacity
@@ -592,7 +604,7 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
   timing_begin(p, s, &e);
   HIPCK(p, e);
   if (p->merge_only) {
-    HIPCK(p, launch_wave_merge(operands_of(p, nullptr, nullptr), kSymbolic, p->tune.merge_lists, ctr(p),
+    HIPCK(p, launch_wave_merge(operands_of(p, nullptr, nullptr), kSymbolic, p->merge_m, 0, ctr(p),
                                p->pa.status, p->pa.cnt, nullptr, nullptr, nullptr, 0, s));
   } else {
     st = run_wave(p, kSymbolic, nullptr, nullptr, nullptr, nullptr, nullptr, 0, s);
@@ -611,6 +623,14 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
   int64_t nnz = p->A.rows > 0 ? h[kCtrNnz] : 0;
   p->info.c_nnz = nnz;
   *c_nnz = nnz;
+  if (p->merge_only) {
+    // staging of the numeric merge waves: the largest output of 64 rows
+    HIPCK(p, launch_wave_span(c_row_ptr, p->A.rows, ctr(p), p->pa.partials, s));
+    st = read_counters(p, s, &h);
+    if (st != SPGEMM_OK) return st;
+    const int64_t span = std::max<int64_t>(h[kCtrWaveSpan], 64);
+    p->merge_stage = (int)std::min<int64_t>((span + 63) & ~(int64_t)63, kMergeStageMax);
+  }
   // size the numeric pass from the exact counts
   if (!p->merge_only) {
     st = size_pass(p, kNumeric, s);

@@ -46,6 +46,7 @@ enum Counter : int {
   kCtrScratchRows = 18,  // rows that may need a workgroup-tier device table
   kCtrResident = 19,   // one-pass workgroups that have started
   kCtrResidentSeen = 20,  // workgroups found resident together when a one-pass grid was too large
+  kCtrWaveSpan = 21,   // largest output of 64 consecutive rows (merge staging)
   kNumCounters = 32
 };
 enum : int64_t {
@@ -169,9 +170,12 @@ hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists
 hipError_t launch_big_rows(const BigParams &bp, int mode, int grid, hipStream_t s);
 hipError_t launch_sum_partials(const int64_t *partials, int64_t nblocks, int n, int stride, const int32_t *dst,
                                const int32_t *is_max, int64_t *counters, hipStream_t s);
-// Row-per-thread merge kernels for matrices whose rows all take the merge tier.
-hipError_t launch_wave_merge(const Operands &op, int mode, int merge_lists, int64_t *counters, uint64_t *status,
-                             int32_t *cnt_out, int64_t *c_rp, int32_t *c_col, double *c_val, int64_t c_capacity,
-                             hipStream_t s);
+// Row-per-thread merge kernels for matrices whose rows all take the merge
+// tier (merge_lists 4, 8 or 16); `stage` entries of LDS staging per wave.
+hipError_t launch_wave_merge(const Operands &op, int mode, int merge_lists, int stage, int64_t *counters,
+                             uint64_t *status, int32_t *cnt_out, int64_t *c_rp, int32_t *c_col, double *c_val,
+                             int64_t c_capacity, hipStream_t s);
+// counters[kCtrWaveSpan] = max over groups of 64 rows of rp[end] - rp[start]
+hipError_t launch_wave_span(const int64_t *rp, int64_t rows, int64_t *counters, int64_t *partials, hipStream_t s);
 
 }  // namespace spg

@@ -602,10 +602,13 @@ __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, 
                              int64_t lim) {
   const int64_t as = op.a_rp[row];
   const int m = (int)(op.a_rp[row + 1] - as);
-  int32_t h[M];
+  // per list: head (h, v), the entry after it (h2, v2), the next position
+  // to load and how many entries are left to load; the entry after the head
+  // is loaded one consumption ahead, so a list rarely waits on a load
+  int32_t h[M], h2[M];
   int64_t pos[M];
   int32_t rem[M];
-  double a[M], v[M];
+  double a[M], v[M], v2[M];
 #pragma unroll
   for (int l = 0; l < M; ++l) {
     rem[l] = 0;
@@ -623,6 +626,10 @@ __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, 
   for (int l = 0; l < M; ++l) {
     h[l] = rem[l] > 0 ? op.b_col[pos[l]] : kColMax;
     v[l] = (VALUES && rem[l] > 0) ? op.b_val[pos[l]] : 0.0;
+    h2[l] = rem[l] > 1 ? op.b_col[pos[l] + 1] : kColMax;
+    v2[l] = (VALUES && rem[l] > 1) ? op.b_val[pos[l] + 1] : 0.0;
+    pos[l] += 2;
+    rem[l] -= 2;
   }
   int64_t n = 0;
   while (true) {
@@ -635,10 +642,12 @@ __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, 
     for (int l = 0; l < M; ++l) {
       if (h[l] == mn) {
         if (VALUES) acc = mul_add_rn(acc, a[l], v[l]);
+        h[l] = h2[l];
+        if (VALUES) v[l] = v2[l];
+        h2[l] = rem[l] > 0 ? op.b_col[pos[l]] : kColMax;
+        if (VALUES) v2[l] = rem[l] > 0 ? op.b_val[pos[l]] : 0.0;
         ++pos[l];
         --rem[l];
-        h[l] = rem[l] > 0 ? op.b_col[pos[l]] : kColMax;
-        if (VALUES) v[l] = rem[l] > 0 ? op.b_val[pos[l]] : 0.0;
       }
     }
     if (n < lim) {
@@ -1467,7 +1476,14 @@ __global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
 //             merge with values into the staging while predecessors
 //             publish; then resolve the wave's offset and copy out.
 // One-pass tickets are taken per workgroup; its waves are tiles 4t .. 4t+3.
-constexpr int kWaveStage = 1024;   // staged entries per wave (12 KB)
+// Staging of a merge wave: `stage` entries per wave, columns of the
+// block's four waves first, then their values (16-byte aligned).
+__host__ __device__ inline size_t wave_merge_vals_offset(int stage) {
+  return (((size_t)kWavesPerBlock * stage * 4) + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t wave_merge_lds(int stage) {
+  return wave_merge_vals_offset(stage) + (size_t)kWavesPerBlock * stage * 8;
+}
 
 __device__ __forceinline__ void status_publish(uint64_t *status, int64_t tile, int64_t agg) {
   if (lane_id() == 0) status_store(status + tile, (tile == 0 ? kFlagPre : kFlagAgg) | (uint64_t)agg);
@@ -1507,12 +1523,14 @@ __device__ inline int64_t lookback_resolve(uint64_t *status, int64_t tile, int64
 template <int M, int MODE>
 __global__ void __launch_bounds__(kBlock) k_wave_merge(Operands op, int64_t *counters, uint64_t *status,
                                                        int32_t *cnt_out, int64_t *c_rp, int32_t *c_col,
-                                                       double *c_val, int64_t c_capacity) {
-  __shared__ int32_t sc[kWavesPerBlock][kWaveStage];
-  __shared__ double sv[kWavesPerBlock][kWaveStage];
+                                                       double *c_val, int64_t c_capacity, int stage) {
+  extern __shared__ __align__(16) unsigned char wm_lds[];
   __shared__ int64_t s_ticket;
   const int l = lane_id();
   const int w = threadIdx.x / kWave;
+  // this wave's staging: stage columns, then stage values
+  int32_t *scw = reinterpret_cast<int32_t *>(wm_lds) + (size_t)w * stage;
+  double *svw = reinterpret_cast<double *>(wm_lds + wave_merge_vals_offset(stage)) + (size_t)w * stage;
   int64_t wt;
   if (MODE == kOnePass) {
     if (threadIdx.x == 0)
@@ -1545,9 +1563,9 @@ __global__ void __launch_bounds__(kBlock) k_wave_merge(Operands op, int64_t *cou
     o = inc - n;
     status_publish(status, wt, tot);
   }
-  const bool staged = tot <= kWaveStage;
+  const bool staged = tot <= stage;
   if (staged && valid) {
-    const int64_t got = merge_row<M, true>(op, row, &sc[w][o], &sv[w][o], n);
+    const int64_t got = merge_row<M, true>(op, row, scw + o, svw + o, n);
     if (MODE == kNumeric && got != n)
       atomicOr((unsigned long long *)&counters[kCtrError], (unsigned long long)kErrInconsistent);
   }
@@ -1566,8 +1584,8 @@ __global__ void __launch_bounds__(kBlock) k_wave_merge(Operands op, int64_t *cou
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   if (staged) {
     for (int64_t q = l; q < lim; q += kWave) {
-      c_col[base + q] = sc[w][q];
-      c_val[base + q] = sv[w][q];
+      c_col[base + q] = scw[q];
+      c_val[base + q] = svw[q];
     }
   } else if (valid) {
     // the wave's output does not fit the staging: rows write their own entries
@@ -1578,27 +1596,75 @@ __global__ void __launch_bounds__(kBlock) k_wave_merge(Operands op, int64_t *cou
   }
 }
 
-hipError_t launch_wave_merge(const Operands &op, int mode, int merge_lists, int64_t *counters, uint64_t *status,
-                             int32_t *cnt_out, int64_t *c_rp, int32_t *c_col, double *c_val, int64_t c_capacity,
-                             hipStream_t s) {
+template <int M, int MODE>
+static hipError_t launch_wave_merge_mm(const Operands &op, int64_t blocks, int stage, int64_t *counters,
+                                       uint64_t *status, int32_t *cnt_out, int64_t *c_rp, int32_t *c_col,
+                                       double *c_val, int64_t c_capacity, hipStream_t s) {
+  const size_t lds = MODE == kSymbolic ? 0 : wave_merge_lds(stage);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wave_merge<M, MODE>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_wave_merge<M, MODE>), dim3((unsigned)blocks), dim3(kBlock), lds, s, op, counters, status,
+                     cnt_out, c_rp, c_col, c_val, c_capacity, stage);
+  return hipGetLastError();
+}
+
+template <int M>
+static hipError_t launch_wave_merge_m(const Operands &op, int mode, int64_t blocks, int stage, int64_t *counters,
+                                      uint64_t *status, int32_t *cnt_out, int64_t *c_rp, int32_t *c_col,
+                                      double *c_val, int64_t c_capacity, hipStream_t s) {
+  if (mode == kSymbolic)
+    return launch_wave_merge_mm<M, kSymbolic>(op, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val,
+                                              c_capacity, s);
+  if (mode == kNumeric)
+    return launch_wave_merge_mm<M, kNumeric>(op, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val,
+                                             c_capacity, s);
+  return launch_wave_merge_mm<M, kOnePass>(op, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val,
+                                           c_capacity, s);
+}
+
+hipError_t launch_wave_merge(const Operands &op, int mode, int merge_lists, int stage, int64_t *counters,
+                             uint64_t *status, int32_t *cnt_out, int64_t *c_rp, int32_t *c_col, double *c_val,
+                             int64_t c_capacity, hipStream_t s) {
   if (op.rows <= 0) return hipSuccess;
   const int64_t blocks = (op.rows + kBlock - 1) / kBlock;
-#define SPG_WM(MM, MD)                                                                                        \
-  hipLaunchKernelGGL((k_wave_merge<MM, MD>), dim3((unsigned)blocks), dim3(kBlock), 0, s, op, counters, status, \
-                     cnt_out, c_rp, c_col, c_val, c_capacity)
-  if (merge_lists == 4) {
-    if (mode == kSymbolic) SPG_WM(4, kSymbolic);
-    else if (mode == kNumeric) SPG_WM(4, kNumeric);
-    else SPG_WM(4, kOnePass);
-  } else if (merge_lists == 8) {
-    if (mode == kSymbolic) SPG_WM(8, kSymbolic);
-    else if (mode == kNumeric) SPG_WM(8, kNumeric);
-    else SPG_WM(8, kOnePass);
-  } else {
-    return hipErrorInvalidValue;
+  switch (merge_lists) {
+    case 4: return launch_wave_merge_m<4>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
+    case 8: return launch_wave_merge_m<8>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
+    case 16: return launch_wave_merge_m<16>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
+    default: return hipErrorInvalidValue;
   }
-#undef SPG_WM
-  return hipGetLastError();
+}
+
+// Largest output of one merge wave (64 consecutive rows) from the row
+// pointers of C: sizes the numeric pass's staging.
+__global__ void __launch_bounds__(kBlock) k_wave_span(const int64_t *rp, int64_t rows, int64_t *partials) {
+  int64_t m = 0;
+  const int64_t waves = (rows + kWave - 1) / kWave;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < waves; i += (int64_t)gridDim.x * kBlock)
+    m = max(m, rp[min((i + 1) * kWave, rows)] - rp[i * kWave]);
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) m = max(m, __shfl_xor(m, d, kWave));
+  __shared__ int64_t red[kWavesPerBlock];
+  if (lane_id() == 0) red[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int j = 0; j < kWavesPerBlock; ++j) t = max(t, red[j]);
+    partials[blockIdx.x] = t;
+  }
+}
+
+hipError_t launch_wave_span(const int64_t *rp, int64_t rows, int64_t *counters, int64_t *partials, hipStream_t s) {
+  if (rows <= 0) return launch_fill_i64(counters + kCtrWaveSpan, 0, 1, s);
+  const int64_t waves = (rows + kWave - 1) / kWave;
+  const int64_t blocks = std::min<int64_t>(1024, (waves + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_wave_span, dim3((unsigned)blocks), dim3(kBlock), 0, s, rp, rows, partials);
+  const int32_t dst[1] = {kCtrWaveSpan};
+  const int32_t mx[1] = {1};
+  return launch_sum_partials(partials, blocks, 1, 1, dst, mx, counters, s);
 }
 
 size_t wave_tile_lds(int mode, int table_slots, int stage_slots) {
