@@ -221,6 +221,7 @@ static spgemm_status read_counters(spgemm_plan *p, hipStream_t s, int64_t **out)
 // many entries; its per-wave staging holds at most kMergeStageMax entries
 // (waves with more output write their rows directly).
 constexpr int kMergeOnlyLists = 16;
+constexpr double kMergeOnlyRowEst = 128.0;
 constexpr int64_t kMergeStageMax = 2048;
 
 // Hashed rows of at most this many entries are staged in LDS by the numeric
@@ -542,7 +543,13 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return fail(st);
-  p->merge_only = A->rows > 0 && h[kCtrMaxA] <= kMergeOnlyLists && p->tune.merge_max_nnz > 0;
+  // The merge pays per output entry for every list: it takes rows with
+  // few entries of A and short outputs (estimated from the mean row lengths
+  // of A and B).
+  const double est_row = (A->rows > 0 ? (double)A->nnz / (double)A->rows : 0.0) *
+                         (B->rows > 0 ? (double)B->nnz / (double)B->rows : 0.0);
+  p->merge_only = A->rows > 0 && h[kCtrMaxA] <= kMergeOnlyLists && p->tune.merge_max_nnz > 0 &&
+                  (h[kCtrMaxA] <= p->tune.merge_lists || est_row <= kMergeOnlyRowEst);
   p->merge_m = h[kCtrMaxA] <= 4 ? 4 : (h[kCtrMaxA] <= 8 ? 8 : 16);
   // one pass: staging for 64 rows of up to 2 x 16 entries each (8-list rows)
   // or 2 x 32 (16-list rows); the numeric pass sizes it from the exact counts

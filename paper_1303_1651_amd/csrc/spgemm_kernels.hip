@@ -597,14 +597,15 @@ __device__ __forceinline__ RowHash make_hash(int32_t lo, int32_t hi, int64_t slo
 // carrying it in list order, i.e. in A's column order.  Output comes out
 // sorted and every entry is accumulated exactly like the dense temporary of
 // the row-major kernel.  Writes min(count, lim) entries; returns the count.
-template <int M, bool VALUES>
+template <int M, bool VALUES, bool DBUF = true>
 __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, double *out_val,
                              int64_t lim) {
   const int64_t as = op.a_rp[row];
   const int m = (int)(op.a_rp[row + 1] - as);
-  // per list: head (h, v), the entry after it (h2, v2), the next position
-  // to load and how many entries are left to load; the entry after the head
-  // is loaded one consumption ahead, so a list rarely waits on a load
+  // per list: head (h, v), with DBUF the entry after it (h2, v2), the next
+  // position to load and how many entries are left to load; with DBUF the
+  // entry after the head is loaded one consumption ahead, so a list rarely
+  // waits on a load (more registers: the tile kernel merges without it)
   int32_t h[M], h2[M];
   int64_t pos[M];
   int32_t rem[M];
@@ -626,10 +627,15 @@ __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, 
   for (int l = 0; l < M; ++l) {
     h[l] = rem[l] > 0 ? op.b_col[pos[l]] : kColMax;
     v[l] = (VALUES && rem[l] > 0) ? op.b_val[pos[l]] : 0.0;
-    h2[l] = rem[l] > 1 ? op.b_col[pos[l] + 1] : kColMax;
-    v2[l] = (VALUES && rem[l] > 1) ? op.b_val[pos[l] + 1] : 0.0;
-    pos[l] += 2;
-    rem[l] -= 2;
+    if (DBUF) {
+      h2[l] = rem[l] > 1 ? op.b_col[pos[l] + 1] : kColMax;
+      v2[l] = (VALUES && rem[l] > 1) ? op.b_val[pos[l] + 1] : 0.0;
+      pos[l] += 2;
+      rem[l] -= 2;
+    } else {
+      pos[l] += 1;
+      rem[l] -= 1;
+    }
   }
   int64_t n = 0;
   while (true) {
@@ -642,10 +648,15 @@ __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, 
     for (int l = 0; l < M; ++l) {
       if (h[l] == mn) {
         if (VALUES) acc = mul_add_rn(acc, a[l], v[l]);
-        h[l] = h2[l];
-        if (VALUES) v[l] = v2[l];
-        h2[l] = rem[l] > 0 ? op.b_col[pos[l]] : kColMax;
-        if (VALUES) v2[l] = rem[l] > 0 ? op.b_val[pos[l]] : 0.0;
+        if (DBUF) {
+          h[l] = h2[l];
+          if (VALUES) v[l] = v2[l];
+          h2[l] = rem[l] > 0 ? op.b_col[pos[l]] : kColMax;
+          if (VALUES) v2[l] = rem[l] > 0 ? op.b_val[pos[l]] : 0.0;
+        } else {
+          h[l] = rem[l] > 0 ? op.b_col[pos[l]] : kColMax;
+          if (VALUES) v[l] = rem[l] > 0 ? op.b_val[pos[l]] : 0.0;
+        }
         ++pos[l];
         --rem[l];
       }
@@ -1312,11 +1323,11 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
       sp = __shfl(inc, kWave - 1, kWave);
       if (tier == kTierMerge) {
         const int32_t o = inc - res;
-        n = merge_row<M, true>(op, row, scol + o, sval + o, capr);
+        n = merge_row<M, true, false>(op, row, scol + o, sval + o, capr);
         if (n <= capr) soff = o;
       }
     } else if (MERGE && tier == kTierMerge) {
-      n = merge_row<M, false>(op, row, nullptr, nullptr, 0);
+      n = merge_row<M, false, false>(op, row, nullptr, nullptr, 0);
     }
     wave_sync();
 
@@ -1407,7 +1418,7 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
     if (MERGE && redo && tier == kTierMerge) {
       const int64_t o = base + ex;
       const int64_t rl = max((int64_t)0, min(n, p.c_capacity - o));
-      merge_row<M, true>(op, row, p.c_col + o, p.c_val + o, rl);
+      merge_row<M, true, false>(op, row, p.c_col + o, p.c_val + o, rl);
     }
     uint64_t hr = ballot(redo && tier == kTierHash);
     while (hr) {
