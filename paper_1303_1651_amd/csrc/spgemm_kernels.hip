@@ -1087,21 +1087,76 @@ __device__ __forceinline__ void insert_batch(const Operands &op, int64_t e0, int
   }
 }
 
+// The entries of a row's A part staged in the wave's LDS, 64 at a time: the
+// start and length of the B row each selects, and its A value.
+struct RowEntries {
+  int64_t *bs;
+  int32_t *bl;
+  double *av;
+};
+
+template <bool VALUES, int PF>
+__device__ __forceinline__ void entries_batch1(const RowEntries &re, int e0, int gn, int lw, Batch1<PF> &b) {
+  const int per = kWave >> lw, sub = (int)threadIdx.x >> lw;
+#pragma unroll
+  for (int u = 0; u < PF; ++u) {
+    const int e = e0 + u * per + sub;
+    b.bs[u] = 0;
+    b.bl[u] = 0;
+    b.av[u] = 0.0;
+    if (e < gn) {
+      b.bs[u] = re.bs[e];
+      b.bl[u] = re.bl[e];
+      if (VALUES) b.av[u] = re.av[e];
+    }
+  }
+}
+
 // Inserts every product of row [as, ae) (longest selected B row maxb) into
 // the wave's table; returns the number of distinct columns (wave-uniform).
+// The row's A entries and their B row bounds are loaded once (one per lane)
+// into LDS; the B entries of the next batch are requested before the
+// current batch is inserted.
 template <bool VALUES>
 __device__ int32_t wave_insert_row(const Operands &op, int64_t as, int64_t ae, int32_t maxb, const WaveTable &tb,
-                                   int64_t *err) {
+                                   const RowEntries &re, int64_t *err) {
+  const int lane = threadIdx.x;
   const int lw = lanes_log2(maxb);
   constexpr int PF = wave_prefetch<VALUES>();
-  const int64_t step = (int64_t)(kWave >> lw) * PF;
+  const int step = (kWave >> lw) * PF;
   int32_t cnt = 0;
-  for (int64_t e0 = as; e0 < ae; e0 += step) {
-    Batch1<PF> b1;
-    Batch2<PF> b2;
-    load_batch1<VALUES>(op, e0, ae, lw, b1);
-    load_batch2<VALUES>(op, lw, b1, b2);
-    insert_batch<VALUES>(op, e0, ae, lw, b1, b2, tb, cnt, err);
+  for (int64_t g0 = as; g0 < ae; g0 += kWave) {
+    const int gn = (int)min((int64_t)kWave, ae - g0);
+    if (lane < gn) {
+      const int32_t k = op.a_col[g0 + lane];
+      const int64_t bs = op.b_rp[k];
+      re.bs[lane] = bs;
+      re.bl[lane] = (int32_t)(op.b_rp[k + 1] - bs);
+      if (VALUES) re.av[lane] = op.a_val[g0 + lane];
+    }
+    wave_sync();
+    Batch2<PF> c2, n2;
+    {
+      Batch1<PF> b1;
+      entries_batch1<VALUES, PF>(re, 0, gn, lw, b1);
+      load_batch2<VALUES, PF>(op, lw, b1, c2);
+    }
+    for (int e0 = 0; e0 < gn; e0 += step) {
+      const bool more = e0 + step < gn;
+      if (more) {
+        Batch1<PF> b1;
+        entries_batch1<VALUES, PF>(re, e0 + step, gn, lw, b1);
+        load_batch2<VALUES, PF>(op, lw, b1, n2);
+      }
+      {
+        // the A values and B row bounds again from LDS (not held in registers)
+        Batch1<PF> b1;
+        entries_batch1<VALUES, PF>(re, e0, gn, lw, b1);
+        insert_batch<VALUES, PF>(op, e0, gn, lw, b1, c2, tb, cnt, err);
+      }
+      if (more) c2 = n2;
+    }
+    wave_sync();
   }
   return (int32_t)wave_sum(cnt);
 }
@@ -1243,12 +1298,14 @@ constexpr int32_t kWritten = -2;     // row written to C directly
 // LDS of a wave tile: table keys, table values, the compaction buffer of a
 // hashed row (kSortMax keys at most), stage columns, stage values.
 struct WaveLds {
-  size_t vals, buf, scol, sval, total;
+  size_t ent, vals, buf, scol, sval, total;
 };
 __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots, int stage_slots) {
   auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
   WaveLds L;
-  L.vals = a16((size_t)table_slots * 4);
+  // row entries (64 x (int64 + int32 + double)) first, then the table
+  L.ent = (size_t)kWave * 20;
+  L.vals = L.ent + a16((size_t)table_slots * 4);
   if (!values) {
     L.buf = L.scol = L.sval = L.total = L.vals;
     return L;
@@ -1269,7 +1326,9 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
   const Operands &op = p.op;
   int64_t *err = p.counters + kCtrError;
   const WaveLds L = wave_lds_layout(VALUES, p.table_slots, p.stage_slots);
-  int32_t *tkeys = reinterpret_cast<int32_t *>(lds);
+  const RowEntries re{reinterpret_cast<int64_t *>(lds), reinterpret_cast<int32_t *>(lds + kWave * 8),
+                      reinterpret_cast<double *>(lds + kWave * 12)};
+  int32_t *tkeys = reinterpret_cast<int32_t *>(lds + L.ent);
   double *tvals = reinterpret_cast<double *>(lds + L.vals);
   int32_t *buf = reinterpret_cast<int32_t *>(lds + L.buf);
   int32_t *scol = reinterpret_cast<int32_t *>(lds + L.scol);
@@ -1338,7 +1397,7 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
       hm &= hm - 1;
       const int64_t hrow = r0 + r;
       const WaveTable tb = wave_table(tkeys, tvals, __shfl(inf, r, kWave), p.lo[hrow]);
-      const int32_t c = wave_insert_row<VALUES>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], tb, err);
+      const int32_t c = wave_insert_row<VALUES>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], tb, re, err);
       if (!VALUES) {
         wave_clear(tb);
       } else if (sp + c <= p.stage_slots && (MODE == kOnePass || c <= p.stage_row_max)) {
@@ -1426,7 +1485,7 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
       hr &= hr - 1;
       const int64_t hrow = r0 + r;
       const WaveTable tb = wave_table(tkeys, tvals, p.info[hrow], p.lo[hrow]);
-      const int32_t c = wave_insert_row<true>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], tb, err);
+      const int32_t c = wave_insert_row<true>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], tb, re, err);
       const int64_t o = base + __shfl(ex, r, kWave);
       const int64_t rl = max((int64_t)0, min((int64_t)c, p.c_capacity - o));
       wave_extract(tb, c, buf, p.c_col + o, p.c_val + o, rl);
