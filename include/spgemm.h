@@ -94,7 +94,9 @@ typedef struct spgemm_model spgemm_model;   /* learned row-size network (host ob
 /* Launch and tier parameters.  Zero fields take the library defaults; the
  * autotuner fills them for a workload family.  table_slots = -1 turns the
  * wave hash tier off (every row that is not merged goes to the workgroup
- * tier); merge_max_nnz = -1 turns the register-merge tier off. */
+ * tier); merge_max_nnz = -1 turns the register-merge tier off; spill_ratio
+ * = -1 sends every row that a learned one pass has no room for to the exact
+ * path. */
 typedef struct spgemm_tuning {
     int32_t table_slots;     /* largest LDS hash table of a wave: 256..4096, power of two   */
     int32_t stage_slots;     /* LDS staging of a wave tile (entries): 256..8192, with
@@ -105,6 +107,8 @@ typedef struct spgemm_tuning {
     float margin;            /* learned sizing: capacity = pred * (1 + margin) + slack     */
     int32_t slack;
     int32_t blocks_per_cu;   /* workgroups per compute unit of the workgroup-tier kernel   */
+    float spill_ratio;       /* learned one pass: spill arena = ratio * summed capacities
+                                (at least 4096 entries), 0 < ratio <= 4; -1: no arena      */
 } spgemm_tuning;
 
 typedef struct spgemm_options {
@@ -122,14 +126,16 @@ typedef struct spgemm_info {
     int64_t c_nnz;             /* exact nnz(C) once known (after symbolic or numeric), else -1 */
     size_t scratch_bytes;      /* scratch the numeric (and symbolic) call needs            */
     int64_t rows_merge, rows_hash, rows_global, rows_empty;  /* tier histogram          */
-    int64_t overflow_rows;     /* one pass: rows whose output did not fit the wave's staging
-                                  (capacity too small) and were computed again            */
+    int64_t overflow_rows;     /* one pass: rows computed again with their exact size
+                                  (their wave tile had no room for them, the tile's rows
+                                  sharing the sum of their capacities, and the spill arena
+                                  was full)                                                */
+    int64_t spilled_rows;      /* one pass: rows placed in the spill arena (a quarter of
+                                  the summed capacities, LEARNED only) instead             */
     int64_t tiles;             /* wave tiles of the current pass                           */
     double tile_ms;            /* SPGEMM_OPT_TIMING: duration of the last pass's row kernels
                                   (wave tiles and workgroup-tier rows, one event pair)      */
     double tile_ms_total;      /* SPGEMM_OPT_TIMING: sum over the plan's passes            */
-    int64_t grid_retries;      /* one pass: times the persistent grid was found not resident
-                                  as a whole and the wave tiles ran again with a smaller one */
 } spgemm_info;
 
 typedef struct spgemm_plan spgemm_plan;

@@ -44,7 +44,8 @@ class spgemm_csr(ctypes.Structure):
 class spgemm_tuning(ctypes.Structure):
     _fields_ = [("table_slots", I32), ("stage_slots", I32),
                 ("merge_max_nnz", I32), ("merge_lists", I32), ("dense_ratio", F32),
-                ("margin", F32), ("slack", I32), ("blocks_per_cu", I32)]
+                ("margin", F32), ("slack", I32), ("blocks_per_cu", I32),
+                ("spill_ratio", F32)]
 
 
 class spgemm_options(ctypes.Structure):
@@ -54,8 +55,9 @@ class spgemm_options(ctypes.Structure):
 class spgemm_info(ctypes.Structure):
     _fields_ = [("multiplications", I64), ("c_capacity_hint", I64), ("c_nnz", I64),
                 ("scratch_bytes", SZ), ("rows_merge", I64), ("rows_hash", I64),
-                ("rows_global", I64), ("rows_empty", I64), ("overflow_rows", I64), ("tiles", I64),
-                ("tile_ms", ctypes.c_double), ("tile_ms_total", ctypes.c_double), ("grid_retries", I64)]
+                ("rows_global", I64), ("rows_empty", I64), ("overflow_rows", I64), ("spilled_rows", I64),
+                ("tiles", I64),
+                ("tile_ms", ctypes.c_double), ("tile_ms_total", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -46,7 +46,7 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace carve-up: every array 256-byte aligned.
 struct Layout {
-  size_t counters, model, partials, keys, nnz_a, ub, maxb, lo, hi, pred, cnt, info, cap, cost, tile_row, status, scan_status, big, total;
+  size_t counters, model, partials, keys, nnz_a, ub, maxb, lo, hi, pred, cnt, info, cap, cost, tile_row, status, scan_status, big, ovf, pad_rp, pad_src, total;
 };
 
 Layout layout_for(int64_t rows) {
@@ -78,6 +78,9 @@ Layout layout_for(int64_t rows) {
   L.status = take(8 * tiles_max);
   L.scan_status = take(8 * scan_tiles);
   L.big = take(4 * R);
+  L.ovf = take(4 * R);
+  L.pad_rp = take(8 * (R + 1));
+  L.pad_src = take(8 * R);
   L.total = o;
   return L;
 }
@@ -94,6 +97,7 @@ spgemm_tuning default_tuning(const spgemm_csr *A, const spgemm_csr *B) {
   t.margin = 0.05f;
   t.slack = 2;
   t.blocks_per_cu = 4;
+  t.spill_ratio = 0.25f;
   return t;
 }
 
@@ -107,6 +111,7 @@ static void merge_tuning(spgemm_tuning *t, const spgemm_tuning *u) {
   if (u->margin > 0) t->margin = u->margin;
   if (u->slack) t->slack = u->slack;
   if (u->blocks_per_cu) t->blocks_per_cu = u->blocks_per_cu;
+  if (u->spill_ratio) t->spill_ratio = u->spill_ratio < 0 ? 0.0f : u->spill_ratio;
 }
 
 static bool tuning_ok(const spgemm_tuning &t) {
@@ -115,7 +120,7 @@ static bool tuning_ok(const spgemm_tuning &t) {
   return t_ok && t.stage_slots >= 256 && t.stage_slots <= 8192 &&
          12 * ((int64_t)t.table_slots + t.stage_slots) <= 147456 && (t.merge_lists == 4 || t.merge_lists == 8) &&
          t.merge_max_nnz >= 0 && t.dense_ratio >= 0 && t.margin >= 0 && t.slack >= 0 && t.blocks_per_cu >= 1 &&
-         t.blocks_per_cu <= 16;
+         t.blocks_per_cu <= 16 && t.spill_ratio >= 0 && t.spill_ratio <= 4;
 }
 
 spgemm_status check_csr(const spgemm_csr *M, bool need_val) {
@@ -147,6 +152,8 @@ struct spgemm_plan {
   int64_t scratch_slots;   // per workgroup, current sizing
   int64_t scratch_slots_plan;
   int64_t scratch_rows;    // rows that may need a workgroup-tier table (plan sizing)
+  int64_t pad_total;       // one pass: entries of the padded buffer (sum of capacities)
+  int64_t spill_cap;       // one pass, learned: entries of the spill arena after it
   int table_launch;        // LDS table slots of the wave-tile launch
   int stage_launch;        // LDS staging entries of the wave-tile launch
   int merge_only;      // every row takes the register-merge tier: row-per-thread kernels
@@ -194,7 +201,6 @@ static spgemm_status lookback_failed(spgemm_plan *p) {
 // count that differs from the symbolic one, a look-back that gave up).
 static spgemm_status device_errors(spgemm_plan *p, const int64_t *h) {
   if (h[kCtrError] & kErrScratch) return SPGEMM_E_WORKSPACE;
-  if (h[kCtrError] & kErrResidency) return lookback_failed(p);
   if (h[kCtrError] & kErrLookback) return lookback_failed(p);
   if (h[kCtrError] & kErrInconsistent) return SPGEMM_E_STATE;
   return SPGEMM_OK;
@@ -228,6 +234,7 @@ constexpr int64_t kMergeStageMax = 2048;
 // pass (copied out with the tile's other rows); larger rows are written to C
 // by their own wave directly.
 constexpr int kStageRowMax = 128;
+constexpr int64_t kSpillMin = 4096;   // smallest spill arena (entries)
 
 // Sizing of one pass (tiers, capacities, tile costs) plus tile bounds.
 static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
@@ -287,36 +294,10 @@ static void timing_end(spgemm_plan *p, hipStream_t s, hipError_t *e) {
   }
 }
 
-// Wave tiles of one pass (the caller has sized the pass).
-// Resident one-pass grid found by measurement, per LDS size (the occupancy
-// estimate can exceed what the hardware keeps resident together).
-struct GridMemo {
-  size_t lds;
-  int merge_lists;
-  int64_t grid;
-};
-static std::mutex g_grid_mu;
-static std::vector<GridMemo> g_grid_memo;
-
-static int64_t grid_memo_get(size_t lds, int merge_lists) {
-  std::lock_guard<std::mutex> lk(g_grid_mu);
-  for (const GridMemo &m : g_grid_memo)
-    if (m.lds == lds && m.merge_lists == merge_lists) return m.grid;
-  return 0;
-}
-
-static void grid_memo_put(size_t lds, int merge_lists, int64_t grid) {
-  std::lock_guard<std::mutex> lk(g_grid_mu);
-  for (GridMemo &m : g_grid_memo)
-    if (m.lds == lds && m.merge_lists == merge_lists) {
-      m.grid = grid;
-      return;
-    }
-  g_grid_memo.push_back({lds, merge_lists, grid});
-}
-
-static spgemm_status run_wave(spgemm_plan *p, int mode, const double *a_val, const double *b_val, int64_t *c_rp,
-                              int32_t *c_col, double *c_val, int64_t c_capacity, hipStream_t s, int64_t grid_cap = 0) {
+// Wave tiles of one pass (the caller has sized the pass).  kOnePass: c_rp,
+// c_col, c_val are the padded offsets and buffer.
+static spgemm_status run_wave(spgemm_plan *p, int mode, const double *a_val, const double *b_val,
+                              const int64_t *c_rp, int32_t *c_col, double *c_val, int64_t c_capacity, hipStream_t s) {
   if (p->ntiles == 0) return SPGEMM_OK;
   WaveTileParams wp{};
   wp.op = operands_of(p, a_val, b_val);
@@ -325,11 +306,13 @@ static spgemm_status run_wave(spgemm_plan *p, int mode, const double *a_val, con
   wp.maxb = p->pa.f.maxb;
   wp.lo = p->pa.f.lo;
   wp.tile_row = mode == kSymbolic ? nullptr : p->pa.tile_row;
-  wp.big_cnt = p->pa.cnt;
   wp.ntiles = p->ntiles;
   wp.counters = ctr(p);
-  wp.status = p->pa.status;
   wp.cnt_out = p->pa.cnt;
+  wp.ovf_list = p->pa.ovf;
+  wp.pad_src = p->pa.pad_src;
+  wp.spill_base = p->pad_total;
+  wp.spill_cap = mode == kOnePass ? p->spill_cap : 0;
   wp.c_rp = c_rp;
   wp.c_col = c_col;
   wp.c_val = c_val;
@@ -337,28 +320,36 @@ static spgemm_status run_wave(spgemm_plan *p, int mode, const double *a_val, con
   wp.table_slots = p->table_launch;
   wp.stage_slots = p->stage_launch;
   wp.stage_row_max = kStageRowMax;
-  if (mode == kOnePass) {
-    HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
-    HIPCK(p, launch_fill_i64(ctr(p) + kCtrResident, 0, 2, s));
-    if (grid_cap == 0)
-      grid_cap = grid_memo_get(wave_tile_lds(mode, wp.table_slots, wp.stage_slots),
-                               p->info.rows_merge > 0 ? p->tune.merge_lists : 0);
-  }
-  HIPCK(p, launch_wave_tiles(wp, mode, p->tune.merge_lists, p->info.rows_merge > 0, grid_cap, s));
+  HIPCK(p, launch_wave_tiles(wp, mode, p->tune.merge_lists, p->info.rows_merge > 0, s));
   return SPGEMM_OK;
 }
 
-// Workgroup-tier rows of one pass: one workgroup per row, device tables in
-// the caller's scratch.
-static spgemm_status run_big(spgemm_plan *p, int mode, void *scratch, size_t scratch_bytes, const double *a_val,
-                             const double *b_val, int64_t *c_rp, int32_t *c_col, double *c_val, int64_t c_capacity,
-                             hipStream_t s) {
-  if (p->nbig == 0) return SPGEMM_OK;
+// Scratch of a plan: the padded buffer of the one pass (capacity sum x 12
+// bytes) first, then one device table per workgroup of k_big.
+// Entries of the padded buffer and the spill arena after it.
+static int64_t pad_entries(const spgemm_plan *p) {
+  return p->first_mode == kOnePass && !p->merge_only ? p->pad_total + p->spill_cap : 0;
+}
+static size_t pad_bytes(const spgemm_plan *p) {
+  const size_t e = (size_t)pad_entries(p);
+  return e ? align_up(align_up(e * 4, 256) + e * 8, 256) : 0;
+}
+
+// Rows computed one workgroup each with device tables in the caller's
+// scratch: the workgroup-tier list (kCtrGlobal rows) or, one pass, the rows
+// that outgrew their capacity (kCtrOverflow rows, count known on the device).
+static spgemm_status run_big(spgemm_plan *p, int mode, bool overflow_list, void *scratch, size_t scratch_bytes,
+                             const double *a_val, const double *b_val, const int64_t *c_rp, int32_t *c_col,
+                             double *c_val, int64_t c_capacity, hipStream_t s) {
+  const int64_t nrows = overflow_list ? (p->opts.sizer == SPGEMM_SIZER_LEARNED ? p->A.rows : 0) : p->nbig;
+  if (nrows == 0) return SPGEMM_OK;
+  const size_t off = pad_bytes(p);
   const size_t per = (size_t)p->scratch_slots * 12;
-  if (per > 0 && (!scratch || scratch_bytes < per)) return SPGEMM_E_WORKSPACE;
+  if (per > 0 && (!scratch || scratch_bytes < off + per)) return SPGEMM_E_WORKSPACE;
   BigParams bp{};
   bp.op = operands_of(p, a_val, b_val);
-  bp.list = p->pa.big;
+  bp.list = overflow_list ? p->pa.ovf : p->pa.big;
+  bp.count_ctr = overflow_list ? kCtrOverflow : kCtrGlobal;
   bp.ub = p->pa.f.ub;
   bp.maxb = p->pa.f.maxb;
   bp.cnt = p->pa.cnt;
@@ -369,12 +360,12 @@ static spgemm_status run_big(spgemm_plan *p, int mode, void *scratch, size_t scr
   bp.c_col = c_col;
   bp.c_val = c_val;
   bp.c_capacity = c_capacity;
-  bp.scratch = static_cast<char *>(scratch);
+  bp.scratch = static_cast<char *>(scratch) + off;
   bp.scratch_slots = p->scratch_slots;
   bp.fast = (p->opts.flags & SPGEMM_OPT_FAST) ? 1 : 0;
   int64_t g = (int64_t)device_cus() * p->tune.blocks_per_cu;
-  g = std::min(g, p->nbig);
-  if (per > 0) g = std::min<int64_t>(g, (int64_t)(scratch_bytes / per));
+  g = std::min(g, nrows);
+  if (per > 0) g = std::min<int64_t>(g, (int64_t)((scratch_bytes - off) / per));
   HIPCK(p, launch_big_rows(bp, mode == kSymbolic ? kSymbolic : kNumeric, (int)g, s));
   return SPGEMM_OK;
 }
@@ -383,6 +374,8 @@ static spgemm_status clear_run_counters(spgemm_plan *p, hipStream_t s) {
   HIPCK(p, launch_fill_i64(ctr(p) + kCtrError, 0, 1, s));
   HIPCK(p, launch_fill_i64(ctr(p) + kCtrOverflow, 0, 1, s));
   HIPCK(p, launch_fill_i64(ctr(p) + kCtrTicket, 0, 1, s));
+  HIPCK(p, launch_fill_i64(ctr(p) + kCtrSpill, 0, 1, s));
+  HIPCK(p, launch_fill_i64(ctr(p) + kCtrSpillRows, 0, 1, s));
   return SPGEMM_OK;
 }
 
@@ -403,11 +396,41 @@ spgemm_status numeric_enqueue(spgemm_plan *p, void *scratch, size_t scratch_byte
                                c_row_ptr, c_col, c_val, c_capacity, s));
     return SPGEMM_OK;
   }
-  // one pass: workgroup-tier rows are counted first, the wave tiles then
-  // place every row, and those rows are written last
-  if (mode == kOnePass) st = run_big(p, kSymbolic, scratch, scratch_bytes, av, bv, nullptr, nullptr, nullptr, 0, s);
-  if (st == SPGEMM_OK) st = run_wave(p, mode, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
-  if (st == SPGEMM_OK) st = run_big(p, kNumeric, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+  if (mode == kNumeric) {
+    st = run_wave(p, kNumeric, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+    if (st == SPGEMM_OK)
+      st = run_big(p, kNumeric, false, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+    return st;
+  }
+  // one pass: workgroup-tier rows are counted first; the wave tiles write
+  // every other row into their tile's padded range (the tile's share of the
+  // scan of the capacities) and count it; the counts are scanned into
+  // row_ptr, the rows moved to their places, and the workgroup-tier rows and
+  // the rows their tile had no room for are computed into C with their exact
+  // sizes
+  const int64_t pe = pad_entries(p);
+  if (pe > 0 && (!scratch || scratch_bytes < pad_bytes(p))) return SPGEMM_E_WORKSPACE;
+  int32_t *pcol = static_cast<int32_t *>(scratch);
+  double *pval = reinterpret_cast<double *>(static_cast<char *>(scratch) + align_up((size_t)pe * 4, 256));
+  st = run_big(p, kSymbolic, false, scratch, scratch_bytes, av, bv, nullptr, nullptr, nullptr, 0, s);
+  if (st == SPGEMM_OK) st = run_wave(p, kOnePass, av, bv, p->pa.pad_rp, pcol, pval, pe, s);
+  if (st != SPGEMM_OK) return st;
+  HIPCK(p, launch_scan_i32(p->pa.cnt, c_row_ptr, p->A.rows, p->pa.scan_status, ctr(p) + kCtrScanTicket,
+                           ctr(p) + kCtrNnz, ctr(p) + kCtrError, s));
+  CompactParams cp{};
+  cp.rows = p->A.rows;
+  cp.info = p->pa.info;
+  cp.pad_src = p->pa.pad_src;
+  cp.pad_col = pcol;
+  cp.pad_val = pval;
+  cp.c_rp = c_row_ptr;
+  cp.c_col = c_col;
+  cp.c_val = c_val;
+  cp.c_capacity = c_capacity;
+  HIPCK(p, launch_compact(cp, s));
+  st = run_big(p, kNumeric, false, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
+  if (st == SPGEMM_OK)
+    st = run_big(p, kNumeric, true, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
   return st;
 }
 
@@ -507,6 +530,9 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   p->pa.scan_status = (uint64_t *)(w + L.scan_status);
   p->pa.partials = (int64_t *)(w + L.partials);
   p->pa.big = (int32_t *)(w + L.big);
+  p->pa.ovf = (int32_t *)(w + L.ovf);
+  p->pa.pad_rp = (int64_t *)(w + L.pad_rp);
+  p->pa.pad_src = (int64_t *)(w + L.pad_src);
   p->keys = (uint64_t *)(w + L.keys);
   hipStream_t s = (hipStream_t)stream;
 
@@ -586,15 +612,25 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
     }
     st = size_pass(p, p->first_mode, s);
     if (st != SPGEMM_OK) return fail(st);
+    if (p->first_mode == kOnePass &&
+        launch_scan_i32(p->pa.cap, p->pa.pad_rp, A->rows, p->pa.scan_status, p->pa.counters + kCtrScanTicket,
+                        p->pa.counters + kCtrPadTotal, p->pa.counters + kCtrError, s) != hipSuccess)
+      return fail(SPGEMM_E_HIP);
     st = read_counters(p, s, &h);
     if (st != SPGEMM_OK) return fail(st);
+    p->pad_total = p->first_mode == kOnePass ? h[kCtrPadTotal] : 0;
+    // learned capacities may fall short: rows their tile has no room for go
+    // to an arena of spill_ratio times the padded buffer (at least kSpillMin)
+    p->spill_cap = learned && !p->merge_only && p->tune.spill_ratio > 0
+                       ? std::max<int64_t>((int64_t)((double)p->tune.spill_ratio * (double)p->pad_total), kSpillMin)
+                       : 0;
   }
   p->info.multiplications = h[kCtrMults];
   p->scratch_slots_plan = p->scratch_slots;
   // room for one table per resident workgroup of the workgroup-tier kernel
   // (no more workgroups than rows that may need one)
   int64_t groups = std::min<int64_t>((int64_t)device_cus() * p->tune.blocks_per_cu, std::max<int64_t>(p->scratch_rows, 1));
-  p->info.scratch_bytes = (size_t)(p->scratch_slots * 12) * (size_t)groups;
+  p->info.scratch_bytes = pad_bytes(p) + (size_t)(p->scratch_slots * 12) * (size_t)groups;
   if (info) *info = p->info;
   *out = p;
   return SPGEMM_OK;
@@ -615,7 +651,8 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
                                p->pa.status, p->pa.cnt, nullptr, nullptr, nullptr, 0, s));
   } else {
     st = run_wave(p, kSymbolic, nullptr, nullptr, nullptr, nullptr, nullptr, 0, s);
-    if (st == SPGEMM_OK) st = run_big(p, kSymbolic, scratch, scratch_bytes, nullptr, nullptr, nullptr, nullptr, nullptr, 0, s);
+    if (st == SPGEMM_OK)
+      st = run_big(p, kSymbolic, false, scratch, scratch_bytes, nullptr, nullptr, nullptr, nullptr, nullptr, 0, s);
     if (st != SPGEMM_OK) return st;
   }
   timing_end(p, s, &e);
@@ -673,7 +710,6 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
     p->stage = 2;
     return SPGEMM_OK;
   }
-  const int mode = two_pass ? kNumeric : kOnePass;
   hipError_t e = hipSuccess;
   timing_begin(p, s, &e);
   HIPCK(p, e);
@@ -684,28 +720,6 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return st;
-  // a one-pass grid that was not resident as a whole stopped early: run the
-  // wave tiles (and the rows after them) again with a grid of 7/8 of the
-  // workgroups found resident together, and remember it for this LDS size
-  for (int round = 1; !p->merge_only && mode == kOnePass && (h[kCtrError] & kErrResidency) && round <= 4; ++round) {
-    const int64_t seen = h[kCtrResidentSeen];
-    const int64_t cap = std::max<int64_t>(1, seen > 8 ? seen - seen / 8 : seen / 2);
-    grid_memo_put(wave_tile_lds(kOnePass, p->table_launch, p->stage_launch),
-                  p->info.rows_merge > 0 ? p->tune.merge_lists : 0, cap);
-    p->info.grid_retries = round;
-    p->info.tile_ms_total -= p->info.tile_ms;   // the attempt that stopped early does not count
-    HIPCK(p, launch_fill_i64(ctr(p) + kCtrError, 0, 1, s));
-    HIPCK(p, launch_fill_i64(ctr(p) + kCtrOverflow, 0, 1, s));
-    timing_begin(p, s, &e);
-    HIPCK(p, e);
-    st = run_wave(p, mode, av, bv, c_row_ptr, c_col, c_val, c_capacity, s, cap);
-    if (st == SPGEMM_OK)
-      st = run_big(p, kNumeric, scratch, scratch_bytes, av, bv, c_row_ptr, c_col, c_val, c_capacity, s);
-    timing_end(p, s, &e);
-    HIPCK(p, e);
-    if (st == SPGEMM_OK) st = read_counters(p, s, &h);
-    if (st != SPGEMM_OK) return st;
-  }
   st = device_errors(p, h);
   if (st != SPGEMM_OK) return st;
   if (two_pass) {
@@ -713,7 +727,9 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
   } else {
     p->info.c_nnz = h[kCtrNnz];
     p->info.overflow_rows = h[kCtrOverflow];
+    p->info.spilled_rows = h[kCtrSpillRows];
     *c_nnz = h[kCtrNnz];
+    if (h[kCtrNnz] > c_capacity) return SPGEMM_E_CAPACITY;
   }
   if (h[kCtrError] & kErrCapacity) return SPGEMM_E_CAPACITY;
   p->stage = 2;

@@ -34,24 +34,24 @@ enum Counter : int {
   kCtrMerge = 4, kCtrHash = 5,
   kCtrGlobal = 6,      // workgroup-tier rows (length of the list in PlanArrays::big)
   kCtrEmpty = 7,
-  kCtrOverflow = 8,    // one-pass rows whose capacity was too small
+  kCtrOverflow = 8,    // one-pass rows whose capacity was too small (length of PlanArrays::ovf)
   kCtrScratch = 9,     // largest device table (slots) a workgroup-level row needs
   kCtrError = 10,      // bit flags, see kErr*
   kCtrNnz = 11,        // nnz(C) after a one-pass numeric
   kCtrScanTicket = 12,
   kCtrStaged = 13,     // rows a numeric or one-pass tile stages in LDS
+  kCtrSpillRows = 14,  // one pass: rows placed in the spill arena
   kCtrMaxA = 15,       // longest row of A
   kCtrUnpacked = 16,   // summed bounds of rows whose feature triple does not pack
   kCtrTable = 17,      // largest wave table (slots) a hashed row uses
   kCtrScratchRows = 18,  // rows that may need a workgroup-tier device table
-  kCtrResident = 19,   // one-pass workgroups that have started
-  kCtrResidentSeen = 20,  // workgroups found resident together when a one-pass grid was too large
+  kCtrPadTotal = 19,   // one pass: entries of the padded buffer (sum of capacities)
+  kCtrSpill = 20,      // one pass: entries claimed in the spill arena
   kCtrWaveSpan = 21,   // largest output of 64 consecutive rows (merge staging)
   kNumCounters = 32
 };
 enum : int64_t {
-  kErrCapacity = 1, kErrNotCanonical = 2, kErrInconsistent = 4, kErrScratch = 8, kErrLookback = 16,
-  kErrResidency = 32   // a one-pass grid was not resident as a whole (the host retries smaller)
+  kErrCapacity = 1, kErrNotCanonical = 2, kErrInconsistent = 4, kErrScratch = 8, kErrLookback = 16
 };
 
 struct Operands {
@@ -101,6 +101,10 @@ struct PlanArrays {
   float *pred;          // learned prediction
   int64_t *partials;    // per-workgroup partial sums of the sizing kernel (8 per workgroup)
   int32_t *big;         // workgroup-tier rows (any order)
+  int32_t *ovf;         // one pass: rows that outgrew their capacity (any order)
+  int64_t *pad_rp;      // one pass: exclusive scan of the capacities (rows + 1)
+  int64_t *pad_src;     // one pass: where a row sits in the padded buffer
+                        // (-1: computed straight into C)
 };
 
 constexpr int64_t kMinTable = 64;   // smallest hashed wave table (slots)
@@ -108,27 +112,42 @@ constexpr int64_t kMinTable = 64;   // smallest hashed wave table (slots)
 struct WaveTileParams {
   Operands op;
   const uint32_t *info;
-  const int32_t *cap;
+  const int32_t *cap;       // per row: exact count (kNumeric), capacity (kOnePass)
   const int32_t *maxb;
   const int32_t *lo;
   const int32_t *tile_row;  // tile bounds (ntiles + 1); null: tiles of 64 rows
-  const int32_t *big_cnt;   // kOnePass: exact counts of workgroup-tier rows
   int64_t ntiles;
   int64_t *counters;
-  uint64_t *status;         // kOnePass: look-back status, one per tile
-  int32_t *cnt_out;         // kSymbolic
-  int64_t *c_rp;            // kNumeric: input; kOnePass: output
-  int32_t *c_col;
+  int32_t *cnt_out;         // kSymbolic, kOnePass: per-row counts
+  int32_t *ovf_list;        // kOnePass: rows with no room (exact path)
+  int64_t *pad_src;         // kOnePass: per-row place in the padded buffer
+  int64_t spill_base;       // kOnePass: first entry of the spill arena
+  int64_t spill_cap;        //           and its entries
+  const int64_t *c_rp;      // kNumeric: exact offsets; kOnePass: padded offsets
+  int32_t *c_col;           // C (kNumeric) or the padded buffer (kOnePass)
   double *c_val;
   int64_t c_capacity;
   int table_slots;          // LDS table of a wave (slots)
   int stage_slots;          // LDS staging of a wave (entries)
-  int stage_row_max;        // kNumeric: hashed rows up to this size are staged (larger ones go to C directly)
+  int stage_row_max;        // hashed rows of at most this capacity are staged
+};
+
+struct CompactParams {
+  int64_t rows;
+  const uint32_t *info;
+  const int64_t *pad_src;
+  const int32_t *pad_col;
+  const double *pad_val;
+  const int64_t *c_rp;
+  int32_t *c_col;
+  double *c_val;
+  int64_t c_capacity;
 };
 
 struct BigParams {
   Operands op;
-  const int32_t *list;      // workgroup-tier rows, counters[kCtrGlobal] of them
+  const int32_t *list;      // rows to compute, counters[count_ctr] of them
+  int count_ctr;
   const int32_t *ub;
   const int32_t *maxb;
   int32_t *cnt;             // kSymbolic: output; kNumeric: exact counts
@@ -163,10 +182,9 @@ hipError_t launch_scan_i64_inplace(int64_t *inout, int64_t n, uint64_t *status, 
 hipError_t launch_tile_bounds(const int64_t *cost, int64_t rows, int64_t half_pool,
                               int32_t *tile_row, int64_t *counters, hipStream_t s);
 size_t wave_tile_lds(int mode, int table_slots, int stage_slots);
-// grid_cap > 0 bounds the one-pass grid (else: the occupancy estimate)
 // has_merge: some row of the pass takes the merge tier
-hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, int64_t grid_cap,
-                             hipStream_t s);
+hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, hipStream_t s);
+hipError_t launch_compact(const CompactParams &cp, hipStream_t s);
 hipError_t launch_big_rows(const BigParams &bp, int mode, int grid, hipStream_t s);
 hipError_t launch_sum_partials(const int64_t *partials, int64_t nblocks, int n, int stride, const int32_t *dst,
                                const int32_t *is_max, int64_t *counters, hipStream_t s);

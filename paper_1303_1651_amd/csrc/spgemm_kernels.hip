@@ -372,9 +372,9 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
         tier = kTierHash;
         info = pack_info(kTierHash, dense, (uint32_t)T);
         tmax = T;
-        // the numeric pass stages small hashed rows and writes larger ones
-        // straight to C
-        if (sp.mode == kOnePass || (sp.mode == kNumeric && c <= sp.stage_row_max)) {
+        // small hashed rows are staged; larger ones are written straight to
+        // C (or the padded buffer of the one pass)
+        if (!sym && c <= sp.stage_row_max) {
           cost = max(min(c, HT), mincost);
           staged = true;
         }
@@ -390,6 +390,9 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
         scratch = global_table_bound(sp.mode == kNumeric ? c : ub);
       }
     }
+    // learned one pass: any row may outgrow its capacity and be computed by
+    // a workgroup with a device table sized by its exact count (<= bound)
+    if (sp.mode == kOnePass && sp.sizer == 2 && tier != kTierEmpty) scratch = max(scratch, global_table_bound(ub));
     pa.info[i] = info;
     pa.cap[i] = (int32_t)c;
     pa.cost[i] = cost;
@@ -1282,19 +1285,21 @@ __device__ void wave_extract(const WaveTable &tb, int32_t n, int32_t *buf, int32
   else wave_sort_out<16>(tb, n, buf, ocol, oval, lim);
 }
 
-// Tile kernel.  MODE kSymbolic: per-row counts (merge rows and hashed rows;
-// workgroup-tier rows are counted by k_big).  kNumeric: row_ptr known, rows
-// staged and copied.  kOnePass: counts found on chip, the tile's offset by a
-// decoupled look-back over tiles, rows staged and copied; rows whose output
-// does not fit the staging left (learned capacity too small) are computed
-// again after the offset is known and written straight to C.
-// One-pass tiles are taken in the order t = blockIdx.x + k * gridDim.x by a
-// grid that is resident as a whole, so every tile waits only on tiles that
-// are running or done.
-constexpr int64_t kResidentPolls = 1ll << 14;
-constexpr int32_t kNotStaged = -1;   // row not (yet) in the stage
-constexpr int32_t kWritten = -2;     // row written to C directly
-
+// Tile kernel.  A tile is a run of at most 64 consecutive rows; its merge
+// rows take one lane each, its hashed rows the whole wave one after another,
+// and its workgroup-tier rows are left to k_big.
+//   kSymbolic: per-row counts (cnt_out).
+//   kNumeric:  c_rp holds the exact row offsets; every row is written there.
+//   kOnePass:  c_rp holds padded offsets (the scan of the rows' capacities,
+//              learned or bound).  A tile's rows share its padded range and
+//              are laid out in it by their exact counts; every row's count
+//              goes to cnt_out and its place to pad_src, and a row the range
+//              has no room for takes a place in the spill arena (after the
+//              padded range) or, with the arena full, is listed in ovf_list
+//              (counted in counters[kCtrOverflow]) for the exact path.
+// Merge rows and small hashed rows (capacity <= stage_row_max) are staged in
+// LDS at offsets that follow their capacities and copied out with
+// contiguous stores; larger hashed rows are written by their wave directly.
 // LDS of a wave tile: table keys, table values, the compaction buffer of a
 // hashed row (kSortMax keys at most), stage columns, stage values.
 struct WaveLds {
@@ -1335,32 +1340,6 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
   double *sval = reinterpret_cast<double *>(lds + L.sval);
   for (int32_t q = lane; q < p.table_slots; q += kWave) tkeys[q] = kEmpty;
   wave_sync();
-  if (MODE == kOnePass) {
-    // tiles wait on lower tiles of other workgroups, so the whole grid must
-    // be resident: count the workgroups in and wait (boundedly) for all of
-    // them; if they do not all arrive, raise kErrResidency and stop (the
-    // host runs the pass again with a smaller grid)
-    int64_t e = 0;
-    if (lane == 0) {
-      unsigned long long *ctr_res = (unsigned long long *)&p.counters[kCtrResident];
-      __hip_atomic_fetch_add(ctr_res, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      for (int64_t polls = 0;; ++polls) {
-        if (__hip_atomic_load(ctr_res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (unsigned long long)gridDim.x)
-          break;
-        if (polls > kResidentPolls) {
-          // workgroups resident together (none has left before this point)
-          atomicMax((unsigned long long *)&p.counters[kCtrResidentSeen],
-                    __hip_atomic_load(ctr_res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-          atomicOr((unsigned long long *)err, (unsigned long long)kErrResidency);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
-      e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    e = __shfl(e, 0, kWave);
-    if (e & kErrResidency) return;
-  }
 
   for (int64_t t = blockIdx.x; t < p.ntiles; t += gridDim.x) {
     const int64_t r0 = p.tile_row ? (int64_t)p.tile_row[t] : t * kWave;
@@ -1372,23 +1351,46 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
     const uint32_t tier = valid ? info_tier(inf) : (uint32_t)kTierEmpty;
     const int32_t capr = valid ? p.cap[row] : 0;
     int64_t n = 0;
-    int32_t soff = kNotStaged;   // or the row's stage offset, or kWritten
 
-    // merge rows, one lane each, staged at their reserved capacity
-    int32_t sp = 0;
+    // staged rows and their stage offsets (by capacity, in row order)
+    const bool staged = VALUES && ((MERGE && tier == kTierMerge) || (tier == kTierHash && capr <= p.stage_row_max));
+    const int32_t res = staged ? capr : 0;
+    const int32_t sinc = wave_inclusive_sum32(res);
+    const int32_t soff = sinc - res;
+    int64_t base = 0, pos = 0, tile_len = 0;
+    if (VALUES) {
+      base = p.c_rp[r0];
+      pos = valid ? p.c_rp[row] - base : 0;
+      tile_len = p.c_rp[r1] - base;
+    }
+    bool fits = true;   // kOnePass: the row keeps its place in the tile's range
+
+    // merge rows, one lane each
     if (VALUES && MERGE) {
-      const int32_t res = tier == kTierMerge ? capr : 0;
-      const int32_t inc = wave_inclusive_sum32(res);
-      sp = __shfl(inc, kWave - 1, kWave);
       if (tier == kTierMerge) {
-        const int32_t o = inc - res;
-        n = merge_row<M, true, false>(op, row, scol + o, sval + o, capr);
-        if (n <= capr) soff = o;
+        n = merge_row<M, true, false>(op, row, scol + soff, sval + soff, capr);
+        fits = n <= capr;
       }
     } else if (MERGE && tier == kTierMerge) {
       n = merge_row<M, false, false>(op, row, nullptr, nullptr, 0);
     }
     wave_sync();
+
+    // one pass: the tile's rows share its padded range (the sum of their
+    // capacities) and are laid out there by their exact counts, in row
+    // order.  The merge rows that fit their staging keep their places; then
+    // every hashed row, in row order, takes the next place if the range
+    // still holds it.  hb: entries of the kept hashed rows before a row.  A
+    // row with no room claims a place in the spill arena; only when that is
+    // full is the row left to the exact path.
+    int32_t mexcl = 0, mtot = 0, hb = 0;
+    int64_t hsum = 0, spos = -1;
+    if (MODE == kOnePass) {
+      const int32_t mk = (tier == kTierMerge && fits) ? (int32_t)n : 0;
+      const int32_t minc = wave_inclusive_sum32(mk);
+      mexcl = minc - mk;
+      mtot = __shfl(minc, kWave - 1, kWave);
+    }
 
     // hashed rows, the whole wave on one row at a time
     uint64_t hm = ballot(tier == kTierHash);
@@ -1398,66 +1400,133 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
       const int64_t hrow = r0 + r;
       const WaveTable tb = wave_table(tkeys, tvals, __shfl(inf, r, kWave), p.lo[hrow]);
       const int32_t c = wave_insert_row<VALUES>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], tb, re, err);
-      if (!VALUES) {
+      const int32_t cap_r = __shfl(capr, r, kWave);
+      bool keep, spill = false;
+      int64_t o;   // the row's place when written straight out
+      if (MODE == kOnePass) {
+        keep = (int64_t)mtot + hsum + c <= tile_len;
+        o = base + __shfl(mexcl, r, kWave) + hsum;
+        if (!keep) {
+          int64_t at = 0;
+          if (lane == 0) at = (int64_t)atomicAdd((unsigned long long *)&p.counters[kCtrSpill], (unsigned long long)c);
+          at = __shfl(at, 0, kWave);
+          spill = at + c <= p.spill_cap;
+          o = p.spill_base + at;
+        }
+      } else {
+        keep = VALUES && c <= cap_r;
+        o = base + __shfl(pos, r, kWave);
+      }
+      if (!keep && !spill) {
+        // counted only, or no room (one pass: computed again by the exact path)
         wave_clear(tb);
-      } else if (sp + c <= p.stage_slots && (MODE == kOnePass || c <= p.stage_row_max)) {
-        wave_extract(tb, c, buf, scol + sp, sval + sp, c);
-        if (lane == r) soff = sp;
-        sp += c;
-      } else if (MODE == kNumeric) {
-        // the row's place in C is known: sorted entries go straight there
-        const int64_t o = p.c_rp[hrow];
+      } else if (keep && __shfl(staged ? 1 : 0, r, kWave) && c <= cap_r) {
+        const int32_t so = __shfl(soff, r, kWave);
+        wave_extract(tb, c, buf, scol + so, sval + so, c);
+      } else {
+        // straight to the row's place in C (or in the padded buffer)
         const int64_t rl = max((int64_t)0, min((int64_t)c, p.c_capacity - o));
         wave_extract(tb, c, buf, p.c_col + o, p.c_val + o, rl);
-        if (lane == r) soff = kWritten;
-      } else {
-        wave_clear(tb);
       }
-      if (lane == r) n = c;
+      if (MODE == kOnePass && keep) {
+        if (lane > r) hb += c;
+        hsum += c;
+      }
+      if (lane == r) {
+        n = c;
+        fits = keep;
+        if (spill) spos = o;
+      }
     }
 
     if (MODE == kSymbolic) {
       if (valid && tier != kTierGlobal) p.cnt_out[row] = (int32_t)n;
       continue;
     }
-    if (tier == kTierGlobal) n = (MODE == kNumeric) ? (int64_t)capr : (int64_t)p.big_cnt[row];
     if (MODE == kNumeric && valid && tier != kTierGlobal && n != capr)
       atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
-
-    // offsets of the tile's rows in C
-    const int64_t inc = wave_inclusive_sum(n);
-    const int64_t total = __shfl(inc, kWave - 1, kWave);
-    const int64_t ex = inc - n;
-    int64_t base;
-    if (MODE == kNumeric) {
-      base = p.c_rp[r0];
-    } else {
-      base = lookback_exclusive(p.status, t, total, err, kErrLookback, kErrResidency);
-      if (valid) p.c_rp[row] = base + ex;
-      if (t == p.ntiles - 1 && lane == 0) {
-        p.c_rp[op.rows] = base + total;
-        p.counters[kCtrNnz] = base + total;
-      }
-    }
-    if (lane == 0 && base + total > p.c_capacity)
+    if (lane == 0 && base + tile_len > p.c_capacity)
       atomicOr((unsigned long long *)err, (unsigned long long)kErrCapacity);
 
-    // copy-out of the staged rows: one contiguous copy when the stage is in
-    // C order (every row with entries sits at its C offset), else row by row
-    const bool in_order = ballot(valid && n > 0 && soff != ex) == 0ull;
+    if (MODE == kOnePass) {
+      // merge rows longer than their staging: merged again into the arena
+      const bool mspill = MERGE && valid && tier == kTierMerge && !fits;
+      if (ballot(mspill)) {
+        const int64_t want = mspill ? n : 0;
+        const int32_t winc = wave_inclusive_sum32((int32_t)want);
+        int64_t at = 0;
+        if (lane == kWave - 1 && winc > 0)
+          at = (int64_t)atomicAdd((unsigned long long *)&p.counters[kCtrSpill], (unsigned long long)winc);
+        at = __shfl(at, kWave - 1, kWave) + (winc - want);
+        if (mspill && at + want <= p.spill_cap) {
+          spos = p.spill_base + at;
+          merge_row<M, true, false>(op, row, p.c_col + spos, p.c_val + spos, want);
+        }
+      }
+      const bool row_out = valid && tier != kTierGlobal;
+      const bool kept = row_out && fits;
+      const int32_t ppos = mexcl + hb;   // place in the tile's range (kept rows)
+      // every row of the tile gets its place (-1: written straight into C,
+      // as the workgroup-tier rows and the rows with no room are)
+      if (row_out) p.cnt_out[row] = (int32_t)n;
+      if (valid) p.pad_src[row] = kept ? base + ppos : (row_out ? spos : (int64_t)-1);
+      const uint64_t sb = ballot(row_out && !fits && spos >= 0);
+      if (sb && lane == 0) atomicAdd((unsigned long long *)&p.counters[kCtrSpillRows], (unsigned long long)__popcll(sb));
+      // rows with no room anywhere go to the exact path
+      const bool ov = row_out && !fits && spos < 0;
+      const uint64_t ob = ballot(ov);
+      if (ob) {
+        int64_t at = 0;
+        if (lane == 0)
+          at = (int64_t)atomicAdd((unsigned long long *)&p.counters[kCtrOverflow], (unsigned long long)__popcll(ob));
+        at = __shfl(at, 0, kWave);
+        if (ov) p.ovf_list[at + __popcll(ob & lanemask_lt())] = (int32_t)row;
+      }
+      // staged kept rows move from their staging (laid out by capacity) to
+      // their places (laid out by count): every entry of the kept range
+      // finds its row by a search over the places in LDS (the row-entry
+      // area, free here)
+      int32_t *s_pos = reinterpret_cast<int32_t *>(lds);
+      int32_t *s_so = s_pos + kWave;
+      s_pos[lane] = ppos;
+      s_so[lane] = (kept && staged && n <= capr) ? soff : -1;
+      wave_sync();
+      const int64_t ktot = (int64_t)mtot + hsum;
+      const int64_t lim = max((int64_t)0, min(ktot, p.c_capacity - base));
+      for (int64_t q = lane; q < lim; q += kWave) {
+        int lo = 0, hi = kWave - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pos[mid] <= q) lo = mid;
+          else hi = mid - 1;
+        }
+        const int32_t so = s_so[lo];
+        if (so >= 0) {
+          const int32_t from = so + (int32_t)(q - s_pos[lo]);
+          p.c_col[base + q] = scol[from];
+          p.c_val[base + q] = sval[from];
+        }
+      }
+      wave_sync();
+      continue;
+    }
+
+    // copy-out of the staged rows: one contiguous copy of the tile's range
+    // when every row with room is staged at its place, else row by row
+    const bool in_order = ballot(valid && capr > 0 && !(staged && fits && soff == pos)) == 0ull;
     if (in_order) {
-      const int64_t lim = max((int64_t)0, min(total, p.c_capacity - base));
+      const int64_t lim = max((int64_t)0, min(tile_len, p.c_capacity - base));
       for (int64_t q = lane; q < lim; q += kWave) {
         p.c_col[base + q] = scol[q];
         p.c_val[base + q] = sval[q];
       }
     } else {
-      uint64_t sm = ballot(valid && n > 0 && soff >= 0);
+      uint64_t sm = ballot(valid && staged && fits && n > 0);
       while (sm) {
         const int r = __ffsll((unsigned long long)sm) - 1;
         sm &= sm - 1;
         const int32_t so = __shfl(soff, r, kWave);
-        const int64_t o = base + __shfl(ex, r, kWave);
+        const int64_t o = base + __shfl(pos, r, kWave);
         const int64_t lim = max((int64_t)0, min(__shfl(n, r, kWave), p.c_capacity - o));
         for (int64_t q = lane; q < lim; q += kWave) {
           p.c_col[o + q] = scol[so + q];
@@ -1466,32 +1535,54 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
       }
     }
     wave_sync();
-
-    // rows that were not staged (learned capacity too small): again, into C
-    const bool redo = valid && n > 0 && soff == kNotStaged && tier != kTierGlobal;
-    if (MODE == kOnePass) {
-      const uint64_t rb = ballot(redo);
-      if (lane == 0 && rb)
-        atomicAdd((unsigned long long *)&p.counters[kCtrOverflow], (unsigned long long)__popcll(rb));
-    }
-    if (MERGE && redo && tier == kTierMerge) {
-      const int64_t o = base + ex;
-      const int64_t rl = max((int64_t)0, min(n, p.c_capacity - o));
-      merge_row<M, true, false>(op, row, p.c_col + o, p.c_val + o, rl);
-    }
-    uint64_t hr = ballot(redo && tier == kTierHash);
-    while (hr) {
-      const int r = __ffsll((unsigned long long)hr) - 1;
-      hr &= hr - 1;
-      const int64_t hrow = r0 + r;
-      const WaveTable tb = wave_table(tkeys, tvals, p.info[hrow], p.lo[hrow]);
-      const int32_t c = wave_insert_row<true>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], tb, re, err);
-      const int64_t o = base + __shfl(ex, r, kWave);
-      const int64_t rl = max((int64_t)0, min((int64_t)c, p.c_capacity - o));
-      wave_extract(tb, c, buf, p.c_col + o, p.c_val + o, rl);
-    }
-    wave_sync();
   }
+}
+
+// Moves the one-pass rows from the padded buffer to their exact places:
+// 64 rows per wave, their entries copied as one contiguous range of C (rows
+// written elsewhere, workgroup-tier and overflow rows, are skipped).
+__global__ void __launch_bounds__(kBlock) k_compact(CompactParams p) {
+  // the wave's row offsets live in LDS: the search below runs in divergent
+  // lanes, where a cross-lane read from an inactive lane would return 0
+  __shared__ int64_t s_dst[kWavesPerBlock][kWave + 1];
+  __shared__ int64_t s_src[kWavesPerBlock][kWave];
+  const int l = lane_id();
+  const int w = threadIdx.x / kWave;
+  const int64_t r0 = ((int64_t)blockIdx.x * kWavesPerBlock + w) * kWave;
+  if (r0 >= p.rows) return;
+  const int64_t row = r0 + l;
+  const int nr = (int)min((int64_t)kWave, p.rows - r0);
+  const int64_t base = p.c_rp[r0];
+  if (l < nr) {
+    s_dst[w][l] = p.c_rp[row] - base;
+    // rows written straight into C (workgroup tier, no room) are marked -1
+    s_src[w][l] = info_tier(p.info[row]) == kTierGlobal ? (int64_t)-1 : p.pad_src[row];
+  }
+  if (l == 0) s_dst[w][nr] = p.c_rp[r0 + nr] - base;
+  wave_sync();
+  const int64_t lim = min(base + s_dst[w][nr], p.c_capacity) - base;
+  for (int64_t q = l; q < lim; q += kWave) {
+    // the row holding entry base + q: the last row whose start is <= q
+    int lo = 0, hi = nr - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_dst[w][mid] <= q) lo = mid;
+      else hi = mid - 1;
+    }
+    const int64_t from = s_src[w][lo];
+    if (from >= 0) {
+      p.c_col[base + q] = p.pad_col[from + (q - s_dst[w][lo])];
+      p.c_val[base + q] = p.pad_val[from + (q - s_dst[w][lo])];
+    }
+  }
+}
+
+hipError_t launch_compact(const CompactParams &cp, hipStream_t s) {
+  if (cp.rows <= 0) return hipSuccess;
+  const int64_t waves = (cp.rows + kWave - 1) / kWave;
+  const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)blocks), dim3(kBlock), 0, s, cp);
+  return hipGetLastError();
 }
 
 // Workgroup-tier rows: one workgroup per listed row, the table in the
@@ -1500,7 +1591,7 @@ template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
   __shared__ WgScratch ws;
   const Operands &op = p.op;
-  const int64_t nbig = p.counters[kCtrGlobal];
+  const int64_t nbig = p.counters[p.count_ctr];
   int32_t *gkeys = reinterpret_cast<int32_t *>(p.scratch + (size_t)blockIdx.x * (size_t)p.scratch_slots * 12);
   double *gvals = reinterpret_cast<double *>(p.scratch + (size_t)blockIdx.x * (size_t)p.scratch_slots * 12 +
                                              (size_t)p.scratch_slots * 4);
@@ -1742,45 +1833,33 @@ size_t wave_tile_lds(int mode, int table_slots, int stage_slots) {
 }
 
 template <int MODE, int M, bool MERGE>
-static hipError_t launch_wt_mm(const WaveTileParams &wp, size_t lds, int64_t grid_cap, hipStream_t s) {
+static hipError_t launch_wt_mm(const WaveTileParams &wp, size_t lds, hipStream_t s) {
   const void *fn = reinterpret_cast<const void *>(&k_wt<MODE, M, MERGE>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  int64_t grid = wp.ntiles;
-  if (MODE == kOnePass) {
-    // the whole grid must be resident: tiles wait on lower-numbered tiles
-    int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWave, lds);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) return hipErrorInvalidConfiguration;
-    per_cu = std::min(per_cu, 16);
-    grid = std::min<int64_t>(grid, (int64_t)per_cu * device_cus());
-    if (grid_cap > 0) grid = std::min(grid, grid_cap);
-  }
-  grid = std::min<int64_t>(grid, 0x7fffffff);
+  const int64_t grid = std::min<int64_t>(wp.ntiles, 0x7fffffff);
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_wt<MODE, M, MERGE>), dim3((unsigned)grid), dim3(kWave), lds, s, wp);
   return hipGetLastError();
 }
 
 template <int M, bool MERGE>
-static hipError_t launch_wt_m(const WaveTileParams &wp, int mode, size_t lds, int64_t grid_cap, hipStream_t s) {
+static hipError_t launch_wt_m(const WaveTileParams &wp, int mode, size_t lds, hipStream_t s) {
   switch (mode) {
-    case kSymbolic: return launch_wt_mm<kSymbolic, M, MERGE>(wp, lds, grid_cap, s);
-    case kNumeric: return launch_wt_mm<kNumeric, M, MERGE>(wp, lds, grid_cap, s);
-    default: return launch_wt_mm<kOnePass, M, MERGE>(wp, lds, grid_cap, s);
+    case kSymbolic: return launch_wt_mm<kSymbolic, M, MERGE>(wp, lds, s);
+    case kNumeric: return launch_wt_mm<kNumeric, M, MERGE>(wp, lds, s);
+    default: return launch_wt_mm<kOnePass, M, MERGE>(wp, lds, s);
   }
 }
 
-hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, int64_t grid_cap,
-                             hipStream_t s) {
+hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, hipStream_t s) {
   const size_t lds = wave_tile_lds(mode, wp.table_slots, wp.stage_slots);
-  if (!has_merge) return launch_wt_m<4, false>(wp, mode, lds, grid_cap, s);
+  if (!has_merge) return launch_wt_m<4, false>(wp, mode, lds, s);
   switch (merge_lists) {
-    case 4: return launch_wt_m<4, true>(wp, mode, lds, grid_cap, s);
-    case 8: return launch_wt_m<8, true>(wp, mode, lds, grid_cap, s);
+    case 4: return launch_wt_m<4, true>(wp, mode, lds, s);
+    case 8: return launch_wt_m<8, true>(wp, mode, lds, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -78,7 +78,7 @@ def test_invalid_tuning_is_rejected():
     from paper_1303_1651_amd import _lib as L
     A = L.spgemm_csr(4, 4, 0, 1, None, None)
     for bad in (dict(table_slots=300), dict(stage_slots=100), dict(stage_slots=9000),
-                dict(merge_lists=6)):
+                dict(merge_lists=6), dict(spill_ratio=5.0)):
         t = L.spgemm_tuning(**bad)
         opts = L.spgemm_options(0, 0, None, ctypes.pointer(t))
         plan = ctypes.c_void_p()

@@ -89,8 +89,8 @@ def test_batch_with_empty_instances_and_learned_sizer():
     wants = [oracle.spgemm(it.A, it.B) for it in insts]
     As, Bs = _dev(insts)
     # a network that predicts the smallest size for every row: capacities
-    # fall short, rows are computed again after the look-back, and the pools
-    # grow once
+    # fall short, rows spill or are computed again with their exact size,
+    # and the pools grow once
     theta = np.zeros(1217, np.float32)
     theta[-1] = -30.0
     model = P.Model.create(theta, [0, 0, 0], [1, 1, 1])

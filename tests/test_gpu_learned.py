@@ -137,17 +137,41 @@ def test_learned_product_equals_oracle(trained, case):
 
 
 def test_bad_model_still_gives_exact_product():
-    # a network that predicts the smallest size for every row forces the
-    # overflow fallback on every hashed row; the product must not change
+    # a network that predicts the smallest size for every row, with no spill
+    # arena, sends the rows their tiles have no room for to the exact path;
+    # the product must not change
     import paper_1303_1651_amd as P
     theta = np.zeros(1217, np.float32)
     theta[-1] = -30.0                   # rho ~ 0: predict the longest B row
     model = P.Model.create(theta, [0, 0, 0], [1, 1, 1])
     A = synth.zipf_matrix(30000, 8)
     want = oracle.spgemm(A, A)
-    got = gpu_product(A, A, "learned", model=model, tuning={"merge_max_nnz": -1})
+    for tuning in ({"merge_max_nnz": -1, "spill_ratio": -1}, {"spill_ratio": -1}):
+        got = gpu_product(A, A, "learned", model=model, tuning=tuning)
+        assert_bit_exact(got, want)
+        assert got[3]["overflow_rows"] > 0 and got[3]["spilled_rows"] == 0
+
+
+@pytest.mark.parametrize("tuning", [None, {"merge_max_nnz": -1}])
+def test_short_capacities_spill_into_the_arena(tuning):
+    # capacities of the longest selected B row for rows of several times
+    # that: the rows a tile has no room for take places in the spill arena
+    # (at least 4096 entries, more than this whole product), merge rows are
+    # merged again into it, and no row is computed a second time
+    import paper_1303_1651_amd as P
+    theta = np.zeros(1217, np.float32)
+    theta[-1] = -30.0
+    model = P.Model.create(theta, [0, 0, 0], [1, 1, 1])
+    A = synth.random_uniform_lengths(60, 2, 20, 17)
+    assert np.diff(A.row_ptr).max() > 16      # not the merge-only path
+    want = oracle.spgemm(A, A)
+    assert want[0][-1] < 4096
+    got = gpu_product(A, A, "learned", model=model, tuning=tuning)
     assert_bit_exact(got, want)
-    assert got[3]["overflow_rows"] > 0
+    assert got[3]["overflow_rows"] == 0
+    assert got[3]["spilled_rows"] > 0
+    if tuning is None:
+        assert got[3]["rows_merge"] > 0
 
 
 def test_trained_network_gains_over_the_bound():
