@@ -73,22 +73,37 @@ def make_workloads(name):
     raise ValueError(name)
 
 
-def train_sizer(P, torch, seed_base=1001):
-    """Trains the row-size network on the GPU with the library's kernels.
-    Training rows: power-law matrices (seeds disjoint from any evaluation
-    seed), small stencils and small fixed-length random matrices; labels are
-    the exact row sizes from the symbolic pass."""
+# Source matrices of the row-size network per workload family: smaller
+# instances of the same kind, with seeds disjoint from every evaluation seed.
+# The network sees only (nnz(A_i), UB_i, longest B row), and rows of
+# different families can share those features while their sizes differ (an
+# interior 27-point row and a power-law row of 27 entries whose products all
+# land on distinct columns), so it is trained per family.
+SIZER_FAMILIES = {"roofline": ("stencil", "random"), "stencil": ("stencil",), "st9": ("stencil",),
+                  "st27": ("stencil",), "random": ("random",), "zipf": ("zipf",)}
+
+
+def sizer_sources(family, seed_base):
+    import synth
+    if family == "zipf":
+        return [(synth.zipf_matrix(1 << 18, seed_base + i),) * 2 for i in range(4)]
+    if family == "stencil":
+        out = [(synth.stencil(g),) * 2 for g in (64, 96, 128)]
+        out += [(synth.stencil(g, dim, pts),) * 2 for pts, dim, g in ((9, 2, 64), (9, 2, 96), (27, 3, 16), (27, 3, 24))]
+        return out
+    return [(synth.random_fixed(1 << 16, k, seed_base + 40 + k), synth.random_fixed(1 << 16, k, seed_base + 80 + k))
+            for k in (4, 8, 16, 32)]
+
+
+def train_sizer(P, torch, workload, seed_base=1001):
+    """Trains the row-size network on the GPU with the library's kernels, on
+    the workload's family; labels are the exact row sizes from the symbolic
+    pass.  Every source matrix contributes the same number of rows (drawn
+    with replacement from a seeded generator), so that rare row shapes weigh
+    as much as common ones."""
     import synth
     feats, labels = [], []
-    pairs = [(synth.zipf_matrix(1 << 18, seed_base + i),) * 2 for i in range(4)]
-    for g in (64, 96, 128):
-        S = synth.stencil(g)
-        pairs.append((S, S))
-    for pts, dim, g in ((9, 2, 96), (27, 3, 24)):
-        S = synth.stencil(g, dim, pts)
-        pairs.append((S, S))
-    for k in (4, 8, 16, 32):
-        pairs.append((synth.random_fixed(1 << 16, k, seed_base + 40 + k), synth.random_fixed(1 << 16, k, seed_base + 80 + k)))
+    pairs = [pr for fam in SIZER_FAMILIES[workload] for pr in sizer_sources(fam, seed_base)]
     for A, B in pairs:
         dA = P.DeviceCSR.from_host(A)
         dB = dA if B is A else P.DeviceCSR.from_host(B)
@@ -98,18 +113,21 @@ def train_sizer(P, torch, seed_base=1001):
         plan.close()
         feats.append((f1, f2, f3))
         labels.append((rp[1:] - rp[:-1]).to(torch.int32))
-    f1 = torch.cat([f[0] for f in feats])
-    f2 = torch.cat([f[1] for f in feats])
-    f3 = torch.cat([f[2] for f in feats])
-    lab = torch.cat(labels)
-    # shuffle once so mini-batches mix the sources (permutation from a seed)
     g = torch.Generator(device="cpu").manual_seed(seed_base)
+    per_source = 1 << 16
+    picks = [torch.randint(0, f[0].numel(), (per_source,), generator=g).to(f[0].device) for f in feats]
+    f1 = torch.cat([f[0][i] for f, i in zip(feats, picks)])
+    f2 = torch.cat([f[1][i] for f, i in zip(feats, picks)])
+    f3 = torch.cat([f[2][i] for f, i in zip(feats, picks)])
+    lab = torch.cat([l[i] for l, i in zip(labels, picks)])
+    # shuffle once so mini-batches mix the sources (permutation from a seed)
     perm = torch.randperm(f1.numel(), generator=g).to(f1.device)
     f1, f2, f3, lab = f1[perm].contiguous(), f2[perm].contiguous(), f3[perm].contiguous(), lab[perm].contiguous()
     mu, sd = P.feature_stats(f1, f2, f3)
     theta0 = synth.mlp_init(seed_base)
-    model, curve = P.train_model(theta0, mu, sd, f1, f2, f3, lab, epochs=20, batch_size=32768, lr=3e-3)
-    return model, {"train_rows": int(f1.numel()), "loss_first": float(curve[0]), "loss_last": float(curve[-1])}
+    model, curve = P.train_model(theta0, mu, sd, f1, f2, f3, lab, epochs=30, batch_size=8192, lr=3e-3)
+    return model, {"families": list(SIZER_FAMILIES[workload]), "train_rows": int(f1.numel()),
+                   "loss_first": float(curve[0]), "loss_last": float(curve[-1])}
 
 
 class Product:
@@ -365,7 +383,7 @@ def main():
     if need_model:
         log("training the row-size network on the GPU")
         t0 = time.time()
-        model, train_info = train_sizer(P, torch)
+        model, train_info = train_sizer(P, torch, args.workload)
         train_info["seconds"] = round(time.time() - t0, 2)
 
     log("timed steps (%s)" % args.sizer)
@@ -385,7 +403,8 @@ def main():
                            "numeric_pass_ms": round(num_ms, 4), "symbolic_pass_ms": round(sym_ms, 4),
                            "numeric_pass_GBps": round(mb / num_ms / 1e6, 1),
                            "tiers": {k: info[k] for k in ("rows_merge", "rows_hash", "rows_global", "rows_empty")},
-                           "overflow_rows": info["overflow_rows"]}
+                           "overflow_rows": info["overflow_rows"],
+                           "capacity_over_nnz": round(info["c_capacity_hint"] / max(got, 1), 3)}
         if dominant is None or num_ms > dominant[1]:
             dominant = (p.name, num_ms, mb, info)
     gflops = flops_step / (ms * 1e-3) / 1e9
@@ -400,6 +419,8 @@ def main():
                 details[p.name]["numeric_pass_ms_" + other] = round(
                     sum(s[i][1]["numeric_ms"] for s in oper) / len(oper), 4)
                 details[p.name]["overflow_rows_" + other] = oper[-1][i][1]["overflow_rows"]
+                details[p.name]["capacity_over_nnz_" + other] = round(
+                    oper[-1][i][1]["c_capacity_hint"] / max(oper[-1][i][0], 1), 3)
         details["step_ms_" + args.sizer] = round(ms, 4)
 
     name, dms, dbytes, dinfo = dominant

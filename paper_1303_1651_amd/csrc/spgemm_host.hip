@@ -157,7 +157,7 @@ struct spgemm_plan {
   int table_launch;        // LDS table slots of the wave-tile launch
   int stage_launch;        // LDS staging entries of the wave-tile launch
   int merge_only;      // every row takes the register-merge tier: row-per-thread kernels
-  int merge_m;         // lists of the row-per-thread merge (4, 8 or 16)
+  int merge_m;         // lists of the row-per-thread merge (4, 6, 8, 10 or 16)
   int merge_stage;     // staged entries per merge wave
   spgemm_info info;
   hipError_t last_err;
@@ -237,6 +237,15 @@ constexpr int kStageRowMax = 128;
 constexpr int64_t kSpillMin = 4096;   // smallest spill arena (entries)
 
 // Sizing of one pass (tiers, capacities, tile costs) plus tile bounds.
+// Hashed rows of at most this capacity are staged in LDS.  A learned
+// capacity carries the sizing margin: the limit scales with it, so that a
+// row predicted at kStageRowMax entries is staged like an exact one.
+static int stage_row_max(const spgemm_plan *p, int mode) {
+  if (mode == kOnePass && p->opts.sizer == SPGEMM_SIZER_LEARNED)
+    return (int)std::ceil(kStageRowMax * (1.0 + (double)p->tune.margin)) + p->tune.slack;
+  return kStageRowMax;
+}
+
 static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   const int tvals = p->tune.table_slots;                   // values table (numeric, one pass)
   const int tkeys = std::min(4 * tvals, 16384);            // keys-only table (symbolic): same bytes
@@ -247,7 +256,7 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   sp.table_max = mode == kSymbolic ? tkeys : tvals;
   sp.value_table_max = tvals;
   sp.stage = stage;
-  sp.stage_row_max = kStageRowMax;
+  sp.stage_row_max = stage_row_max(p, mode);
   sp.merge_lists = p->tune.merge_lists;
   sp.merge_max = std::min(p->tune.merge_max_nnz, stage / 2);
   sp.dense_ratio = p->tune.dense_ratio;
@@ -319,7 +328,7 @@ static spgemm_status run_wave(spgemm_plan *p, int mode, const double *a_val, con
   wp.c_capacity = c_capacity;
   wp.table_slots = p->table_launch;
   wp.stage_slots = p->stage_launch;
-  wp.stage_row_max = kStageRowMax;
+  wp.stage_row_max = stage_row_max(p, mode);
   HIPCK(p, launch_wave_tiles(wp, mode, p->tune.merge_lists, p->info.rows_merge > 0, s));
   return SPGEMM_OK;
 }
@@ -404,16 +413,21 @@ spgemm_status numeric_enqueue(spgemm_plan *p, void *scratch, size_t scratch_byte
   }
   // one pass: workgroup-tier rows are counted first; the wave tiles write
   // every other row into their tile's padded range (the tile's share of the
-  // scan of the capacities) and count it; the counts are scanned into
-  // row_ptr, the rows moved to their places, and the workgroup-tier rows and
-  // the rows their tile had no room for are computed into C with their exact
-  // sizes
+  // scan of the capacities) or the spill arena and count it; the listed rows
+  // (no room anywhere, or a learned-size table that filled) are counted
+  // again; the counts are scanned into row_ptr, the rows moved to their
+  // places, and the workgroup-tier and listed rows are computed into C with
+  // their exact sizes
   const int64_t pe = pad_entries(p);
   if (pe > 0 && (!scratch || scratch_bytes < pad_bytes(p))) return SPGEMM_E_WORKSPACE;
   int32_t *pcol = static_cast<int32_t *>(scratch);
   double *pval = reinterpret_cast<double *>(static_cast<char *>(scratch) + align_up((size_t)pe * 4, 256));
   st = run_big(p, kSymbolic, false, scratch, scratch_bytes, av, bv, nullptr, nullptr, nullptr, 0, s);
   if (st == SPGEMM_OK) st = run_wave(p, kOnePass, av, bv, p->pa.pad_rp, pcol, pval, pe, s);
+  // rows whose learned-size table filled have no count yet: the listed rows
+  // are counted again (learned sizer only; the list is empty otherwise)
+  if (st == SPGEMM_OK)
+    st = run_big(p, kSymbolic, true, scratch, scratch_bytes, av, bv, nullptr, nullptr, nullptr, 0, s);
   if (st != SPGEMM_OK) return st;
   HIPCK(p, launch_scan_i32(p->pa.cnt, c_row_ptr, p->A.rows, p->pa.scan_status, ctr(p) + kCtrScanTicket,
                            ctr(p) + kCtrNnz, ctr(p) + kCtrError, s));
@@ -576,10 +590,15 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
                          (B->rows > 0 ? (double)B->nnz / (double)B->rows : 0.0);
   p->merge_only = A->rows > 0 && h[kCtrMaxA] <= kMergeOnlyLists && p->tune.merge_max_nnz > 0 &&
                   (h[kCtrMaxA] <= p->tune.merge_lists || est_row <= kMergeOnlyRowEst);
-  p->merge_m = h[kCtrMaxA] <= 4 ? 4 : (h[kCtrMaxA] <= 8 ? 8 : 16);
-  // one pass: staging for 64 rows of up to 2 x 16 entries each (8-list rows)
-  // or 2 x 32 (16-list rows); the numeric pass sizes it from the exact counts
-  p->merge_stage = p->merge_m == 16 ? 2048 : 1024;
+  // the fewest lists that hold every row of A (registers grow with them)
+  {
+    const int64_t ma = h[kCtrMaxA];
+    p->merge_m = ma <= 4 ? 4 : ma <= 6 ? 6 : ma <= 8 ? 8 : ma <= 10 ? 10 : 16;
+  }
+  // one pass: staging for 64 rows of up to 2 x 16 entries each (rows of at
+  // most 8 lists) or 2 x 32 (10 or 16 lists); the numeric pass sizes it from
+  // the exact counts
+  p->merge_stage = p->merge_m >= 10 ? 2048 : 1024;
   if (p->merge_only) {
     // row sums (multiplications, empty rows) and, for the learned sizer, the
     // packed feature triple of every row and the learned capacity

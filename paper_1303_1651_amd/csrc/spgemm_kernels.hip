@@ -359,15 +359,21 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
         dense = true;
         T = span;
       } else {
-        const int64_t need = sym ? 2 * ub : (sp.mode == kNumeric ? 2 * c : max(ub + 1, 2 * c));
+        // the bound one pass sizes its tables so that they never fill; the
+        // learned one sizes them like the numeric pass, by the predicted size
+        // (the capacity without its margin), and a row whose table fills is
+        // computed again by the exact path
+        const bool learned1 = sp.mode == kOnePass && sp.sizer == 2;
+        const int64_t ct = learned1 ? min(max((int64_t)ceilf(sp.pred[i]), mx), ub) : c;
+        const int64_t need = sym ? 2 * ub : ((sp.mode == kNumeric || learned1) ? 2 * ct : max(ub + 1, 2 * c));
         T = table_pow2(need);
         // one pass: a table just above the bound still never fills (the
         // load is high only where the capacity is close to the bound)
         if (sp.mode == kOnePass && T > sp.table_max) T = table_pow2(ub + 1);
       }
       // a hashed (not dense) row's keys are sorted in the wave's registers:
-      // at most kSortMax of them
-      const int64_t most = sym ? 0 : (sp.mode == kNumeric ? c : ub);
+      // at most kSortMax of them (a table holds at most T)
+      const int64_t most = sym ? 0 : (sp.mode == kNumeric ? c : min(ub, T));
       if (sp.table_max > 0 && T <= sp.table_max && (dense || most <= kSortMax)) {
         tier = kTierHash;
         info = pack_info(kTierHash, dense, (uint32_t)T);
@@ -1308,8 +1314,9 @@ struct WaveLds {
 __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots, int stage_slots) {
   auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
   WaveLds L;
-  // row entries (64 x (int64 + int32 + double)) first, then the table
-  L.ent = (size_t)kWave * 20;
+  // row entries (64 x (int64 + int32 + double)) first, a flag word (16
+  // bytes), then the table
+  L.ent = (size_t)kWave * 20 + 16;
   L.vals = L.ent + a16((size_t)table_slots * 4);
   if (!values) {
     L.buf = L.scol = L.sval = L.total = L.vals;
@@ -1324,7 +1331,7 @@ __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots,
 }
 
 template <int MODE, int M, bool MERGE>
-__global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
+__global__ void __launch_bounds__(kWave, MODE == kOnePass && MERGE ? 2 : 4) k_wt(WaveTileParams p) {
   constexpr bool VALUES = (MODE != kSymbolic);
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x;
@@ -1338,7 +1345,10 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
   int32_t *buf = reinterpret_cast<int32_t *>(lds + L.buf);
   int32_t *scol = reinterpret_cast<int32_t *>(lds + L.scol);
   double *sval = reinterpret_cast<double *>(lds + L.sval);
+  // one pass: set by a probe that found its row's table full
+  int64_t *full_flag = reinterpret_cast<int64_t *>(lds + kWave * 20);
   for (int32_t q = lane; q < p.table_slots; q += kWave) tkeys[q] = kEmpty;
+  if (lane == 0) *full_flag = 0;
   wave_sync();
 
   for (int64_t t = blockIdx.x; t < p.ntiles; t += gridDim.x) {
@@ -1399,14 +1409,21 @@ __global__ void __launch_bounds__(kWave, 2) k_wt(WaveTileParams p) {
       hm &= hm - 1;
       const int64_t hrow = r0 + r;
       const WaveTable tb = wave_table(tkeys, tvals, __shfl(inf, r, kWave), p.lo[hrow]);
-      const int32_t c = wave_insert_row<VALUES>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], tb, re, err);
+      const int32_t c = wave_insert_row<VALUES>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], tb, re,
+                                                MODE == kOnePass ? full_flag : err);
       const int32_t cap_r = __shfl(capr, r, kWave);
-      bool keep, spill = false;
+      bool keep, spill = false, full = false;
       int64_t o;   // the row's place when written straight out
       if (MODE == kOnePass) {
-        keep = (int64_t)mtot + hsum + c <= tile_len;
+        // a table sized by a learned capacity may have filled: keys were
+        // dropped, and the row goes to the exact path
+        wave_sync();
+        full = *full_flag != 0;
+        wave_sync();
+        if (full && lane == 0) *full_flag = 0;
+        keep = !full && (int64_t)mtot + hsum + c <= tile_len;
         o = base + __shfl(mexcl, r, kWave) + hsum;
-        if (!keep) {
+        if (!keep && !full) {
           int64_t at = 0;
           if (lane == 0) at = (int64_t)atomicAdd((unsigned long long *)&p.counters[kCtrSpill], (unsigned long long)c);
           at = __shfl(at, 0, kWave);
@@ -1682,7 +1699,7 @@ __device__ inline int64_t lookback_resolve(uint64_t *status, int64_t tile, int64
 }
 
 template <int M, int MODE>
-__global__ void __launch_bounds__(kBlock) k_wave_merge(Operands op, int64_t *counters, uint64_t *status,
+__global__ void __launch_bounds__(kBlock, M == 10 ? 3 : (M <= 8 ? 4 : 1)) k_wave_merge(Operands op, int64_t *counters, uint64_t *status,
                                                        int32_t *cnt_out, int64_t *c_rp, int32_t *c_col,
                                                        double *c_val, int64_t c_capacity, int stage) {
   extern __shared__ __align__(16) unsigned char wm_lds[];
@@ -1793,7 +1810,9 @@ hipError_t launch_wave_merge(const Operands &op, int mode, int merge_lists, int 
   const int64_t blocks = (op.rows + kBlock - 1) / kBlock;
   switch (merge_lists) {
     case 4: return launch_wave_merge_m<4>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
+    case 6: return launch_wave_merge_m<6>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
     case 8: return launch_wave_merge_m<8>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
+    case 10: return launch_wave_merge_m<10>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
     case 16: return launch_wave_merge_m<16>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
     default: return hipErrorInvalidValue;
   }
