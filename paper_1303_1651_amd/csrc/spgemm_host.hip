@@ -159,6 +159,7 @@ struct spgemm_plan {
   int merge_only;      // every row takes the register-merge tier: row-per-thread kernels
   int merge_m;         // lists of the row-per-thread merge (4, 6, 8, 10 or 16)
   int merge_stage;     // staged entries per merge wave
+  int merge_off;       // one pass sized without the register-merge tier
   spgemm_info info;
   hipError_t last_err;
   const spgemm_model *model;
@@ -234,6 +235,7 @@ constexpr int64_t kMergeStageMax = 2048;
 // pass (copied out with the tile's other rows); larger rows are written to C
 // by their own wave directly.
 constexpr int kStageRowMax = 128;
+constexpr int64_t kMergeFewRows = 64;   // merge rows under 1/64 of the rows: one pass without them
 constexpr int64_t kSpillMin = 4096;   // smallest spill arena (entries)
 
 // Sizing of one pass (tiers, capacities, tile costs) plus tile bounds.
@@ -258,7 +260,7 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   sp.stage = stage;
   sp.stage_row_max = stage_row_max(p, mode);
   sp.merge_lists = p->tune.merge_lists;
-  sp.merge_max = std::min(p->tune.merge_max_nnz, stage / 2);
+  sp.merge_max = p->merge_off ? 0 : std::min(p->tune.merge_max_nnz, stage / 2);
   sp.dense_ratio = p->tune.dense_ratio;
   sp.margin = p->tune.margin;
   sp.slack = p->tune.slack;
@@ -630,6 +632,14 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
         return fail(SPGEMM_E_HIP);
     }
     st = size_pass(p, p->first_mode, s);
+    // a one pass with only a handful of merge rows is sized again without
+    // the merge tier: the tile kernel that also merges holds more registers
+    // (fewer resident waves) for every tile
+    if (st == SPGEMM_OK && p->first_mode == kOnePass && p->info.rows_merge > 0 &&
+        p->info.rows_merge * kMergeFewRows < A->rows) {
+      p->merge_off = 1;
+      st = size_pass(p, p->first_mode, s);
+    }
     if (st != SPGEMM_OK) return fail(st);
     if (p->first_mode == kOnePass &&
         launch_scan_i32(p->pa.cap, p->pa.pad_rp, A->rows, p->pa.scan_status, p->pa.counters + kCtrScanTicket,
