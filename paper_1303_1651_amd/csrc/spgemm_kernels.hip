@@ -953,12 +953,16 @@ struct WaveTable {
   int32_t lo;
   uint32_t shift;  // 32 - log2(T)
   bool dense;
+  // hashed tables whose columns minus lo, shifted left by log2(T), stay
+  // below 2^31: a key and its slot sort together as one 32-bit word
+  bool packs;
   __device__ __forceinline__ int32_t home(int32_t j) const {
     return dense ? j - lo : (int32_t)(((uint32_t)j * 0x9E3779B1u) >> shift);
   }
 };
 
-__device__ __forceinline__ WaveTable wave_table(int32_t *keys, double *vals, uint32_t inf, int32_t lo) {
+__device__ __forceinline__ WaveTable wave_table(int32_t *keys, double *vals, uint32_t inf, int32_t lo,
+                                                int32_t b_cols) {
   WaveTable t;
   t.keys = keys;
   t.vals = vals;
@@ -966,6 +970,7 @@ __device__ __forceinline__ WaveTable wave_table(int32_t *keys, double *vals, uin
   t.dense = info_dense(inf);
   t.lo = lo;
   t.shift = t.dense ? 0u : (uint32_t)(32 - __builtin_ctz((unsigned)t.T));
+  t.packs = !t.dense && (((int64_t)b_cols - lo) << (32 - t.shift)) < ((int64_t)1 << 31);
   return t;
 }
 
@@ -1179,6 +1184,17 @@ __device__ __forceinline__ void wave_clear(const WaveTable &tb) {
 // E + e): partners within a lane are exchanged in registers, partners in
 // other lanes through a lane shuffle.  One instantiation per (block size K,
 // partner distance J) stage, so every register index is a constant.
+// The value of the lane whose index differs from this lane's in bit LM:
+// a DPP quad permutation for 1 and 2 (no trip through the LDS unit), a
+// swizzle within 32 lanes up to 16, a permute across the halves for 32.
+template <int LM>
+__device__ __forceinline__ int32_t xor_lane(int32_t v) {
+  if constexpr (LM == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad (1,0,3,2)
+  else if constexpr (LM == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // quad (2,3,0,1)
+  else if constexpr (LM < 32) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (LM << 10));      // lane ^ LM
+  else return __shfl_xor(v, LM, kWave);
+}
+
 template <int E, int K, int J>
 __device__ __forceinline__ void wave_bitonic_stage(int32_t (&x)[E]) {
   const int lane = threadIdx.x;
@@ -1188,7 +1204,7 @@ __device__ __forceinline__ void wave_bitonic_stage(int32_t (&x)[E]) {
     const bool lower = (lane & lm) == 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int32_t y = __shfl_xor(x[e], lm, kWave);
+      const int32_t y = xor_lane<lm>(x[e]);
       x[e] = (lower == up) ? min(x[e], y) : max(x[e], y);
     }
   } else {
@@ -1213,9 +1229,11 @@ __device__ __forceinline__ void wave_bitonic(int32_t (&x)[E]) {
 }
 
 // Sorted write-out of a hashed row whose n keys were compacted (in slot
-// order) to buf[0..n) in LDS: sort them there, then look every key up again
-// for its value and write (column, value) at positions 0..n-1 of ocol/oval
-// (at most lim), and empty the table.  ocol may be buf itself.
+// order) to buf[0..n) in LDS: sort them there, then take every key's value
+// from the slot its sorted word carries (or, where key and slot do not pack
+// into one word, look the key up again) and write (column, value) at
+// positions 0..n-1 of ocol/oval (at most lim), and empty the table.  ocol
+// may be buf itself.
 template <int E>
 __device__ void wave_sort_out(const WaveTable &tb, int32_t n, int32_t *buf, int32_t *ocol, double *oval,
                               int64_t lim) {
@@ -1235,12 +1253,22 @@ __device__ void wave_sort_out(const WaveTable &tb, int32_t n, int32_t *buf, int3
   }
   wave_sync();
   const int32_t m = (int32_t)min((int64_t)n, lim);
-  for (int32_t pos = lane; pos < m; pos += kWave) {
-    const int32_t key = buf[pos];
-    int32_t h = tb.home(key);
-    for (int32_t it = 0; it < tb.T && tb.keys[h] != key; ++it) h = (h + 1) & (tb.T - 1);
-    ocol[pos] = key;
-    oval[pos] = tb.vals[h];
+  if (tb.packs) {
+    // the sorted words carry each key's slot: no second probe
+    const int l2 = 32 - (int)tb.shift;
+    for (int32_t pos = lane; pos < m; pos += kWave) {
+      const int32_t w = buf[pos];
+      ocol[pos] = (w >> l2) + tb.lo;
+      oval[pos] = tb.vals[w & (tb.T - 1)];
+    }
+  } else {
+    for (int32_t pos = lane; pos < m; pos += kWave) {
+      const int32_t key = buf[pos];
+      int32_t h = tb.home(key);
+      for (int32_t it = 0; it < tb.T && tb.keys[h] != key; ++it) h = (h + 1) & (tb.T - 1);
+      ocol[pos] = key;
+      oval[pos] = tb.vals[h];
+    }
   }
   wave_sync();
   wave_clear(tb);
@@ -1279,7 +1307,7 @@ __device__ void wave_extract(const WaveTable &tb, int32_t n, int32_t *buf, int32
     const int32_t key = q < tb.T ? tb.keys[q] : kEmpty;
     const bool occ = key != kEmpty;
     const uint64_t bal = ballot(occ);
-    if (occ) buf[run + __popcll(bal & lt)] = key;
+    if (occ) buf[run + __popcll(bal & lt)] = tb.packs ? ((key - tb.lo) << (32 - tb.shift)) | q : key;
     run += __popcll(bal);
   }
   wave_sync();
@@ -1408,7 +1436,7 @@ __global__ void __launch_bounds__(kWave, MODE == kOnePass && MERGE ? 2 : 4) k_wt
       const int r = __ffsll((unsigned long long)hm) - 1;
       hm &= hm - 1;
       const int64_t hrow = r0 + r;
-      const WaveTable tb = wave_table(tkeys, tvals, __shfl(inf, r, kWave), p.lo[hrow]);
+      const WaveTable tb = wave_table(tkeys, tvals, __shfl(inf, r, kWave), p.lo[hrow], op.b_cols);
       const int32_t c = wave_insert_row<VALUES>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], tb, re,
                                                 MODE == kOnePass ? full_flag : err);
       const int32_t cap_r = __shfl(capr, r, kWave);
