@@ -361,6 +361,8 @@ static spgemm_status run_big(spgemm_plan *p, int mode, bool overflow_list, void 
   bp.op = operands_of(p, a_val, b_val);
   bp.list = overflow_list ? p->pa.ovf : p->pa.big;
   bp.count_ctr = overflow_list ? kCtrOverflow : kCtrGlobal;
+  bp.huge_ctr = overflow_list ? -1 : kCtrHuge;
+  bp.list_len = p->A.rows;
   bp.ub = p->pa.f.ub;
   bp.maxb = p->pa.f.maxb;
   bp.cnt = p->pa.cnt;

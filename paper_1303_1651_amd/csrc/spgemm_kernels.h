@@ -48,6 +48,9 @@ enum Counter : int {
   kCtrPadTotal = 19,   // one pass: entries of the padded buffer (sum of capacities)
   kCtrSpill = 20,      // one pass: entries claimed in the spill arena
   kCtrWaveSpan = 21,   // largest output of 64 consecutive rows (merge staging)
+  kCtrHuge = 22,       // workgroup-tier rows of kHugeWork products or more (listed first)
+  kCtrBigTail = 23,    // the other workgroup-tier rows (listed from the end of the list)
+  kCtrBigTicket = 24,  // next list entry a k_big workgroup takes
   kNumCounters = 32
 };
 enum : int64_t {
@@ -108,6 +111,7 @@ struct PlanArrays {
 };
 
 constexpr int64_t kMinTable = 64;   // smallest hashed wave table (slots)
+constexpr int64_t kHugeWork = 8192;  // workgroup-tier rows of this many products start first
 
 struct WaveTileParams {
   Operands op;
@@ -148,6 +152,8 @@ struct BigParams {
   Operands op;
   const int32_t *list;      // rows to compute, counters[count_ctr] of them
   int count_ctr;
+  int huge_ctr;             // >= 0: the list holds counters[huge_ctr] rows at its
+  int64_t list_len;         //   front and the rest from its end (list_len entries)
   const int32_t *ub;
   const int32_t *maxb;
   int32_t *cnt;             // kSymbolic: output; kNumeric: exact counts

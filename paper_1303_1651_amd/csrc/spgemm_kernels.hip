@@ -405,14 +405,23 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
     n_tier[tier] = 1;
     capsum = c;
   }
-  // workgroup-tier rows: appended to the list, one atomic per wave
+  // workgroup-tier rows: rows of many products at the front of the list
+  // (their workgroups start first), the others from its end; one atomic per
+  // wave and kind
   const uint64_t bm = ballot(big);
   if (bm) {
-    int64_t base = 0;
-    if (lane_id() == 0)
-      base = (int64_t)atomicAdd((unsigned long long *)&pa.counters[kCtrGlobal], (unsigned long long)__popcll(bm));
-    base = __shfl(base, 0, kWave);
-    if (big) pa.big[base + __popcll(bm & lanemask_lt())] = (int32_t)i;
+    const bool huge = big && (int64_t)pa.f.ub[i] >= kHugeWork;
+    const uint64_t hb = ballot(huge), rb = bm & ~hb;
+    int64_t hbase = 0, rbase = 0;
+    if (lane_id() == 0) {
+      atomicAdd((unsigned long long *)&pa.counters[kCtrGlobal], (unsigned long long)__popcll(bm));
+      if (hb) hbase = (int64_t)atomicAdd((unsigned long long *)&pa.counters[kCtrHuge], (unsigned long long)__popcll(hb));
+      if (rb) rbase = (int64_t)atomicAdd((unsigned long long *)&pa.counters[kCtrBigTail], (unsigned long long)__popcll(rb));
+    }
+    hbase = __shfl(hbase, 0, kWave);
+    rbase = __shfl(rbase, 0, kWave);
+    if (huge) pa.big[hbase + __popcll(hb & lanemask_lt())] = (int32_t)i;
+    else if (big) pa.big[op.rows - 1 - (rbase + __popcll(rb & lanemask_lt()))] = (int32_t)i;
   }
   const int w = threadIdx.x / kWave;
   int64_t v[8] = {n_tier[kTierMerge], n_tier[kTierHash], n_tier[kTierEmpty], capsum, scratch > 0 ? 1 : 0,
@@ -451,6 +460,7 @@ hipError_t launch_size_rows(const Operands &op, const PlanArrays &pa, const Size
     ps.is_max[j] = (j >= 6);
   }
   hipError_t e = launch_fill_i64(pa.counters + kCtrGlobal, 0, 1, s);
+  if (e == hipSuccess) e = launch_fill_i64(pa.counters + kCtrHuge, 0, 2, s);
   if (e != hipSuccess) return e;
   if (op.rows <= 0) {
     e = launch_fill_i64(pa.partials, 0, 8, s);
@@ -708,6 +718,7 @@ __device__ __forceinline__ void wg_sync_global() {
 }
 
 // Write the sorted row held by an LDS table (G lanes).
+constexpr int kDupSlots = 1024;   // LDS set of a batch's table slots (ordered values)
 struct WgScratch {
   int64_t pref[kBlock + 1];
   int64_t bs[kBlock];
@@ -715,6 +726,8 @@ struct WgScratch {
   int64_t wtot[kWavesPerBlock + 1];
   int32_t cnt, dmax;
   int64_t run;
+  int32_t dset[kDupSlots];
+  int32_t first, last;   // entries of an ordered chunk
 };
 
 // Products of the row enumerated flat over the workgroup, 256 A entries at
@@ -813,14 +826,25 @@ __device__ __forceinline__ void wave_mem_wait() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Orders the LDS accesses of the lanes of one wave (a wave's LDS
+// instructions execute in issue order): a fence at wavefront scope keeps the
+// compiler from moving memory operations across, without waiting for
+// outstanding global loads.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Values of the row into the table built by wg_global_keys.  Ordered: the
-// first wave takes 64 / W entries of A per step (W lanes over each B row,
-// W the next power of two >= the longest selected B row, 16..64), loads a
-// few steps ahead, and the entries of one step update their slots in A's
-// stored order (one sub-step each), so every slot is accumulated in A's
-// column order.  Fast: every product at once with atomic adds.
-__device__ void wg_global_values(const Operands &op, int64_t row, int32_t maxb, const int32_t *keys,
-                                 double *vals, int64_t alloc, const RowHash &hs, WgScratch &ws, bool fast) {
+// products are taken in A's stored order, 256 at a time over the workgroup
+// (entries of A 256 at a time, their B rows enumerated flat).  Products of
+// one chunk that share no slot (checked through an LDS set) update their
+// slots at once; a chunk where a slot repeats updates entry by entry.  The
+// stores of a chunk complete before the next chunk reads, so every slot is
+// accumulated in A's column order.  Fast: every product at once with atomic
+// adds.
+__device__ void wg_global_values(const Operands &op, int64_t row, const int32_t *keys, double *vals,
+                                 int64_t alloc, const RowHash &hs, WgScratch &ws, bool fast) {
   if (fast) {
     wg_for_products(op, row, ws, [&](int64_t bpos, double av) {
       int32_t j = op.b_col[bpos];
@@ -832,54 +856,89 @@ __device__ void wg_global_values(const Operands &op, int64_t row, int32_t maxb, 
       }
       if (s >= 0) atomicAdd(&vals[s], p);
     });
-  } else if (threadIdx.x < kWave) {
-    constexpr int PF = 4;
-    const int lane = threadIdx.x;
-    const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
-    int lw = 4;
-    while ((1 << lw) < maxb && lw < 6) ++lw;
-    const int W = 1 << lw, per = kWave >> lw, sub = lane >> lw, bp = lane & (W - 1);
-    for (int64_t e0 = as; e0 < ae; e0 += (int64_t)per * PF) {
-      int64_t bs[PF];
-      int32_t bl[PF], jj[PF];
-      double av[PF], bb[PF];
-#pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        const int64_t e = e0 + (int64_t)u * per + sub;
-        bs[u] = 0;
-        bl[u] = 0;
-        av[u] = 0.0;
-        if (e < ae) {
-          const int32_t k = op.a_col[e];
-          av[u] = op.a_val[e];
-          bs[u] = op.b_rp[k];
-          bl[u] = (int32_t)(op.b_rp[k + 1] - bs[u]);
+    wg_sync_global();
+    return;
+  }
+  const int t = threadIdx.x;
+  for (int q = t; q < kDupSlots; q += kBlock) ws.dset[q] = -1;
+  const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
+  for (int64_t eb = as; eb < ae; eb += kBlock) {
+    const int64_t e = eb + t;
+    int64_t bs = 0, bl = 0;
+    double av = 0.0;
+    if (e < ae) {
+      const int32_t k = op.a_col[e];
+      av = op.a_val[e];
+      bs = op.b_rp[k];
+      bl = op.b_rp[k + 1] - bs;
+    }
+    int64_t tot;
+    const int64_t ex = block_exclusive_sum(bl, ws.wtot, &tot);
+    ws.pref[t] = ex;
+    ws.bs[t] = bs;
+    ws.av[t] = av;
+    __syncthreads();
+    for (int64_t q0 = 0; q0 < tot; q0 += kBlock) {
+      const int64_t q = q0 + t;
+      int ent = kBlock;   // the product's entry within this block of A entries
+      int64_t sl = -1;
+      double a = 0.0, b = 0.0;
+      if (q < tot) {
+        int lo = 0, hi = kBlock - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (ws.pref[mid] <= q) lo = mid;
+          else hi = mid - 1;
         }
+        ent = lo;
+        const int64_t bpos = ws.bs[lo] + (q - ws.pref[lo]);
+        a = ws.av[lo];
+        b = op.b_val[bpos];
+        sl = global_find(keys, alloc, hs, op.b_col[bpos]);
       }
-#pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        const bool live = bp < bl[u];
-        jj[u] = live ? op.b_col[bs[u] + bp] : kEmpty;
-        bb[u] = live ? op.b_val[bs[u] + bp] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        if (e0 + (int64_t)u * per >= ae) continue;   // uniform
-        const int64_t s = jj[u] != kEmpty ? global_find(keys, alloc, hs, jj[u]) : -1;
-        for (int q = 0; q < per; ++q) {
-          if (sub == q && s >= 0) gstored(vals + s, mul_add_rn(gloadd(vals + s), av[u], bb[u]));
-          wave_mem_wait();
-        }
-        if (W == kWave && bl[u] > kWave) {
-          for (int32_t f = kWave + lane; f < bl[u]; f += kWave) {
-            const int32_t j = op.b_col[bs[u] + f];
-            const int64_t sl = global_find(keys, alloc, hs, j);
-            if (sl >= 0) gstored(vals + sl, mul_add_rn(gloadd(vals + sl), av[u], op.b_val[bs[u] + f]));
+      // does a slot repeat within the chunk?
+      bool dup = false;
+      int32_t at = -1;
+      if (sl >= 0) {
+        uint32_t h = ((uint32_t)sl * 0x9E3779B1u) >> (32 - 10);
+        while (true) {
+          const int32_t old = atomicCAS(&ws.dset[h], -1, (int32_t)sl);
+          if (old == -1) {
+            at = (int32_t)h;
+            break;
           }
+          if (old == (int32_t)sl) {
+            dup = true;
+            break;
+          }
+          h = (h + 1) & (kDupSlots - 1);
+        }
+      }
+      const bool ordered = __syncthreads_or(dup ? 1 : 0) != 0;
+      if (at >= 0) ws.dset[at] = -1;
+      if (!ordered) {
+        if (sl >= 0) gstored(vals + sl, mul_add_rn(gloadd(vals + sl), a, b));
+        wave_mem_wait();
+        __syncthreads();
+      } else {
+        // entry by entry: the chunk's entries lie in [first, last] (its
+        // first product is thread 0's)
+        if (t == 0) {
+          ws.first = ent;
+          ws.last = 0;
+        }
+        __syncthreads();
+        if (q < tot) atomicMax(&ws.last, ent);
+        __syncthreads();
+        const int first = ws.first, last = ws.last;
+        for (int u = first; u <= last; ++u) {
+          if (ent == u && sl >= 0) gstored(vals + sl, mul_add_rn(gloadd(vals + sl), a, b));
           wave_mem_wait();
+          __syncthreads();
         }
       }
     }
+    __syncthreads();
   }
   wg_sync_global();
 }
@@ -911,9 +970,75 @@ __device__ void wg_sort_runs(int32_t *keys, double *vals, int64_t alloc) {
   wg_sync_global();
 }
 
+// Sorted write-out through LDS, kExtChunk slots at a time: a chunk is read
+// with coalesced loads (with kExtPad slots beyond it) and ends at the first
+// empty slot at or after kExtChunk, so no run crosses chunks; its runs are
+// sorted in LDS (one thread per run), and its occupied slots are compacted
+// to the output.  Returns false, having written nothing final, when a run is
+// longer than the pad (the caller then sorts the runs in device memory).
+constexpr int kExtChunk = 2048, kExtPad = 256;
+struct ExtLds {
+  int32_t k[kExtChunk + kExtPad];
+  double v[kExtChunk + kExtPad];
+};
+
+__device__ bool wg_extract_chunked(const int32_t *keys, const double *vals, int64_t alloc, WgScratch &ws,
+                                   ExtLds &xl, int32_t *out_col, double *out_val, int64_t lim) {
+  const int t = threadIdx.x;
+  int64_t c0 = 0, run = 0;
+  while (c0 < alloc) {
+    const int n = (int)min((int64_t)(kExtChunk + kExtPad), alloc - c0);
+    for (int i = t; i < n; i += kBlock) {
+      xl.k[i] = gload(keys + c0 + i);
+      xl.v[i] = vals ? gloadd(vals + c0 + i) : 0.0;
+    }
+    if (t == 0) ws.first = n;
+    __syncthreads();
+    // the chunk ends at the first empty slot from kExtChunk on
+    if (n > kExtChunk)
+      for (int i = kExtChunk + t; i < n; i += kBlock)
+        if (xl.k[i] == kEmpty) atomicMin(&ws.first, i);
+    __syncthreads();
+    const int end = ws.first;
+    if (end == n && c0 + n < alloc) return false;   // uniform: a run longer than the pad
+    for (int i = t; i < end; i += kBlock) {
+      if (xl.k[i] == kEmpty || (i > 0 && xl.k[i - 1] != kEmpty)) continue;
+      for (int q = i + 1; q < end && xl.k[q] != kEmpty; ++q) {
+        const int32_t k = xl.k[q];
+        const double v = xl.v[q];
+        int at = q;
+        while (at > i && xl.k[at - 1] > k) {
+          xl.k[at] = xl.k[at - 1];
+          xl.v[at] = xl.v[at - 1];
+          --at;
+        }
+        xl.k[at] = k;
+        xl.v[at] = v;
+      }
+    }
+    __syncthreads();
+    for (int i0 = 0; i0 < end; i0 += kBlock) {
+      const int i = i0 + t;
+      const int32_t key = i < end ? xl.k[i] : kEmpty;
+      const int64_t occ = key != kEmpty ? 1 : 0;
+      int64_t tot;
+      const int64_t ex = block_exclusive_sum(occ, ws.wtot, &tot);
+      if (occ && run + ex < lim) {
+        out_col[run + ex] = key;
+        if (out_val) out_val[run + ex] = xl.v[i];
+      }
+      run += tot;
+    }
+    c0 += end;
+    __syncthreads();
+  }
+  return true;
+}
+
 // Sorted write-out of a device table by the whole workgroup.
 __device__ void wg_global_extract(int32_t *keys, double *vals, int64_t alloc, int32_t dmax, WgScratch &ws,
-                                  int32_t *out_col, double *out_val, int64_t lim) {
+                                  ExtLds &xl, int32_t *out_col, double *out_val, int64_t lim) {
+  if (wg_extract_chunked(keys, vals, alloc, ws, xl, out_col, out_val, lim)) return;
   if (dmax > 0) wg_sort_runs(keys, vals, alloc);
   int64_t run = 0;
   for (int64_t c = 0; c < alloc; c += kBlock) {
@@ -974,14 +1099,6 @@ __device__ __forceinline__ WaveTable wave_table(int32_t *keys, double *vals, uin
   return t;
 }
 
-// Orders the LDS accesses of the lanes of one wave (the workgroup is one
-// wave, and a wave's LDS instructions execute in issue order): a fence at
-// wavefront scope keeps the compiler from moving memory operations across,
-// without waiting for outstanding global loads.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 // Claim or find column j; returns its slot.  A table sized by the rules of
 // k_size_rows never fills, so the probe always ends; a probe that would run
@@ -1635,14 +1752,24 @@ hipError_t launch_compact(const CompactParams &cp, hipStream_t s) {
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
   __shared__ WgScratch ws;
+  __shared__ ExtLds xl;
   const Operands &op = p.op;
   const int64_t nbig = p.counters[p.count_ctr];
   int32_t *gkeys = reinterpret_cast<int32_t *>(p.scratch + (size_t)blockIdx.x * (size_t)p.scratch_slots * 12);
   double *gvals = reinterpret_cast<double *>(p.scratch + (size_t)blockIdx.x * (size_t)p.scratch_slots * 12 +
                                              (size_t)p.scratch_slots * 4);
   int64_t *err = p.counters + kCtrError;
-  for (int64_t i = blockIdx.x; i < nbig; i += gridDim.x) {
-    const int64_t row = p.list[i];
+  const int64_t nh = p.huge_ctr >= 0 ? p.counters[p.huge_ctr] : nbig;
+  __shared__ int64_t s_i;
+  while (true) {
+    // the next row from the ticket: workgroups that finish early take more
+    if (threadIdx.x == 0)
+      s_i = (int64_t)atomicAdd((unsigned long long *)&p.counters[kCtrBigTicket], 1ull);
+    __syncthreads();
+    const int64_t i = s_i;
+    __syncthreads();
+    if (i >= nbig) break;
+    const int64_t row = i < nh ? p.list[i] : p.list[p.list_len - 1 - (i - nh)];
     const int64_t c = (MODE == kNumeric) ? (int64_t)p.cnt[row] : (int64_t)p.ub[row];
     const int64_t span = (int64_t)p.hi[row] - (int64_t)p.lo[row] + 1;
     bool dense;
@@ -1658,11 +1785,11 @@ __global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
       if (threadIdx.x == 0) p.cnt[row] = n;
     } else {
       if (threadIdx.x == 0 && n != c) atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
-      wg_global_values(op, row, p.maxb[row], gkeys, gvals, alloc, hs, ws, p.fast != 0);
+      wg_global_values(op, row, gkeys, gvals, alloc, hs, ws, p.fast != 0);
       const int64_t o = p.c_rp[row];
       const int64_t lim = max((int64_t)0, min((int64_t)n, p.c_capacity - o));
       if (threadIdx.x == 0 && lim < n) atomicOr((unsigned long long *)err, (unsigned long long)kErrCapacity);
-      wg_global_extract(gkeys, gvals, alloc, ws.dmax, ws, p.c_col + o, p.c_val + o, lim);
+      wg_global_extract(gkeys, gvals, alloc, ws.dmax, ws, xl, p.c_col + o, p.c_val + o, lim);
     }
     __syncthreads();
   }
@@ -1913,6 +2040,8 @@ hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists
 
 hipError_t launch_big_rows(const BigParams &bp, int mode, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
+  hipError_t e = launch_fill_i64(bp.counters + kCtrBigTicket, 0, 1, s);
+  if (e != hipSuccess) return e;
   if (mode == kSymbolic) hipLaunchKernelGGL(k_big<kSymbolic>, dim3(grid), dim3(kBlock), 0, s, bp);
   else hipLaunchKernelGGL(k_big<kNumeric>, dim3(grid), dim3(kBlock), 0, s, bp);
   return hipGetLastError();
