@@ -15,12 +15,15 @@ namespace spg {
 enum Tier : uint32_t { kTierEmpty = 0, kTierMerge = 1, kTierHash = 2, kTierGlobal = 3 };
 
 // info word of a row: bits 0-1 tier, bit 2 dense window, bits 3-31 table slots.
-__host__ __device__ inline uint32_t pack_info(uint32_t tier, bool dense, uint32_t slots) {
-  return tier | (dense ? 4u : 0u) | (slots << 3);
+// esc: a hashed-tier row of the numeric pass whose products are sorted as
+// they are (expand, sort, combine) instead of entering a hash table.
+__host__ __device__ inline uint32_t pack_info(uint32_t tier, bool dense, uint32_t slots, bool esc = false) {
+  return tier | (dense ? 4u : 0u) | (esc ? 8u : 0u) | (slots << 4);
 }
 __host__ __device__ inline uint32_t info_tier(uint32_t w) { return w & 3u; }
 __host__ __device__ inline bool info_dense(uint32_t w) { return (w >> 2) & 1u; }
-__host__ __device__ inline uint32_t info_slots(uint32_t w) { return w >> 3; }
+__host__ __device__ inline bool info_esc(uint32_t w) { return (w >> 3) & 1u; }
+__host__ __device__ inline uint32_t info_slots(uint32_t w) { return w >> 4; }
 
 // Pass kinds of the tile kernel.
 enum Mode : int { kSymbolic = 0, kNumeric = 1, kOnePass = 2 };

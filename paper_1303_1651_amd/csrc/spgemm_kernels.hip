@@ -294,6 +294,7 @@ __device__ __forceinline__ int64_t global_table_alloc(int64_t span, int64_t c, b
 __device__ __forceinline__ int64_t global_table_bound(int64_t c) { return 3 * c + 16; }
 
 constexpr int64_t kSortMax = 1024;   // keys a wave sorts in registers (64 lanes x 16)
+constexpr int64_t kEscMax = 512;    // products of an expand-sort row (64 lanes x 8)
 
 // Smallest power of two >= x, at least kMinTable.
 __device__ __forceinline__ int64_t table_pow2(int64_t x) {
@@ -371,12 +372,24 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
         // load is high only where the capacity is close to the bound)
         if (sp.mode == kOnePass && T > sp.table_max) T = table_pow2(ub + 1);
       }
+      // numeric rows whose products rarely share a column (the bound, not
+      // saturated, within a quarter of the count), whose B rows fit one wave
+      // and whose column offsets pack with a product index into one word:
+      // expand, sort, combine (T slots hold the products)
+      bool esc = false;
+      if (!dense && sp.mode == kNumeric && mx <= kWave && ub <= kEscMax && ub < op.b_cols && 4 * ub <= 5 * c) {
+        const int64_t te = table_pow2(ub);
+        if (te <= sp.table_max && (((int64_t)op.b_cols - pa.f.lo[i]) << __builtin_ctzll((uint64_t)te)) < ((int64_t)1 << 31)) {
+          esc = true;
+          T = te;
+        }
+      }
       // a hashed (not dense) row's keys are sorted in the wave's registers:
       // at most kSortMax of them (a table holds at most T)
       const int64_t most = sym ? 0 : (sp.mode == kNumeric ? c : min(ub, T));
       if (sp.table_max > 0 && T <= sp.table_max && (dense || most <= kSortMax)) {
         tier = kTierHash;
-        info = pack_info(kTierHash, dense, (uint32_t)T);
+        info = pack_info(kTierHash, dense, (uint32_t)T, esc);
         tmax = T;
         // small hashed rows are staged; larger ones are written straight to
         // C (or the padded buffer of the one pass)
@@ -1222,7 +1235,8 @@ __device__ __forceinline__ void insert_batch(const Operands &op, int64_t e0, int
 // start and length of the B row each selects, and its A value.
 struct RowEntries {
   int64_t *bs;
-  int32_t *bl;
+  int32_t *bl;   // expand-sort rows: the length (<= 64) in the low 16 bits,
+                 // the index of the entry's first product above
   double *av;
 };
 
@@ -1391,6 +1405,135 @@ __device__ void wave_sort_out(const WaveTable &tb, int32_t n, int32_t *buf, int3
   wave_clear(tb);
 }
 
+// Sorts buf[0..n) (n <= 64 E) ascending in the wave's registers.
+template <int E>
+__device__ __forceinline__ void wave_sort_buf(int32_t *buf, int32_t n) {
+  const int lane = threadIdx.x;
+  int32_t x[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int32_t pos = lane * E + e;
+    x[e] = pos < n ? buf[pos] : kColMax;
+  }
+  wave_sync();
+  wave_bitonic<E>(x);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int32_t pos = lane * E + e;
+    if (pos < n) buf[pos] = x[e];
+  }
+  wave_sync();
+}
+
+constexpr int kEscSteps = 2;
+
+// Expand, sort, combine: the numeric row [as, ae) (every selected B row at
+// most 64 long, at most kEscMax products) without a hash table.  Each
+// product is stored at its index pi (A's stored order, then B's) as the
+// rounded product a*b in pv[pi] and the word ((column - lo) << log2 T) | pi
+// in buf[pi]; sorting the words orders the products by column and, within a
+// column, by pi, i.e. in A's order.  Each run of one column sums its
+// products from +0.0 in that order, exactly the row-major kernel's
+// accumulation (Section IV-A).  Writes the row (at most lim entries) to
+// ocol/oval in column order; returns its size.
+__device__ int32_t wave_esc_row(const Operands &op, int64_t as, int64_t ae, int32_t maxb, int32_t lo, int32_t T,
+                                const RowEntries &re, int32_t *buf, double *pv, int32_t *ocol, double *oval,
+                                int64_t lim) {
+  const int lane = threadIdx.x;
+  const int bits = __builtin_ctz((unsigned)T);
+  const int lw = lanes_log2(maxb);
+  const int per = kWave >> lw, sub = lane >> lw, bp = lane & ((1 << lw) - 1);
+  int32_t pbase = 0;
+  for (int64_t g0 = as; g0 < ae; g0 += kWave) {
+    const int gn = (int)min((int64_t)kWave, ae - g0);
+    int32_t bl = 0;
+    int64_t bs = 0;
+    if (lane < gn) {
+      const int32_t k = op.a_col[g0 + lane];
+      bs = op.b_rp[k];
+      bl = (int32_t)(op.b_rp[k + 1] - bs);
+    }
+    const int32_t inc = wave_inclusive_sum32(bl);
+    if (lane < gn) {
+      re.bs[lane] = bs;
+      re.bl[lane] = bl | ((pbase + inc - bl) << 16);
+      re.av[lane] = op.a_val[g0 + lane];
+    }
+    pbase += __shfl(inc, kWave - 1, kWave);
+    wave_sync();
+    // kEscSteps steps of `per` entries at a time, their loads in flight
+    // together
+    for (int e0 = 0; e0 < gn; e0 += kEscSteps * per) {
+      int32_t jj[kEscSteps], pi[kEscSteps];
+      double ab[kEscSteps], bb[kEscSteps];
+#pragma unroll
+      for (int u = 0; u < kEscSteps; ++u) {
+        const int e = e0 + u * per + sub;
+        pi[u] = -1;
+        const int32_t w = e < gn ? re.bl[e] : 0;
+        if (bp < (w & 0xffff)) {
+          const int64_t at = re.bs[e] + bp;
+          jj[u] = op.b_col[at];
+          bb[u] = op.b_val[at];
+          ab[u] = re.av[e];
+          pi[u] = (w >> 16) + bp;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kEscSteps; ++u) {
+        if (pi[u] < 0) continue;
+        buf[pi[u]] = ((jj[u] - lo) << bits) | pi[u];
+        double p;
+        {
+#pragma clang fp contract(off)
+          p = ab[u] * bb[u];
+        }
+        pv[pi[u]] = p;
+      }
+    }
+    wave_sync();
+  }
+  const int32_t n = pbase;
+  if (n <= 64) wave_sort_buf<1>(buf, n);
+  else if (n <= 128) wave_sort_buf<2>(buf, n);
+  else if (n <= 256) wave_sort_buf<4>(buf, n);
+  else wave_sort_buf<8>(buf, n);   // n <= kEscMax
+  // combine the runs of one column; the rank of a run's head is its place
+  const uint64_t lt = lanemask_lt();
+  int32_t run = 0;
+  for (int32_t q0 = 0; q0 < n; q0 += kWave) {
+    const int32_t q = q0 + lane;
+    int32_t w = 0;
+    bool head = false;
+    if (q < n) {
+      w = buf[q];
+      head = q == 0 || (buf[q - 1] >> bits) != (w >> bits);
+    }
+    const uint64_t hb = ballot(head);
+    if (head) {
+      const int32_t key = w >> bits;
+      double v;
+      {
+#pragma clang fp contract(off)
+        v = 0.0 + pv[w & (T - 1)];
+        for (int32_t t = q + 1; t < n; ++t) {
+          const int32_t w2 = buf[t];
+          if ((w2 >> bits) != key) break;
+          v = v + pv[w2 & (T - 1)];
+        }
+      }
+      const int32_t rank = run + __popcll(hb & lt);
+      if (rank < lim) {
+        ocol[rank] = key + lo;
+        oval[rank] = v;
+      }
+    }
+    run += __popcll(hb);
+  }
+  wave_sync();
+  return run;
+}
+
 // Writes the row held by the table in column order to ocol/oval (at most
 // lim entries) and leaves the table empty.  buf: LDS room for n keys (may be
 // ocol itself when that is in LDS).
@@ -1476,7 +1619,7 @@ __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots,
 }
 
 template <int MODE, int M, bool MERGE>
-__global__ void __launch_bounds__(kWave, MODE == kOnePass && MERGE ? 2 : 4) k_wt(WaveTileParams p) {
+__global__ void __launch_bounds__(kWave, MODE == kOnePass && MERGE ? 2 : (MERGE && M == 8 ? 3 : 4)) k_wt(WaveTileParams p) {
   constexpr bool VALUES = (MODE != kSymbolic);
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x;
@@ -1553,6 +1696,31 @@ __global__ void __launch_bounds__(kWave, MODE == kOnePass && MERGE ? 2 : 4) k_wt
       const int r = __ffsll((unsigned long long)hm) - 1;
       hm &= hm - 1;
       const int64_t hrow = r0 + r;
+      if (MODE == kNumeric && info_esc(__shfl(inf, r, kWave))) {
+        // expand, sort, combine: no table; the row goes straight to its place
+        const int32_t cap_r = __shfl(capr, r, kWave);
+        int32_t *oc;
+        double *ov;
+        int64_t lim;
+        if (__shfl(staged ? 1 : 0, r, kWave)) {
+          const int32_t so = __shfl(soff, r, kWave);
+          oc = scol + so;
+          ov = sval + so;
+          lim = cap_r;
+        } else {
+          const int64_t o = base + __shfl(pos, r, kWave);
+          oc = p.c_col + o;
+          ov = p.c_val + o;
+          lim = max((int64_t)0, min((int64_t)cap_r, p.c_capacity - o));
+        }
+        const int32_t c = wave_esc_row(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], p.lo[hrow],
+                                       (int32_t)info_slots(__shfl(inf, r, kWave)), re, buf, tvals, oc, ov, lim);
+        if (lane == r) {
+          n = c;
+          fits = c <= cap_r;
+        }
+        continue;
+      }
       const WaveTable tb = wave_table(tkeys, tvals, __shfl(inf, r, kWave), p.lo[hrow], op.b_cols);
       const int32_t c = wave_insert_row<VALUES>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], tb, re,
                                                 MODE == kOnePass ? full_flag : err);
