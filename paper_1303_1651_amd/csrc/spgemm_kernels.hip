@@ -82,8 +82,8 @@ hipError_t launch_validate(const int64_t *rp, const int32_t *col, int64_t rows, 
 // C_i), and the smallest/largest column any selected B row touches (the
 // "MinMax" region of Section IV-B).  The exact int64 sum of the counts is
 // the paper's multiplication count of Section III.
-// Features of row i (see above); rows of at most 8 stored entries issue
-// all their loads at once (two dependent gather rounds per row).
+// Features of row i (see above); the stored entries are taken eight at a
+// time, each group's loads issued at once (three dependent gather rounds).
 template <bool SPAN>
 __device__ __forceinline__ void row_features(const Operands &op, int64_t i, int64_t &m, int64_t &ub, int32_t &mx,
                                              int32_t &lo, int32_t &hi) {
@@ -93,37 +93,32 @@ __device__ __forceinline__ void row_features(const Operands &op, int64_t i, int6
   mx = 0;
   lo = 0x7fffffff;
   hi = -1;
-  if (m <= 8) {
+  // eight entries at a time: their gathers are in flight together
+  for (int64_t q0 = s; q0 < e; q0 += 8) {
+    const int cnt = (int)min((int64_t)8, e - q0);
     int32_t k[8];
     int64_t bs[8], be[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) k[q] = q < m ? op.a_col[s + q] : 0;
+    for (int q = 0; q < 8; ++q) k[q] = q < cnt ? op.a_col[q0 + q] : 0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      bs[q] = q < m ? op.b_rp[k[q]] : 0;
-      be[q] = q < m ? op.b_rp[k[q] + 1] : 0;
+      bs[q] = q < cnt ? op.b_rp[k[q]] : 0;
+      be[q] = q < cnt ? op.b_rp[k[q] + 1] : 0;
+    }
+    int32_t l8[8], h8[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const bool has = SPAN && be[q] > bs[q];
+      l8[q] = has ? op.b_col[bs[q]] : 0x7fffffff;
+      h8[q] = has ? op.b_col[be[q] - 1] : -1;
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int32_t len = (int32_t)(be[q] - bs[q]);
       ub += len;
       mx = max(mx, len);
-      if (SPAN && len > 0) {
-        lo = min(lo, op.b_col[bs[q]]);
-        hi = max(hi, op.b_col[be[q] - 1]);
-      }
-    }
-  } else {
-    for (int64_t q = s; q < e; ++q) {
-      const int32_t k = op.a_col[q];
-      const int64_t bs = op.b_rp[k], be = op.b_rp[k + 1];
-      const int32_t len = (int32_t)(be - bs);
-      ub += len;
-      mx = max(mx, len);
-      if (SPAN && len > 0) {
-        lo = min(lo, op.b_col[bs]);
-        hi = max(hi, op.b_col[be - 1]);
-      }
+      lo = min(lo, l8[q]);
+      hi = max(hi, h8[q]);
     }
   }
 }
