@@ -127,6 +127,52 @@ def test_negative_zero_becomes_positive_zero():
             assert bits(got[2])[0] == bits(0.0)
 
 
+def _signed_zero_rows(seed):
+    # rows of 12 entries whose B rows draw their columns from a pool of 1,000
+    # scattered columns: a few products per row share a column, the column
+    # region is wide (hashed, not dense), and the values make signed zeros
+    # and order-sensitive sums (the numeric pass sorts such rows' products)
+    rng = np.random.default_rng(seed)
+    m, k, n, per = 200, 4096, 100000, 12
+    pool = np.sort(rng.choice(n, 1000, replace=False)).astype(np.int32)
+
+    def mat(rows, cols, choose, vals):
+        rp = np.arange(rows + 1, dtype=np.int64) * per
+        col = np.concatenate([np.sort(choose()) for _ in range(rows)]).astype(np.int32)
+        return synth.CSR(rows, cols, rp, col, rng.choice(vals, rows * per))
+    A = mat(m, k, lambda: rng.choice(k, per, replace=False), np.array([-0.0, 1.0, -1.0, 1e16, -1e16, 3.0]))
+    B = mat(k, n, lambda: rng.choice(pool, per, replace=False), np.array([0.0, 2.0, -0.5, 1.0, -0.0]))
+    return A, B
+
+
+@pytest.mark.parametrize("tier", ["default", "hash_only", "small_table"])
+def test_signed_zeros_and_order_in_sorted_product_rows(tier):
+    A, B = _signed_zero_rows(7)
+    want = oracle.spgemm(A, B)
+    got = gpu_product(A, B, "exact", tuning=TIERS[tier])
+    assert_bit_exact(got, want)
+    assert np.any(np.signbit(A.val)) and not np.any(np.signbit(want[2][want[2] == 0.0]))
+
+
+@pytest.mark.parametrize("sizer", SIZERS)
+def test_workgroup_tier_row_with_a_long_run(sizer):
+    # one row of 2,000 columns, 500 of them consecutive in the middle of a
+    # wide region: in the workgroup tier's order-preserving table they share
+    # a few home slots, so one run of occupied slots crosses the boundary of
+    # the LDS chunks of the sorted write-out by more than their pad
+    rng = np.random.default_rng(3)
+    n = 1_000_000
+    spread = rng.choice(np.setdiff1d(np.arange(n), np.arange(500_000, 500_500)), 1500, replace=False)
+    cols = np.sort(np.concatenate([spread, np.arange(500_000, 500_500)])).astype(np.int32)
+    B = synth.CSR(2, n, np.array([0, cols.size, cols.size + 1]), np.concatenate([cols, [7]]).astype(np.int32),
+                  rng.uniform(-1, 1, cols.size + 1))
+    A = synth.CSR(3, 2, np.array([0, 2, 3, 3]), np.array([0, 1, 0], np.int32), np.array([1.5, -2.0, 0.25]))
+    want = oracle.spgemm(A, B)
+    got = gpu_product(A, B, sizer, tuning=TIERS["global_only"])
+    assert_bit_exact(got, want)
+    assert got[3]["rows_global"] >= 2
+
+
 @pytest.mark.parametrize("m,k,n", [(0, 0, 0), (0, 5, 3), (4, 0, 3), (4, 5, 0), (5, 4, 3)])
 def test_empty_operands(m, k, n):
     A = synth.CSR(m, k, np.zeros(m + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
