@@ -54,6 +54,7 @@ enum Counter : int {
   kCtrHuge = 22,       // workgroup-tier rows of kHugeWork products or more (listed first)
   kCtrBigTail = 23,    // the other workgroup-tier rows (listed from the end of the list)
   kCtrBigTicket = 24,  // next list entry a k_big workgroup takes
+  kCtrEsc = 25,        // numeric sizing: hashed rows taken by expand-sort-combine
   kNumCounters = 32
 };
 enum : int64_t {
@@ -192,7 +193,8 @@ hipError_t launch_tile_bounds(const int64_t *cost, int64_t rows, int64_t half_po
                               int32_t *tile_row, int64_t *counters, hipStream_t s);
 size_t wave_tile_lds(int mode, int table_slots, int stage_slots);
 // has_merge: some row of the pass takes the merge tier
-hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, hipStream_t s);
+hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, bool esc_only,
+                             hipStream_t s);
 hipError_t launch_compact(const CompactParams &cp, hipStream_t s);
 hipError_t launch_big_rows(const BigParams &bp, int mode, int grid, hipStream_t s);
 hipError_t launch_sum_partials(const int64_t *partials, int64_t nblocks, int n, int stride, const int32_t *dst,

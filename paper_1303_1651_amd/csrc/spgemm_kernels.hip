@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
   const int64_t mincost = sym ? 1 : (HT + kWave - 1) / kWave;
   int64_t n_tier[4] = {0, 0, 0, 0};
   int64_t capsum = 0, scratch = 0, tmax = 0;
-  bool big = false, staged = false;
+  bool big = false, staged = false, esc_row = false;
   if (i < op.rows) {
     const int32_t m = pa.f.nnz_a[i];
     const int64_t ub = pa.f.ub[i];
@@ -385,6 +385,7 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
       if (sp.table_max > 0 && T <= sp.table_max && (dense || most <= kSortMax)) {
         tier = kTierHash;
         info = pack_info(kTierHash, dense, (uint32_t)T, esc);
+        esc_row = esc;
         tmax = T;
         // small hashed rows are staged; larger ones are written straight to
         // C (or the padded buffer of the one pass)
@@ -413,6 +414,10 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
     n_tier[tier] = 1;
     capsum = c;
   }
+  // expand-sort rows, one atomic per wave
+  const uint64_t eb = ballot(esc_row);
+  if (eb && lane_id() == 0)
+    atomicAdd((unsigned long long *)&pa.counters[kCtrEsc], (unsigned long long)__popcll(eb));
   // workgroup-tier rows: rows of many products at the front of the list
   // (their workgroups start first), the others from its end; one atomic per
   // wave and kind
@@ -469,6 +474,7 @@ hipError_t launch_size_rows(const Operands &op, const PlanArrays &pa, const Size
   }
   hipError_t e = launch_fill_i64(pa.counters + kCtrGlobal, 0, 1, s);
   if (e == hipSuccess) e = launch_fill_i64(pa.counters + kCtrHuge, 0, 2, s);
+  if (e == hipSuccess) e = launch_fill_i64(pa.counters + kCtrEsc, 0, 1, s);
   if (e != hipSuccess) return e;
   if (op.rows <= 0) {
     e = launch_fill_i64(pa.partials, 0, 8, s);
@@ -1613,8 +1619,11 @@ __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots,
   return L;
 }
 
-template <int MODE, int M, bool MERGE>
-__global__ void __launch_bounds__(kWave, MODE == kOnePass && MERGE ? 2 : (MERGE && M == 8 ? 3 : 4)) k_wt(WaveTileParams p) {
+// ESCO: every hashed row of the launch is an expand-sort row (numeric pass,
+// no merge rows): the table path is not compiled, which frees registers.
+template <int MODE, int M, bool MERGE, bool ESCO = false>
+__global__ void __launch_bounds__(kWave, ESCO ? 5 : (MODE == kOnePass && MERGE ? 2 : (MERGE && M == 8 ? 3 : 4)))
+k_wt(WaveTileParams p) {
   constexpr bool VALUES = (MODE != kSymbolic);
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x;
@@ -1691,7 +1700,7 @@ __global__ void __launch_bounds__(kWave, MODE == kOnePass && MERGE ? 2 : (MERGE 
       const int r = __ffsll((unsigned long long)hm) - 1;
       hm &= hm - 1;
       const int64_t hrow = r0 + r;
-      if (MODE == kNumeric && info_esc(__shfl(inf, r, kWave))) {
+      if (MODE == kNumeric && (ESCO || info_esc(__shfl(inf, r, kWave)))) {
         // expand, sort, combine: no table; the row goes straight to its place
         const int32_t cap_r = __shfl(capr, r, kWave);
         int32_t *oc;
@@ -2169,16 +2178,16 @@ size_t wave_tile_lds(int mode, int table_slots, int stage_slots) {
   return wave_lds_layout(mode != kSymbolic, table_slots, stage_slots).total;
 }
 
-template <int MODE, int M, bool MERGE>
+template <int MODE, int M, bool MERGE, bool ESCO = false>
 static hipError_t launch_wt_mm(const WaveTileParams &wp, size_t lds, hipStream_t s) {
-  const void *fn = reinterpret_cast<const void *>(&k_wt<MODE, M, MERGE>);
+  const void *fn = reinterpret_cast<const void *>(&k_wt<MODE, M, MERGE, ESCO>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   const int64_t grid = std::min<int64_t>(wp.ntiles, 0x7fffffff);
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_wt<MODE, M, MERGE>), dim3((unsigned)grid), dim3(kWave), lds, s, wp);
+  hipLaunchKernelGGL((k_wt<MODE, M, MERGE, ESCO>), dim3((unsigned)grid), dim3(kWave), lds, s, wp);
   return hipGetLastError();
 }
 
@@ -2191,8 +2200,10 @@ static hipError_t launch_wt_m(const WaveTileParams &wp, int mode, size_t lds, hi
   }
 }
 
-hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, hipStream_t s) {
+hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, bool esc_only,
+                             hipStream_t s) {
   const size_t lds = wave_tile_lds(mode, wp.table_slots, wp.stage_slots);
+  if (mode == kNumeric && esc_only && !has_merge) return launch_wt_mm<kNumeric, 4, false, true>(wp, lds, s);
   if (!has_merge) return launch_wt_m<4, false>(wp, mode, lds, s);
   switch (merge_lists) {
     case 4: return launch_wt_m<4, true>(wp, mode, lds, s);
