@@ -387,9 +387,9 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
         info = pack_info(kTierHash, dense, (uint32_t)T, esc);
         esc_row = esc;
         tmax = T;
-        // small hashed rows are staged; larger ones are written straight to
-        // C (or the padded buffer of the one pass)
-        if (!sym && c <= sp.stage_row_max) {
+        // small hashed rows are staged; larger ones and expand-sort rows are
+        // written straight to C (or the padded buffer of the one pass)
+        if (!sym && !esc && c <= sp.stage_row_max) {
           cost = max(min(c, HT), mincost);
           staged = true;
         }
@@ -840,6 +840,22 @@ __device__ __forceinline__ void wave_mem_wait() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Stores of C, which the product writes once and does not read back:
+// non-temporal (streaming) stores.  NT false: plain stores (LDS staging or
+// the one pass's padded buffer).  The choice is made at compile time: a
+// branch between the two kinds lets the compiler merge the stores and drop
+// the non-temporal hint.
+template <bool NT = true>
+__device__ __forceinline__ void put_c(int32_t *col, double *val, int64_t i, int32_t c, double v) {
+  if constexpr (NT) {
+    __builtin_nontemporal_store(c, col + i);
+    __builtin_nontemporal_store(v, val + i);
+  } else {
+    col[i] = c;
+    val[i] = v;
+  }
+}
+
 // Orders the LDS accesses of the lanes of one wave (a wave's LDS
 // instructions execute in issue order): a fence at wavefront scope keeps the
 // compiler from moving memory operations across, without waiting for
@@ -1038,8 +1054,8 @@ __device__ bool wg_extract_chunked(const int32_t *keys, const double *vals, int6
       int64_t tot;
       const int64_t ex = block_exclusive_sum(occ, ws.wtot, &tot);
       if (occ && run + ex < lim) {
-        out_col[run + ex] = key;
-        if (out_val) out_val[run + ex] = xl.v[i];
+        if (out_val) put_c(out_col, out_val, run + ex, key, xl.v[i]);
+        else out_col[run + ex] = key;
       }
       run += tot;
     }
@@ -1366,7 +1382,7 @@ __device__ __forceinline__ void wave_bitonic(int32_t (&x)[E]) {
 // into one word, look the key up again) and write (column, value) at
 // positions 0..n-1 of ocol/oval (at most lim), and empty the table.  ocol
 // may be buf itself.
-template <int E>
+template <int E, bool NT>
 __device__ void wave_sort_out(const WaveTable &tb, int32_t n, int32_t *buf, int32_t *ocol, double *oval,
                               int64_t lim) {
   const int lane = threadIdx.x;
@@ -1390,16 +1406,14 @@ __device__ void wave_sort_out(const WaveTable &tb, int32_t n, int32_t *buf, int3
     const int l2 = 32 - (int)tb.shift;
     for (int32_t pos = lane; pos < m; pos += kWave) {
       const int32_t w = buf[pos];
-      ocol[pos] = (w >> l2) + tb.lo;
-      oval[pos] = tb.vals[w & (tb.T - 1)];
+      put_c<NT>(ocol, oval, pos, (w >> l2) + tb.lo, tb.vals[w & (tb.T - 1)]);
     }
   } else {
     for (int32_t pos = lane; pos < m; pos += kWave) {
       const int32_t key = buf[pos];
       int32_t h = tb.home(key);
       for (int32_t it = 0; it < tb.T && tb.keys[h] != key; ++it) h = (h + 1) & (tb.T - 1);
-      ocol[pos] = key;
-      oval[pos] = tb.vals[h];
+      put_c<NT>(ocol, oval, pos, key, tb.vals[h]);
     }
   }
   wave_sync();
@@ -1437,6 +1451,7 @@ constexpr int kEscSteps = 2;
 // products from +0.0 in that order, exactly the row-major kernel's
 // accumulation (Section IV-A).  Writes the row (at most lim entries) to
 // ocol/oval in column order; returns its size.
+template <bool NT>
 __device__ int32_t wave_esc_row(const Operands &op, int64_t as, int64_t ae, int32_t maxb, int32_t lo, int32_t T,
                                 const RowEntries &re, int32_t *buf, double *pv, int32_t *ocol, double *oval,
                                 int64_t lim) {
@@ -1524,10 +1539,7 @@ __device__ int32_t wave_esc_row(const Operands &op, int64_t as, int64_t ae, int3
         }
       }
       const int32_t rank = run + __popcll(hb & lt);
-      if (rank < lim) {
-        ocol[rank] = key + lo;
-        oval[rank] = v;
-      }
+      if (rank < lim) put_c<NT>(ocol, oval, rank, key + lo, v);
     }
     run += __popcll(hb);
   }
@@ -1538,6 +1550,7 @@ __device__ int32_t wave_esc_row(const Operands &op, int64_t as, int64_t ae, int3
 // Writes the row held by the table in column order to ocol/oval (at most
 // lim entries) and leaves the table empty.  buf: LDS room for n keys (may be
 // ocol itself when that is in LDS).
+template <bool NT>
 __device__ void wave_extract(const WaveTable &tb, int32_t n, int32_t *buf, int32_t *ocol, double *oval,
                              int64_t lim) {
   const int lane = threadIdx.x;
@@ -1552,10 +1565,7 @@ __device__ void wave_extract(const WaveTable &tb, int32_t n, int32_t *buf, int32
       const uint64_t bal = ballot(occ);
       if (occ) {
         const int32_t rank = run + __popcll(bal & lt);
-        if (rank < lim) {
-          ocol[rank] = key;
-          oval[rank] = tb.vals[q];
-        }
+        if (rank < lim) put_c<NT>(ocol, oval, rank, key, tb.vals[q]);
         tb.keys[q] = kEmpty;
       }
       run += __popcll(bal);
@@ -1573,11 +1583,11 @@ __device__ void wave_extract(const WaveTable &tb, int32_t n, int32_t *buf, int32
   }
   wave_sync();
   // n <= kSortMax (k_size_rows sends larger hashed rows to the workgroup tier)
-  if (n <= 64) wave_sort_out<1>(tb, n, buf, ocol, oval, lim);
-  else if (n <= 128) wave_sort_out<2>(tb, n, buf, ocol, oval, lim);
-  else if (n <= 256) wave_sort_out<4>(tb, n, buf, ocol, oval, lim);
-  else if (n <= 512) wave_sort_out<8>(tb, n, buf, ocol, oval, lim);
-  else wave_sort_out<16>(tb, n, buf, ocol, oval, lim);
+  if (n <= 64) wave_sort_out<1, NT>(tb, n, buf, ocol, oval, lim);
+  else if (n <= 128) wave_sort_out<2, NT>(tb, n, buf, ocol, oval, lim);
+  else if (n <= 256) wave_sort_out<4, NT>(tb, n, buf, ocol, oval, lim);
+  else if (n <= 512) wave_sort_out<8, NT>(tb, n, buf, ocol, oval, lim);
+  else wave_sort_out<16, NT>(tb, n, buf, ocol, oval, lim);
 }
 
 // Tile kernel.  A tile is a run of at most 64 consecutive rows; its merge
@@ -1655,7 +1665,8 @@ k_wt(WaveTileParams p) {
     int64_t n = 0;
 
     // staged rows and their stage offsets (by capacity, in row order)
-    const bool staged = VALUES && ((MERGE && tier == kTierMerge) || (tier == kTierHash && capr <= p.stage_row_max));
+    const bool staged = VALUES && ((MERGE && tier == kTierMerge) ||
+                                   (tier == kTierHash && capr <= p.stage_row_max && !info_esc(inf)));
     const int32_t res = staged ? capr : 0;
     const int32_t sinc = wave_inclusive_sum32(res);
     const int32_t soff = sinc - res;
@@ -1701,24 +1712,14 @@ k_wt(WaveTileParams p) {
       hm &= hm - 1;
       const int64_t hrow = r0 + r;
       if (MODE == kNumeric && (ESCO || info_esc(__shfl(inf, r, kWave)))) {
-        // expand, sort, combine: no table; the row goes straight to its place
+        // expand, sort, combine: no table; the row (never staged) goes
+        // straight to its place in C
         const int32_t cap_r = __shfl(capr, r, kWave);
-        int32_t *oc;
-        double *ov;
-        int64_t lim;
-        if (__shfl(staged ? 1 : 0, r, kWave)) {
-          const int32_t so = __shfl(soff, r, kWave);
-          oc = scol + so;
-          ov = sval + so;
-          lim = cap_r;
-        } else {
-          const int64_t o = base + __shfl(pos, r, kWave);
-          oc = p.c_col + o;
-          ov = p.c_val + o;
-          lim = max((int64_t)0, min((int64_t)cap_r, p.c_capacity - o));
-        }
-        const int32_t c = wave_esc_row(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], p.lo[hrow],
-                                       (int32_t)info_slots(__shfl(inf, r, kWave)), re, buf, tvals, oc, ov, lim);
+        const int64_t o = base + __shfl(pos, r, kWave);
+        const int64_t lim = max((int64_t)0, min((int64_t)cap_r, p.c_capacity - o));
+        const int32_t c = wave_esc_row<true>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], p.lo[hrow],
+                                             (int32_t)info_slots(__shfl(inf, r, kWave)), re, buf, tvals, p.c_col + o,
+                                             p.c_val + o, lim);
         if (lane == r) {
           n = c;
           fits = c <= cap_r;
@@ -1756,11 +1757,11 @@ k_wt(WaveTileParams p) {
         wave_clear(tb);
       } else if (keep && __shfl(staged ? 1 : 0, r, kWave) && c <= cap_r) {
         const int32_t so = __shfl(soff, r, kWave);
-        wave_extract(tb, c, buf, scol + so, sval + so, c);
+        wave_extract<false>(tb, c, buf, scol + so, sval + so, c);
       } else {
         // straight to the row's place in C (or in the padded buffer)
         const int64_t rl = max((int64_t)0, min((int64_t)c, p.c_capacity - o));
-        wave_extract(tb, c, buf, p.c_col + o, p.c_val + o, rl);
+        wave_extract<MODE == kNumeric>(tb, c, buf, p.c_col + o, p.c_val + o, rl);
       }
       if (MODE == kOnePass && keep) {
         if (lane > r) hb += c;
@@ -1850,10 +1851,7 @@ k_wt(WaveTileParams p) {
     const bool in_order = ballot(valid && capr > 0 && !(staged && fits && soff == pos)) == 0ull;
     if (in_order) {
       const int64_t lim = max((int64_t)0, min(tile_len, p.c_capacity - base));
-      for (int64_t q = lane; q < lim; q += kWave) {
-        p.c_col[base + q] = scol[q];
-        p.c_val[base + q] = sval[q];
-      }
+      for (int64_t q = lane; q < lim; q += kWave) put_c(p.c_col, p.c_val, base + q, scol[q], sval[q]);
     } else {
       uint64_t sm = ballot(valid && staged && fits && n > 0);
       while (sm) {
@@ -1862,10 +1860,7 @@ k_wt(WaveTileParams p) {
         const int32_t so = __shfl(soff, r, kWave);
         const int64_t o = base + __shfl(pos, r, kWave);
         const int64_t lim = max((int64_t)0, min(__shfl(n, r, kWave), p.c_capacity - o));
-        for (int64_t q = lane; q < lim; q += kWave) {
-          p.c_col[o + q] = scol[so + q];
-          p.c_val[o + q] = sval[so + q];
-        }
+        for (int64_t q = lane; q < lim; q += kWave) put_c(p.c_col, p.c_val, o + q, scol[so + q], sval[so + q]);
       }
     }
     wave_sync();
@@ -1905,8 +1900,9 @@ __global__ void __launch_bounds__(kBlock) k_compact(CompactParams p) {
     }
     const int64_t from = s_src[w][lo];
     if (from >= 0) {
-      p.c_col[base + q] = p.pad_col[from + (q - s_dst[w][lo])];
-      p.c_val[base + q] = p.pad_val[from + (q - s_dst[w][lo])];
+      // plain stores here: streaming ones measured slower for this copy
+      put_c<false>(p.c_col, p.c_val, base + q, p.pad_col[from + (q - s_dst[w][lo])],
+                   p.pad_val[from + (q - s_dst[w][lo])]);
     }
   }
 }
@@ -2089,8 +2085,7 @@ __global__ void __launch_bounds__(kBlock, M == 10 ? 3 : (M <= 8 ? 4 : 1)) k_wave
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   if (staged) {
     for (int64_t q = l; q < lim; q += kWave) {
-      c_col[base + q] = scw[q];
-      c_val[base + q] = svw[q];
+      put_c(c_col, c_val, base + q, scw[q], svw[q]);
     }
   } else if (valid) {
     // the wave's output does not fit the staging: rows write their own entries
