@@ -292,7 +292,9 @@ def run_batched(P, torch, args):
         dA = P.DeviceCSR.from_host(it.A)
         As.append(dA)
         Bs.append(dA if it.B is it.A else P.DeviceCSR.from_host(it.B))
-    batch = P.Batch(As, Bs, "upper_bound")
+    # both sides do the whole product every step: the one-pass bound sizer
+    # (an exact-sized batch would replay only its numeric pass)
+    batch = P.Batch(As, Bs, args.batch_sizer)
     batch.run()
     for _ in range(args.warmup):
         batch.run()
@@ -310,7 +312,7 @@ def run_batched(P, torch, args):
         mults += int(np.dot(acol.astype(np.int64), np.diff(np.asarray(it.B.row_ptr)).astype(np.int64)))
     t0 = time.perf_counter()
     for a, b in zip(As, Bs):
-        P.spgemm(a, b, "upper_bound")
+        P.spgemm(a, b, args.batch_sizer)
     torch.cuda.synchronize()
     lms = (time.perf_counter() - t0) * 1e3
     return {"instances": len(insts), "rows": int(sum(it.A.rows for it in insts)), "multiplications": mults,
@@ -332,6 +334,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-lo", type=int, default=256)
     ap.add_argument("--batch-hi", type=int, default=4096)
+    ap.add_argument("--batch-sizer", default="upper_bound", choices=["learned", "upper_bound", "exact"])
     ap.add_argument("--calibrate", action="store_true", help="also run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
                     help="write the traffic summary from two rocprofv3 --pmc runs and exit")
