@@ -149,7 +149,7 @@ struct spgemm_plan {
   int cur_mode;        // mode the current tiles were sized for
   int64_t ntiles;
   int64_t nbig;            // workgroup-tier rows of the current sizing
-  int64_t esc_rows;        // expand-sort rows of the current (numeric) sizing
+  int64_t esc_rows;        // expand-sort rows of the current (numeric or one-pass) sizing
   int64_t scratch_slots;   // per workgroup, current sizing
   int64_t scratch_slots_plan;
   int64_t scratch_rows;    // rows that may need a workgroup-tier table (plan sizing)
@@ -281,7 +281,7 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   if (h[kCtrError] & kErrLookback) return lookback_failed(p);
   p->ntiles = mode == kSymbolic ? (R + 63) / 64 : h[kCtrTiles];
   p->nbig = h[kCtrGlobal];
-  p->esc_rows = mode == kNumeric ? h[kCtrEsc] : 0;
+  p->esc_rows = mode != kSymbolic ? h[kCtrEsc] : 0;
   p->scratch_slots = (h[kCtrScratch] + 1) & ~(int64_t)1;
   p->scratch_rows = h[kCtrScratchRows];
   p->table_launch = (int)h[kCtrTable];
@@ -333,9 +333,9 @@ static spgemm_status run_wave(spgemm_plan *p, int mode, const double *a_val, con
   wp.table_slots = p->table_launch;
   wp.stage_slots = p->stage_launch;
   wp.stage_row_max = stage_row_max(p, mode);
-  // a numeric pass whose hashed rows are all expand-sort rows (and no merge
-  // rows) runs the tile kernel without the table path (fewer registers)
-  const bool esc_only = mode == kNumeric && p->esc_rows > 0 && p->esc_rows == p->info.rows_hash;
+  // a pass whose hashed rows are all expand-sort rows (and no merge rows)
+  // runs the tile kernel without the table path (fewer registers)
+  const bool esc_only = mode != kSymbolic && p->esc_rows > 0 && p->esc_rows == p->info.rows_hash;
   HIPCK(p, launch_wave_tiles(wp, mode, p->tune.merge_lists, p->info.rows_merge > 0, esc_only, s));
   return SPGEMM_OK;
 }

@@ -54,7 +54,7 @@ enum Counter : int {
   kCtrHuge = 22,       // workgroup-tier rows of kHugeWork products or more (listed first)
   kCtrBigTail = 23,    // the other workgroup-tier rows (listed from the end of the list)
   kCtrBigTicket = 24,  // next list entry a k_big workgroup takes
-  kCtrEsc = 25,        // numeric sizing: hashed rows taken by expand-sort-combine
+  kCtrEsc = 25,        // numeric or one-pass sizing: hashed rows taken by expand-sort-combine
   kNumCounters = 32
 };
 enum : int64_t {

@@ -367,12 +367,13 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
         // load is high only where the capacity is close to the bound)
         if (sp.mode == kOnePass && T > sp.table_max) T = table_pow2(ub + 1);
       }
-      // numeric rows whose products rarely share a column (the bound, not
-      // saturated, within a quarter of the count), whose B rows fit one wave
+      // rows whose products rarely share a column (the bound, not
+      // saturated, within a quarter of the count or the capacity), whose B
+      // rows fit one wave
       // and whose column offsets pack with a product index into one word:
       // expand, sort, combine (T slots hold the products)
       bool esc = false;
-      if (!dense && sp.mode == kNumeric && mx <= kWave && ub <= kEscMax && ub < op.b_cols && 4 * ub <= 5 * c) {
+      if (!dense && !sym && mx <= kWave && ub <= kEscMax && ub < op.b_cols && 4 * ub <= 5 * c) {
         const int64_t te = table_pow2(ub);
         if (te <= sp.table_max && (((int64_t)op.b_cols - pa.f.lo[i]) << __builtin_ctzll((uint64_t)te)) < ((int64_t)1 << 31)) {
           esc = true;
@@ -1449,12 +1450,10 @@ constexpr int kEscSteps = 2;
 // in buf[pi]; sorting the words orders the products by column and, within a
 // column, by pi, i.e. in A's order.  Each run of one column sums its
 // products from +0.0 in that order, exactly the row-major kernel's
-// accumulation (Section IV-A).  Writes the row (at most lim entries) to
-// ocol/oval in column order; returns its size.
-template <bool NT>
-__device__ int32_t wave_esc_row(const Operands &op, int64_t as, int64_t ae, int32_t maxb, int32_t lo, int32_t T,
-                                const RowEntries &re, int32_t *buf, double *pv, int32_t *ocol, double *oval,
-                                int64_t lim) {
+// accumulation (Section IV-A).
+// wave_esc_sort: expands and sorts; returns the number of products.
+__device__ int32_t wave_esc_sort(const Operands &op, int64_t as, int64_t ae, int32_t maxb, int32_t lo, int32_t T,
+                                 const RowEntries &re, int32_t *buf, double *pv) {
   const int lane = threadIdx.x;
   const int bits = __builtin_ctz((unsigned)T);
   const int lw = lanes_log2(maxb);
@@ -1514,7 +1513,17 @@ __device__ int32_t wave_esc_row(const Operands &op, int64_t as, int64_t ae, int3
   else if (n <= 128) wave_sort_buf<2>(buf, n);
   else if (n <= 256) wave_sort_buf<4>(buf, n);
   else wave_sort_buf<8>(buf, n);   // n <= kEscMax
-  // combine the runs of one column; the rank of a run's head is its place
+  return n;
+}
+
+// wave_esc_emit: combines the runs of one column of the n sorted products;
+// the rank of a run's head is its place.  WRITE: writes the row (at most lim
+// entries) to ocol/oval in column order.  Returns the row's size.
+template <bool WRITE, bool NT>
+__device__ int32_t wave_esc_emit(const int32_t *buf, const double *pv, int32_t n, int32_t lo, int32_t T,
+                                 int32_t *ocol, double *oval, int64_t lim) {
+  const int lane = threadIdx.x;
+  const int bits = __builtin_ctz((unsigned)T);
   const uint64_t lt = lanemask_lt();
   int32_t run = 0;
   for (int32_t q0 = 0; q0 < n; q0 += kWave) {
@@ -1526,7 +1535,7 @@ __device__ int32_t wave_esc_row(const Operands &op, int64_t as, int64_t ae, int3
       head = q == 0 || (buf[q - 1] >> bits) != (w >> bits);
     }
     const uint64_t hb = ballot(head);
-    if (head) {
+    if (WRITE && head) {
       const int32_t key = w >> bits;
       double v;
       {
@@ -1545,6 +1554,15 @@ __device__ int32_t wave_esc_row(const Operands &op, int64_t as, int64_t ae, int3
   }
   wave_sync();
   return run;
+}
+
+// Expand, sort, combine and write (the numeric pass); returns the row's size.
+template <bool NT>
+__device__ __forceinline__ int32_t wave_esc_row(const Operands &op, int64_t as, int64_t ae, int32_t maxb, int32_t lo,
+                                                int32_t T, const RowEntries &re, int32_t *buf, double *pv,
+                                                int32_t *ocol, double *oval, int64_t lim) {
+  const int32_t n = wave_esc_sort(op, as, ae, maxb, lo, T, re, buf, pv);
+  return wave_esc_emit<true, NT>(buf, pv, n, lo, T, ocol, oval, lim);
 }
 
 // Writes the row held by the table in column order to ocol/oval (at most
@@ -1629,10 +1647,11 @@ __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots,
   return L;
 }
 
-// ESCO: every hashed row of the launch is an expand-sort row (numeric pass,
-// no merge rows): the table path is not compiled, which frees registers.
+// ESCO: every hashed row of the launch is an expand-sort row (numeric or
+// one pass, no merge rows): the table path is not compiled, which frees
+// registers.
 template <int MODE, int M, bool MERGE, bool ESCO = false>
-__global__ void __launch_bounds__(kWave, ESCO ? 5 : (MODE == kOnePass && MERGE ? 2 : (MERGE && M == 8 ? 3 : 4)))
+__global__ void __launch_bounds__(kWave, ESCO ? 5 : (MODE == kOnePass ? (MERGE ? 2 : 3) : (MERGE && M == 8 ? 3 : 4)))
 k_wt(WaveTileParams p) {
   constexpr bool VALUES = (MODE != kSymbolic);
   extern __shared__ __align__(16) unsigned char lds[];
@@ -1711,18 +1730,48 @@ k_wt(WaveTileParams p) {
       const int r = __ffsll((unsigned long long)hm) - 1;
       hm &= hm - 1;
       const int64_t hrow = r0 + r;
-      if (MODE == kNumeric && (ESCO || info_esc(__shfl(inf, r, kWave)))) {
+      if (MODE != kSymbolic && (ESCO || info_esc(__shfl(inf, r, kWave)))) {
         // expand, sort, combine: no table; the row (never staged) goes
-        // straight to its place in C
+        // straight to its place
         const int32_t cap_r = __shfl(capr, r, kWave);
-        const int64_t o = base + __shfl(pos, r, kWave);
-        const int64_t lim = max((int64_t)0, min((int64_t)cap_r, p.c_capacity - o));
-        const int32_t c = wave_esc_row<true>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], p.lo[hrow],
-                                             (int32_t)info_slots(__shfl(inf, r, kWave)), re, buf, tvals, p.c_col + o,
-                                             p.c_val + o, lim);
+        const int32_t T = (int32_t)info_slots(__shfl(inf, r, kWave));
+        if (MODE == kNumeric) {
+          const int64_t o = base + __shfl(pos, r, kWave);
+          const int64_t lim = max((int64_t)0, min((int64_t)cap_r, p.c_capacity - o));
+          const int32_t c = wave_esc_row<true>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], p.lo[hrow], T,
+                                               re, buf, tvals, p.c_col + o, p.c_val + o, lim);
+          if (lane == r) {
+            n = c;
+            fits = c <= cap_r;
+          }
+          continue;
+        }
+        // one pass: count first, then the place (the tile's range or the
+        // spill arena, as for a hashed row), then write
+        const int32_t np = wave_esc_sort(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], p.lo[hrow], T, re, buf,
+                                         tvals);
+        const int32_t c = wave_esc_emit<false, false>(buf, tvals, np, p.lo[hrow], T, nullptr, nullptr, 0);
+        bool keep = (int64_t)mtot + hsum + c <= tile_len, spill = false;
+        int64_t o = base + __shfl(mexcl, r, kWave) + hsum;
+        if (!keep) {
+          int64_t at = 0;
+          if (lane == 0) at = (int64_t)atomicAdd((unsigned long long *)&p.counters[kCtrSpill], (unsigned long long)c);
+          at = __shfl(at, 0, kWave);
+          spill = at + c <= p.spill_cap;
+          o = p.spill_base + at;
+        }
+        if (keep || spill) {
+          const int64_t rl = max((int64_t)0, min((int64_t)c, p.c_capacity - o));
+          wave_esc_emit<true, false>(buf, tvals, np, p.lo[hrow], T, p.c_col + o, p.c_val + o, rl);
+        }
+        if (keep) {
+          if (lane > r) hb += c;
+          hsum += c;
+        }
         if (lane == r) {
           n = c;
-          fits = c <= cap_r;
+          fits = keep;
+          if (spill) spos = o;
         }
         continue;
       }
@@ -2198,7 +2247,9 @@ static hipError_t launch_wt_m(const WaveTileParams &wp, int mode, size_t lds, hi
 hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, bool esc_only,
                              hipStream_t s) {
   const size_t lds = wave_tile_lds(mode, wp.table_slots, wp.stage_slots);
-  if (mode == kNumeric && esc_only && !has_merge) return launch_wt_mm<kNumeric, 4, false, true>(wp, lds, s);
+  if (mode != kSymbolic && esc_only && !has_merge)
+    return mode == kNumeric ? launch_wt_mm<kNumeric, 4, false, true>(wp, lds, s)
+                            : launch_wt_mm<kOnePass, 4, false, true>(wp, lds, s);
   if (!has_merge) return launch_wt_m<4, false>(wp, mode, lds, s);
   switch (merge_lists) {
     case 4: return launch_wt_m<4, true>(wp, mode, lds, s);
