@@ -62,7 +62,7 @@ Layout layout_for(int64_t rows) {
   const size_t scan_tiles = R / 2048 + 2;
   L.counters = take(sizeof(int64_t) * kNumCounters);
   L.model = take(sizeof(float) * kMlpDevFloats);
-  L.partials = take(sizeof(int64_t) * 8 * (R / 256 + 2));
+  L.partials = take(sizeof(int64_t) * 10 * (R / 256 + 2));
   L.keys = take(sizeof(uint64_t) * R);
   L.nnz_a = take(4 * R);
   L.ub = take(4 * R);

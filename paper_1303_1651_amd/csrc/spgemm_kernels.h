@@ -106,7 +106,7 @@ struct PlanArrays {
   int64_t *counters;
   int32_t *cnt;         // exact per-row counts (symbolic output)
   float *pred;          // learned prediction
-  int64_t *partials;    // per-workgroup partial sums of the sizing kernel (8 per workgroup)
+  int64_t *partials;    // per-workgroup partial sums (up to 10 per workgroup)
   int32_t *big;         // workgroup-tier rows (any order)
   int32_t *ovf;         // one pass: rows that outgrew their capacity (any order)
   int64_t *pad_rp;      // one pass: exclusive scan of the capacities (rows + 1)

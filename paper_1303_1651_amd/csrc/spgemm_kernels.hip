@@ -201,15 +201,17 @@ __global__ void __launch_bounds__(kBlock) k_row_max(const int64_t *rp, int64_t r
 // Adds (or takes the max of) per-workgroup partials in a fixed order and
 // stores the results in counters[dst[j]]: one workgroup, no contended
 // atomics.  Partial j of workgroup b is partials[b * stride + j].
+constexpr int kMaxPartials = 10;
+constexpr int kSizeParts = 9;   // partial sums of the sizing kernel per workgroup
 struct PartialSpec {
   int32_t n, stride;
-  int32_t dst[8];
-  int32_t is_max[8];
+  int32_t dst[kMaxPartials];
+  int32_t is_max[kMaxPartials];
 };
 
 __global__ void __launch_bounds__(kBlock) k_sum_partials(const int64_t *partials, int64_t nblocks, PartialSpec ps,
                                                          int64_t *counters) {
-  __shared__ int64_t red[8][kWavesPerBlock];
+  __shared__ int64_t red[kMaxPartials][kWavesPerBlock];
   for (int j = 0; j < ps.n; ++j) {
     int64_t acc = 0;
     for (int64_t b = threadIdx.x; b < nblocks; b += kBlock) {
@@ -318,7 +320,7 @@ __device__ __forceinline__ int64_t table_pow2(int64_t x) {
 // The numeric pass stages merge rows only (hashed rows know their place in
 // C and go there directly).
 __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa, SizeParams sp) {
-  __shared__ int64_t s_red[8][kWavesPerBlock];
+  __shared__ int64_t s_red[kSizeParts][kWavesPerBlock];
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   const bool sym = sp.mode == kSymbolic;
   const int64_t HT = sym ? kWave : sp.stage / 2;
@@ -415,10 +417,6 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
     n_tier[tier] = 1;
     capsum = c;
   }
-  // expand-sort rows, one atomic per wave
-  const uint64_t eb = ballot(esc_row);
-  if (eb && lane_id() == 0)
-    atomicAdd((unsigned long long *)&pa.counters[kCtrEsc], (unsigned long long)__popcll(eb));
   // workgroup-tier rows: rows of many products at the front of the list
   // (their workgroups start first), the others from its end; one atomic per
   // wave and kind
@@ -438,47 +436,47 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
     else if (big) pa.big[op.rows - 1 - (rbase + __popcll(rb & lanemask_lt()))] = (int32_t)i;
   }
   const int w = threadIdx.x / kWave;
-  int64_t v[8] = {n_tier[kTierMerge], n_tier[kTierHash], n_tier[kTierEmpty], capsum, scratch > 0 ? 1 : 0,
-                  staged ? 1 : 0, scratch, tmax};
+  // sums, except the two maxima (scratch, tmax) at 6 and 7
+  int64_t v[kSizeParts] = {n_tier[kTierMerge], n_tier[kTierHash], n_tier[kTierEmpty], capsum, scratch > 0 ? 1 : 0,
+                           staged ? 1 : 0, scratch, tmax, esc_row ? 1 : 0};
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    const int64_t t = wave_sum(v[j]);
-    if (lane_id() == 0) s_red[j][w] = t;
-  }
-#pragma unroll
-  for (int j = 6; j < 8; ++j) {
+  for (int j = 0; j < kSizeParts; ++j) {
     int64_t t = v[j];
+    if (j == 6 || j == 7) {
 #pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) t = max(t, __shfl_xor(t, d, kWave));
+      for (int d = kWave / 2; d > 0; d >>= 1) t = max(t, __shfl_xor(t, d, kWave));
+    } else {
+      t = wave_sum(t);
+    }
     if (lane_id() == 0) s_red[j][w] = t;
   }
   __syncthreads();
   // one partial per workgroup; k_sum_partials adds them (no hot atomics)
-  if (threadIdx.x < 8) {
+  if (threadIdx.x < kSizeParts) {
     const int j = threadIdx.x;
+    const bool mx_j = j == 6 || j == 7;
     int64_t t = 0;
-    for (int q = 0; q < kWavesPerBlock; ++q) t = (j >= 6) ? max(t, s_red[j][q]) : t + s_red[j][q];
-    pa.partials[(int64_t)blockIdx.x * 8 + j] = t;
+    for (int q = 0; q < kWavesPerBlock; ++q) t = mx_j ? max(t, s_red[j][q]) : t + s_red[j][q];
+    pa.partials[(int64_t)blockIdx.x * kSizeParts + j] = t;
   }
 }
 
 hipError_t launch_size_rows(const Operands &op, const PlanArrays &pa, const SizeParams &sp,
                             hipStream_t s) {
   PartialSpec ps{};
-  ps.n = 8;
-  ps.stride = 8;
-  const int32_t dst[8] = {kCtrMerge, kCtrHash, kCtrEmpty, kCtrCapSum, kCtrScratchRows, kCtrStaged, kCtrScratch,
-                          kCtrTable};
-  for (int j = 0; j < 8; ++j) {
+  ps.n = kSizeParts;
+  ps.stride = kSizeParts;
+  const int32_t dst[kSizeParts] = {kCtrMerge,       kCtrHash,   kCtrEmpty,   kCtrCapSum, kCtrScratchRows,
+                                   kCtrStaged,      kCtrScratch, kCtrTable,  kCtrEsc};
+  for (int j = 0; j < kSizeParts; ++j) {
     ps.dst[j] = dst[j];
-    ps.is_max[j] = (j >= 6);
+    ps.is_max[j] = (j == 6 || j == 7);
   }
   hipError_t e = launch_fill_i64(pa.counters + kCtrGlobal, 0, 1, s);
   if (e == hipSuccess) e = launch_fill_i64(pa.counters + kCtrHuge, 0, 2, s);
-  if (e == hipSuccess) e = launch_fill_i64(pa.counters + kCtrEsc, 0, 1, s);
   if (e != hipSuccess) return e;
   if (op.rows <= 0) {
-    e = launch_fill_i64(pa.partials, 0, 8, s);
+    e = launch_fill_i64(pa.partials, 0, kSizeParts, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, (const int64_t *)pa.partials, (int64_t)1, ps,
                        pa.counters);
