@@ -53,7 +53,8 @@ extern "C" {
 typedef enum spgemm_status {
     SPGEMM_OK = 0,
     SPGEMM_E_NULL = 1,            /* a required pointer is NULL                     */
-    SPGEMM_E_DIM = 2,             /* A.cols != B.rows, negative sizes               */
+    SPGEMM_E_DIM = 2,             /* A.cols != B.rows, negative sizes, or (found by
+                                     the plan) nnz != row_ptr[rows] for A or B        */
     SPGEMM_E_NOT_CANONICAL = 3,   /* validate: unsorted/duplicate/out-of-range cols  */
     SPGEMM_E_INDEX_OVERFLOW = 4,  /* cols >= 2^31                                    */
     SPGEMM_E_WORKSPACE = 5,       /* workspace or scratch smaller than required      */
@@ -66,7 +67,7 @@ typedef enum spgemm_status {
 } spgemm_status;
 
 /* A CSR matrix; pointers are device pointers.  val may be NULL where only
- * the structure is used (plan, symbolic). */
+ * the structure is used (plan, symbolic).  nnz equals row_ptr[rows]. */
 typedef struct spgemm_csr {
     int64_t rows, cols, nnz;
     const int64_t *row_ptr;

@@ -188,6 +188,9 @@ static Operands operands_of(const spgemm_plan *p, const double *a_val, const dou
   op.b_val = b_val ? b_val : p->B.val;
   op.rows = p->A.rows;
   op.b_cols = (int32_t)p->B.cols;
+  op.b_rows = p->B.rows;
+  op.a_nnz = p->A.nnz;
+  op.b_nnz = p->B.nnz;
   return op;
 }
 
@@ -661,6 +664,7 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
                        ? std::max<int64_t>((int64_t)((double)p->tune.spill_ratio * (double)p->pad_total), kSpillMin)
                        : 0;
   }
+  if (h[kCtrError] & kErrDescriptor) return fail(SPGEMM_E_DIM);
   p->info.multiplications = h[kCtrMults];
   p->scratch_slots_plan = p->scratch_slots;
   // room for one table per resident workgroup of the workgroup-tier kernel

@@ -58,7 +58,8 @@ enum Counter : int {
   kNumCounters = 32
 };
 enum : int64_t {
-  kErrCapacity = 1, kErrNotCanonical = 2, kErrInconsistent = 4, kErrScratch = 8, kErrLookback = 16
+  kErrCapacity = 1, kErrNotCanonical = 2, kErrInconsistent = 4, kErrScratch = 8, kErrLookback = 16,
+  kErrDescriptor = 32   // a descriptor's nnz differs from its row_ptr[rows]
 };
 
 struct Operands {
@@ -70,6 +71,8 @@ struct Operands {
   const double *b_val;
   int64_t rows;       // rows of A (and C)
   int32_t b_cols;     // columns of B (and C)
+  int64_t b_rows;     // rows of B
+  int64_t a_nnz, b_nnz;  // the descriptors' entry counts (checked by the plan)
 };
 
 struct Features {

@@ -136,9 +136,13 @@ __device__ __forceinline__ uint64_t pack_triple(int64_t m, int64_t ub, int32_t m
 // MODE 2: also the per-row plan arrays (entries, saturated count, longest
 // B row, column span) for tiled passes.
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_features(Operands op, Features f, uint64_t *keys, int64_t *partials) {
+__global__ void __launch_bounds__(kBlock) k_features(Operands op, Features f, uint64_t *keys, int64_t *partials,
+                                                     int64_t *err) {
   __shared__ int64_t s_sum[4][kWavesPerBlock];
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  // arrays sized by the descriptors' nnz rely on it
+  if (i == 0 && (op.a_rp[op.rows] != op.a_nnz || op.b_rp[op.b_rows] != op.b_nnz))
+    atomicOr((unsigned long long *)err, (unsigned long long)kErrDescriptor);
   int64_t ub = 0, m = 0, empty = 0, unpacked = 0;
   if (i < op.rows) {
     int32_t mx, lo, hi;
@@ -251,9 +255,12 @@ hipError_t launch_features(const Operands &op, const Features &f, uint64_t *keys
                            int64_t *partials, int mode, hipStream_t s) {
   if (op.rows <= 0) return launch_fill_i64(counters + kCtrMults, 0, 1, s);
   const int64_t blocks = (op.rows + kBlock - 1) / kBlock;
-  if (mode == 2) hipLaunchKernelGGL(k_features<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, keys, partials);
-  else if (mode == 1) hipLaunchKernelGGL(k_features<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, keys, partials);
-  else hipLaunchKernelGGL(k_features<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, keys, partials);
+  int64_t *err = counters + kCtrError;
+  if (mode == 2)
+    hipLaunchKernelGGL(k_features<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, keys, partials, err);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_features<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, keys, partials, err);
+  else hipLaunchKernelGGL(k_features<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, keys, partials, err);
   const int32_t dst[4] = {kCtrMults, kCtrMaxA, kCtrEmpty, kCtrUnpacked};
   const int32_t mx[4] = {0, 1, 0, 0};
   return launch_sum_partials(partials, blocks, 4, 4, dst, mx, counters, s);

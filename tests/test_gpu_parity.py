@@ -231,6 +231,31 @@ def test_capacity_error_reports_required_size():
     plan.close()
 
 
+@pytest.mark.parametrize("which", ["A", "B"])
+def test_plan_rejects_nnz_that_disagrees_with_row_ptr(which):
+    # the plan keeps arrays sized by the descriptors' nnz; a descriptor whose
+    # nnz is not row_ptr[rows] is refused before any pass
+    import ctypes
+    import torch
+    import paper_1303_1651_amd as P
+    from paper_1303_1651_amd import _lib as L
+    A = synth.random_uniform_lengths(300, 20, 30, 3)
+    dA = P.DeviceCSR.from_host(A)
+    for nnz in (int(A.row_ptr[-1]) - 1, int(A.row_ptr[-1]) + 5):
+        da, db = dA.descriptor(), dA.descriptor()
+        (da if which == "A" else db).nnz = nnz
+        opts = L.spgemm_options(L.SIZER_EXACT, 0, None, None)
+        need = ctypes.c_size_t()
+        L.check(L.spgemm_plan_workspace_size(ctypes.byref(da), ctypes.byref(db), ctypes.byref(opts),
+                                             ctypes.byref(need)), "workspace")
+        ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+        plan = ctypes.c_void_p()
+        code = L.spgemm_plan_create(ctypes.byref(da), ctypes.byref(db), ctypes.byref(opts), ws.data_ptr(),
+                                    need.value, None, ctypes.byref(plan), None)
+        torch.cuda.synchronize()
+        assert code == 2, code
+
+
 def test_validate_rejects_unsorted_columns():
     import paper_1303_1651_amd as P
     A = synth.CSR(2, 3, np.array([0, 2, 3]), np.array([2, 1, 0], np.int32), np.ones(3))
