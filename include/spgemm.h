@@ -81,7 +81,8 @@ typedef enum spgemm_sizer {
     SPGEMM_SIZER_UPPER_BOUND = 1,  /* one pass, per-row accumulators sized by the multiplication
                                       count (Section IV-B estimate)                         */
     SPGEMM_SIZER_LEARNED = 2       /* one pass, accumulators sized by the learned network;
-                                      rows that overflow fall back to exact counting        */
+                                      rows with no room spill to an arena, or with that full
+                                      are computed again with their exact size              */
 } spgemm_sizer;
 
 enum {
@@ -164,7 +165,9 @@ spgemm_status spgemm_symbolic(spgemm_plan *plan, void *scratch, size_t scratch_b
                               int64_t *c_row_ptr, int64_t *c_nnz, void *stream);
 
 /* Numeric pass: writes C.  For SPGEMM_SIZER_EXACT, c_row_ptr must hold the
- * result of spgemm_symbolic.  For the one-pass sizers it is written here.
+ * result of spgemm_symbolic.  For the one-pass sizers it is written here:
+ * the rows are computed into a padded buffer in `scratch` (laid out by the
+ * capacities), counted, scanned into c_row_ptr and moved into C.
  * c_col / c_val (device) have room for c_capacity entries.  If C needs more,
  * nothing past c_capacity is written, the call returns SPGEMM_E_CAPACITY and
  * *c_nnz holds the required size (call again with a larger C).  a_val and

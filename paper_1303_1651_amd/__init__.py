@@ -258,7 +258,7 @@ class Plan:
 def spgemm(A: DeviceCSR, B: DeviceCSR, sizer="exact", model: Model | None = None, fast=False,
            validate=False, tuning: dict | None = None, stream=None) -> Result:
     """C = A * B.  ``sizer``: "exact" (symbolic + numeric), "upper_bound" or
-    "learned" (one pass with decoupled look-back)."""
+    "learned" (one pass: rows laid out by their capacities, then compacted)."""
     plan = Plan(A, B, sizer, model, fast, validate, tuning, stream)
     try:
         dev = plan.device

@@ -6,7 +6,10 @@
 // Output rows are sorted by column (Section IV-B append contract).
 //
 // Pipeline: features -> sizing/tiering -> scan of tile costs -> tile bounds
-// -> tile kernel (symbolic, numeric, or one pass with decoupled look-back).
+// -> tile kernel (symbolic, numeric, or one pass into a padded buffer that
+// k_compact moves into C) and k_big for the workgroup-tier rows; products
+// whose rows all take the row-per-thread merge run k_wave_merge instead
+// (its one pass: a decoupled look-back over waves).
 #include <algorithm>
 
 #include "device_common.h"
