@@ -27,7 +27,8 @@
  *   - Every matrix pointer in spgemm_csr is a DEVICE pointer owned by the
  *     caller.  The library never allocates device memory: the caller passes
  *     a workspace (size from spgemm_plan_workspace_size) and, where the
- *     plan reports one, a scratch buffer.  Host-side plan objects are
+ *     plan reports one, a scratch buffer, both 256-byte aligned (as
+ *     hipMalloc returns them).  Host-side plan objects are
  *     allocated with malloc and freed by spgemm_plan_destroy.
  *   - Row pointers are int64 (rows + 1 entries, row_ptr[0] == 0,
  *     non-decreasing, row_ptr[rows] == nnz).  Column indices are int32 in
@@ -57,7 +58,7 @@ typedef enum spgemm_status {
                                      the plan) nnz != row_ptr[rows] for A or B        */
     SPGEMM_E_NOT_CANONICAL = 3,   /* validate: unsorted/duplicate/out-of-range cols  */
     SPGEMM_E_INDEX_OVERFLOW = 4,  /* cols >= 2^31                                    */
-    SPGEMM_E_WORKSPACE = 5,       /* workspace or scratch smaller than required      */
+    SPGEMM_E_WORKSPACE = 5,       /* workspace or scratch too small or not 256-byte aligned */
     SPGEMM_E_CAPACITY = 6,        /* C capacity too small; required size returned    */
     SPGEMM_E_NO_MODEL = 7,        /* learned sizing requested without a model        */
     SPGEMM_E_STATE = 8,           /* calls out of order (e.g. numeric before plan)   */

@@ -301,7 +301,7 @@ spgemm_status spgemm_batched_plan(int64_t count, const spgemm_csr *A, const spge
   b->o_bval = take(8 * (size_t)nb);
   b->o_crp = take(8 * (size_t)(R + 1));
   b->o_bounds = take(8 * (size_t)(2 * count + 1));
-  b->plan_bytes = plan_workspace_bytes(R);
+  b->plan_bytes = plan_workspace_bytes(R, K);
   b->o_plan = take(b->plan_bytes);
   b->total = o;
   void *pin = nullptr;
@@ -318,7 +318,7 @@ spgemm_status spgemm_batched_plan(int64_t count, const spgemm_csr *A, const spge
 spgemm_status spgemm_batched_reserve(spgemm_batch *b, void *workspace, size_t workspace_bytes, int64_t *c_capacity,
                                      size_t *scratch_bytes, void *stream) {
   if (!b || !workspace || !c_capacity || !scratch_bytes) return SPGEMM_E_NULL;
-  if (workspace_bytes < b->total) return SPGEMM_E_WORKSPACE;
+  if (workspace_bytes < b->total || !aligned256(workspace)) return SPGEMM_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   drop_graph(b);
   if (b->plan) {

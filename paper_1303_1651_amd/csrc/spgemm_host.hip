@@ -46,10 +46,10 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace carve-up: every array 256-byte aligned.
 struct Layout {
-  size_t counters, model, partials, keys, nnz_a, ub, maxb, lo, hi, pred, cnt, info, cap, cost, tile_row, status, scan_status, big, ovf, pad_rp, pad_src, total;
+  size_t counters, model, partials, keys, nnz_a, ub, maxb, lo, hi, pred, cnt, info, cap, cost, tile_row, status, scan_status, big, ovf, pad_rp, pad_src, brow, total;
 };
 
-Layout layout_for(int64_t rows) {
+Layout layout_for(int64_t rows, int64_t brows) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -81,6 +81,8 @@ Layout layout_for(int64_t rows) {
   L.ovf = take(4 * R);
   L.pad_rp = take(8 * (R + 1));
   L.pad_src = take(8 * R);
+  const size_t BR = (size_t)std::max<int64_t>(brows, 0);
+  L.brow = take(16 * BR);
   L.total = o;
   return L;
 }
@@ -364,7 +366,7 @@ static spgemm_status run_big(spgemm_plan *p, int mode, bool overflow_list, void 
   if (nrows == 0) return SPGEMM_OK;
   const size_t off = pad_bytes(p);
   const size_t per = (size_t)p->scratch_slots * 12;
-  if (per > 0 && (!scratch || scratch_bytes < off + per)) return SPGEMM_E_WORKSPACE;
+  if (per > 0 && (!scratch || scratch_bytes < off + per || !aligned256(scratch))) return SPGEMM_E_WORKSPACE;
   BigParams bp{};
   bp.op = operands_of(p, a_val, b_val);
   bp.list = overflow_list ? p->pa.ovf : p->pa.big;
@@ -431,7 +433,7 @@ spgemm_status numeric_enqueue(spgemm_plan *p, void *scratch, size_t scratch_byte
   // places, and the workgroup-tier and listed rows are computed into C with
   // their exact sizes
   const int64_t pe = pad_entries(p);
-  if (pe > 0 && (!scratch || scratch_bytes < pad_bytes(p))) return SPGEMM_E_WORKSPACE;
+  if (pe > 0 && (!scratch || scratch_bytes < pad_bytes(p) || !aligned256(scratch))) return SPGEMM_E_WORKSPACE;
   int32_t *pcol = static_cast<int32_t *>(scratch);
   double *pval = reinterpret_cast<double *>(static_cast<char *>(scratch) + align_up((size_t)pe * 4, 256));
   st = run_big(p, kSymbolic, false, scratch, scratch_bytes, av, bv, nullptr, nullptr, nullptr, 0, s);
@@ -462,7 +464,7 @@ spgemm_status numeric_enqueue(spgemm_plan *p, void *scratch, size_t scratch_byte
 
 int64_t *plan_counters(spgemm_plan *p) { return p->pa.counters; }
 int plan_is_one_pass(const spgemm_plan *p) { return p->first_mode != kSymbolic; }
-size_t plan_workspace_bytes(int64_t rows) { return layout_for(rows).total; }
+size_t plan_workspace_bytes(int64_t rows, int64_t brows) { return layout_for(rows, brows).total; }
 
 spgemm_status plan_check_counters(spgemm_plan *p, const int64_t *h) { return device_errors(p, h); }
 
@@ -497,7 +499,7 @@ spgemm_status spgemm_plan_workspace_size(const spgemm_csr *A, const spgemm_csr *
   if (st != SPGEMM_OK) return st;
   if (A->cols != B->rows) return SPGEMM_E_DIM;
   (void)opts;
-  *bytes = layout_for(A->rows).total;
+  *bytes = layout_for(A->rows, B->rows).total;
   return SPGEMM_OK;
 }
 
@@ -513,9 +515,9 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   if (A->cols != B->rows) return SPGEMM_E_DIM;
   if (opts->sizer < 0 || opts->sizer > 2) return SPGEMM_E_INVALID;
   if (opts->sizer == SPGEMM_SIZER_LEARNED && !opts->model) return SPGEMM_E_NO_MODEL;
-  Layout L = layout_for(A->rows);
+  Layout L = layout_for(A->rows, B->rows);
   if (!workspace) return SPGEMM_E_NULL;
-  if (workspace_bytes < L.total) return SPGEMM_E_WORKSPACE;
+  if (workspace_bytes < L.total || !aligned256(workspace)) return SPGEMM_E_WORKSPACE;
   spgemm_tuning tune = default_tuning(A, B);
   merge_tuning(&tune, opts->tuning);
   if (!tuning_ok(tune)) return SPGEMM_E_INVALID;
@@ -559,6 +561,7 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   p->pa.ovf = (int32_t *)(w + L.ovf);
   p->pa.pad_rp = (int64_t *)(w + L.pad_rp);
   p->pa.pad_src = (int64_t *)(w + L.pad_src);
+  p->pa.f.brow = (int32_t *)(w + L.brow);
   p->keys = (uint64_t *)(w + L.keys);
   hipStream_t s = (hipStream_t)stream;
 
@@ -634,7 +637,8 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
     p->cur_mode = p->first_mode;
   } else {
     // per-row features (and their sums), the learned prediction, tiers
-    if (launch_features(op, p->pa.f, p->keys, p->pa.counters, p->pa.partials, 2, s) != hipSuccess)
+    if (launch_brow_ends(op, p->pa.f, s) != hipSuccess ||
+        launch_features(op, p->pa.f, p->keys, p->pa.counters, p->pa.partials, 2, s) != hipSuccess)
       return fail(SPGEMM_E_HIP);
     if (learned) {
       if (launch_mlp_predict(dev, p->pa.f.nnz_a, p->pa.f.ub, p->pa.f.maxb, A->rows, p->pa.pred, s, p->tune.margin,

@@ -22,7 +22,9 @@ spgemm_status numeric_enqueue(spgemm_plan *p, void *scratch, size_t scratch_byte
                               int64_t c_capacity, hipStream_t s);
 int64_t *plan_counters(spgemm_plan *p);
 int plan_is_one_pass(const spgemm_plan *p);
-size_t plan_workspace_bytes(int64_t rows);
+size_t plan_workspace_bytes(int64_t rows, int64_t brows);
+// workspace and scratch carry 256-byte aligned arrays (16-byte records among them)
+inline bool aligned256(const void *p) { return ((uintptr_t)p & 255) == 0; }
 spgemm_status plan_check_counters(spgemm_plan *p, const int64_t *h);
 
 // Predicted nnz(C_row) for n rows; dev_params holds kMlpDevFloats floats

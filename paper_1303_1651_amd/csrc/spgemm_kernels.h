@@ -80,6 +80,9 @@ struct Features {
   int32_t *ub;        // multiplication count, saturated at b_cols
   int32_t *maxb;      // longest selected B row
   int32_t *lo, *hi;   // smallest / largest column any selected B row touches
+  int32_t *brow;  // per row of B, 16-byte aligned: {entries, first column,
+                  // last column, 0} (empty: {0, INT32_MAX, -1, 0}), written
+                  // before the span pass
 };
 
 struct SizeParams {
@@ -196,6 +199,7 @@ hipError_t launch_tile_bounds(const int64_t *cost, int64_t rows, int64_t half_po
                               int32_t *tile_row, int64_t *counters, hipStream_t s);
 size_t wave_tile_lds(int mode, int table_slots, int stage_slots);
 // has_merge: some row of the pass takes the merge tier
+hipError_t launch_brow_ends(const Operands &op, Features f, hipStream_t s);
 hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, bool esc_only,
                              hipStream_t s);
 hipError_t launch_compact(const CompactParams &cp, hipStream_t s);

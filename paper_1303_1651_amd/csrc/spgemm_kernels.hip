@@ -89,7 +89,7 @@ hipError_t launch_validate(const int64_t *rp, const int32_t *col, int64_t rows, 
 // time, each group's loads issued at once (three dependent gather rounds).
 template <bool SPAN>
 __device__ __forceinline__ void row_features(const Operands &op, int64_t i, int64_t &m, int64_t &ub, int32_t &mx,
-                                             int32_t &lo, int32_t &hi) {
+                                             int32_t &lo, int32_t &hi, const int32_t *brow = nullptr) {
   const int64_t s = op.a_rp[i], e = op.a_rp[i + 1];
   m = e - s;
   ub = 0;
@@ -100,28 +100,34 @@ __device__ __forceinline__ void row_features(const Operands &op, int64_t i, int6
   for (int64_t q0 = s; q0 < e; q0 += 8) {
     const int cnt = (int)min((int64_t)8, e - q0);
     int32_t k[8];
-    int64_t bs[8], be[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) k[q] = q < cnt ? op.a_col[q0 + q] : 0;
+    if (SPAN) {
+      // one aligned 16-byte record per selected B row: length and span
+      int4 r[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      bs[q] = q < cnt ? op.b_rp[k[q]] : 0;
-      be[q] = q < cnt ? op.b_rp[k[q] + 1] : 0;
-    }
-    int32_t l8[8], h8[8];
+      for (int q = 0; q < 8; ++q)
+        r[q] = q < cnt ? reinterpret_cast<const int4 *>(brow)[k[q]] : make_int4(0, 0x7fffffff, -1, 0);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const bool has = SPAN && be[q] > bs[q];
-      l8[q] = has ? op.b_col[bs[q]] : 0x7fffffff;
-      h8[q] = has ? op.b_col[be[q] - 1] : -1;
-    }
+      for (int q = 0; q < 8; ++q) {
+        ub += r[q].x;
+        mx = max(mx, r[q].x);
+        lo = min(lo, r[q].y);
+        hi = max(hi, r[q].z);
+      }
+    } else {
+      int64_t bs[8], be[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int32_t len = (int32_t)(be[q] - bs[q]);
-      ub += len;
-      mx = max(mx, len);
-      lo = min(lo, l8[q]);
-      hi = max(hi, h8[q]);
+      for (int q = 0; q < 8; ++q) {
+        bs[q] = q < cnt ? op.b_rp[k[q]] : 0;
+        be[q] = q < cnt ? op.b_rp[k[q] + 1] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int32_t len = (int32_t)(be[q] - bs[q]);
+        ub += len;
+        mx = max(mx, len);
+      }
     }
   }
 }
@@ -149,7 +155,7 @@ __global__ void __launch_bounds__(kBlock) k_features(Operands op, Features f, ui
   int64_t ub = 0, m = 0, empty = 0, unpacked = 0;
   if (i < op.rows) {
     int32_t mx, lo, hi;
-    row_features<MODE == 2>(op, i, m, ub, mx, lo, hi);
+    row_features<MODE == 2>(op, i, m, ub, mx, lo, hi, f.brow);
     if (MODE == 1) {
       keys[i] = pack_triple(m, ub, mx, op.b_cols);
       if (keys[i] == ~0ull) unpacked = min(ub, (int64_t)op.b_cols);
@@ -186,6 +192,24 @@ __global__ void __launch_bounds__(kBlock) k_features(Operands op, Features f, ui
     partials[blockIdx.x * 4 + 2] = te;
     partials[blockIdx.x * 4 + 3] = tu;
   }
+}
+
+// Length, first and last column of every row of B in one 16-byte record
+// (the span pass gathers one record per stored entry of A).
+__global__ void __launch_bounds__(kBlock) k_brow_ends(const int64_t *b_rp, const int32_t *b_col, int64_t b_rows,
+                                                      int4 *brow) {
+  for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < b_rows; k += (int64_t)gridDim.x * kBlock) {
+    const int64_t s = b_rp[k], e = b_rp[k + 1];
+    brow[k] = e > s ? make_int4((int32_t)(e - s), b_col[s], b_col[e - 1], 0) : make_int4(0, 0x7fffffff, -1, 0);
+  }
+}
+
+hipError_t launch_brow_ends(const Operands &op, Features f, hipStream_t s) {
+  if (op.b_rows <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((op.b_rows + kBlock - 1) / kBlock, 1 << 16);
+  hipLaunchKernelGGL(k_brow_ends, dim3((unsigned)blocks), dim3(kBlock), 0, s, op.b_rp, op.b_col, op.b_rows,
+                     reinterpret_cast<int4 *>(f.brow));
+  return hipGetLastError();
 }
 
 // Longest row of A (row pointers only).

@@ -82,9 +82,21 @@ def test_invalid_tuning_is_rejected():
         t = L.spgemm_tuning(**bad)
         opts = L.spgemm_options(0, 0, None, ctypes.pointer(t))
         plan = ctypes.c_void_p()
-        code = L.spgemm_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(opts), 1, 1 << 20, None,
+        code = L.spgemm_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(opts), 256, 1 << 20, None,
                                     ctypes.byref(plan), None)
         assert code == 10, bad
+
+
+def test_unaligned_workspace_is_rejected():
+    # checked before any device work: the workspace holds 16-byte records
+    from paper_1303_1651_amd import _lib as L
+    A = L.spgemm_csr(4, 4, 0, 1, None, None)
+    opts = L.spgemm_options(0, 0, None, None)
+    plan = ctypes.c_void_p()
+    for ws in (8, 16, 272):
+        code = L.spgemm_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(opts), ws, 1 << 20, None,
+                                    ctypes.byref(plan), None)
+        assert code == 5 and not plan.value, ws
 
 
 def test_model_file_round_trip(tmp_path):
