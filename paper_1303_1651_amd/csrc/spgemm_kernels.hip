@@ -85,6 +85,13 @@ hipError_t launch_validate(const int64_t *rp, const int32_t *col, int64_t rows, 
 // C_i), and the smallest/largest column any selected B row touches (the
 // "MinMax" region of Section IV-B).  The exact int64 sum of the counts is
 // the paper's multiplication count of Section III.
+// The B row that stored entry e of A selects: its start and length.
+__device__ __forceinline__ void b_row_of(const Operands &op, int64_t e, int64_t &bs, int32_t &bl) {
+  const int32_t k = op.a_col[e];
+  bs = op.b_rp[k];
+  bl = (int32_t)(op.b_rp[k + 1] - bs);
+}
+
 // Features of row i (see above); the stored entries are taken eight at a
 // time, each group's loads issued at once (three dependent gather rounds).
 template <bool SPAN>
@@ -682,11 +689,8 @@ __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, 
     pos[l] = 0;
     a[l] = 0.0;
     if (l < m) {
-      int32_t k = op.a_col[as + l];
       if (VALUES) a[l] = op.a_val[as + l];
-      int64_t bs = op.b_rp[k];
-      pos[l] = bs;
-      rem[l] = (int32_t)(op.b_rp[k + 1] - bs);
+      b_row_of(op, as + l, pos[l], rem[l]);
     }
   }
 #pragma unroll
@@ -787,10 +791,10 @@ __device__ void wg_for_products(const Operands &op, int64_t row, WgScratch &ws, 
     int64_t bs = 0, bl = 0;
     double av = 0.0;
     if (e < ae) {
-      int32_t k = op.a_col[e];
       av = op.a_val ? op.a_val[e] : 0.0;
-      bs = op.b_rp[k];
-      bl = op.b_rp[k + 1] - bs;
+      int32_t l;
+      b_row_of(op, e, bs, l);
+      bl = l;
     }
     int64_t tot;
     int64_t ex = block_exclusive_sum(bl, ws.wtot, &tot);
@@ -930,10 +934,10 @@ __device__ void wg_global_values(const Operands &op, int64_t row, const int32_t 
     int64_t bs = 0, bl = 0;
     double av = 0.0;
     if (e < ae) {
-      const int32_t k = op.a_col[e];
       av = op.a_val[e];
-      bs = op.b_rp[k];
-      bl = op.b_rp[k + 1] - bs;
+      int32_t l;
+      b_row_of(op, e, bs, l);
+      bl = l;
     }
     int64_t tot;
     const int64_t ex = block_exclusive_sum(bl, ws.wtot, &tot);
@@ -1220,24 +1224,6 @@ struct Batch2 {
 };
 
 template <bool VALUES, int PF = wave_prefetch<VALUES>()>
-__device__ __forceinline__ void load_batch1(const Operands &op, int64_t e0, int64_t ae, int lw, Batch1<PF> &b) {
-  const int per = kWave >> lw, sub = (int)threadIdx.x >> lw;
-#pragma unroll
-  for (int u = 0; u < PF; ++u) {
-    const int64_t e = e0 + (int64_t)u * per + sub;
-    b.bs[u] = 0;
-    b.bl[u] = 0;
-    b.av[u] = 0.0;
-    if (e < ae) {
-      const int32_t k = op.a_col[e];
-      if (VALUES) b.av[u] = op.a_val[e];
-      b.bs[u] = op.b_rp[k];
-      b.bl[u] = (int32_t)(op.b_rp[k + 1] - b.bs[u]);
-    }
-  }
-}
-
-template <bool VALUES, int PF = wave_prefetch<VALUES>()>
 __device__ __forceinline__ void load_batch2(const Operands &op, int lw, const Batch1<PF> &b1, Batch2<PF> &b2) {
   const int bp = (int)threadIdx.x & ((1 << lw) - 1);
 #pragma unroll
@@ -1323,10 +1309,11 @@ __device__ int32_t wave_insert_row(const Operands &op, int64_t as, int64_t ae, i
   for (int64_t g0 = as; g0 < ae; g0 += kWave) {
     const int gn = (int)min((int64_t)kWave, ae - g0);
     if (lane < gn) {
-      const int32_t k = op.a_col[g0 + lane];
-      const int64_t bs = op.b_rp[k];
+      int64_t bs;
+      int32_t bl;
+      b_row_of(op, g0 + lane, bs, bl);
       re.bs[lane] = bs;
-      re.bl[lane] = (int32_t)(op.b_rp[k + 1] - bs);
+      re.bl[lane] = bl;
       if (VALUES) re.av[lane] = op.a_val[g0 + lane];
     }
     wave_sync();
@@ -1362,51 +1349,86 @@ __device__ __forceinline__ void wave_clear(const WaveTable &tb) {
 }
 
 // Ascending bitonic sort of 64 * E keys held lane-major (element i = lane *
-// E + e): partners within a lane are exchanged in registers, partners in
-// other lanes through a lane shuffle.  One instantiation per (block size K,
-// partner distance J) stage, so every register index is a constant.
-// The value of the lane whose index differs from this lane's in bit LM:
-// a DPP quad permutation for 1 and 2 (no trip through the LDS unit), a
-// swizzle within 32 lanes up to 16, a permute across the halves for 32.
+// E + e), in the form whose every compare-exchange puts the smaller key at
+// the lower index: level K (sorted blocks of K/2 become sorted blocks of K)
+// first compares i with its mirror i ^ (K - 1) inside the block, then i with
+// i ^ J for J = K/4 .. 1.  Partners within a lane are exchanged in
+// registers, partners in other lanes through a lane exchange.  One
+// instantiation per (level, distance) stage, so every register index is a
+// constant.
+// The value of the lane whose index is this lane's xor LM: DPP within a row
+// of 16 lanes (quad permutations for 1, 2, 3, half-row and row mirrors for
+// 7 and 15, a rotation by 8 for 8), a swizzle within 32 lanes for 4, 16 and
+// 31, a permute across the halves for 32 and 63.
 template <int LM>
 __device__ __forceinline__ int32_t xor_lane(int32_t v) {
   if constexpr (LM == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad (1,0,3,2)
   else if constexpr (LM == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // quad (2,3,0,1)
-  else if constexpr (LM < 32) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (LM << 10));      // lane ^ LM
+  else if constexpr (LM == 3) return __builtin_amdgcn_update_dpp(0, v, 0x1B, 0xF, 0xF, false);  // quad (3,2,1,0)
+  else if constexpr (LM == 7) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false); // half-row mirror
+  else if constexpr (LM == 8) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false); // row rotate 8
+  else if constexpr (LM == 15) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false); // row mirror
+  else if constexpr (LM < 32) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (LM << 10));        // lane ^ LM
   else return __shfl_xor(v, LM, kWave);
 }
 
+// Stage (K, J) of the sort: J == K / 2 is the mirror stage of level K.
 template <int E, int K, int J>
 __device__ __forceinline__ void wave_bitonic_stage(int32_t (&x)[E]) {
   const int lane = threadIdx.x;
-  if constexpr (J >= E) {
+  if constexpr (J == K / 2 && K > E) {
+    // mirror partner: lane ^ (K/E - 1), element E - 1 - e
+    constexpr int lm = K / E - 1;
+    const bool lower = (lane & (K / (2 * E))) == 0;
+    // elements e and E - 1 - e trade partners: two values in flight
+#pragma unroll
+    for (int e = 0; e < (E + 1) / 2; ++e) {
+      const int32_t ya = xor_lane<lm>(x[E - 1 - e]);
+      const int32_t yb = xor_lane<lm>(x[e]);
+      x[e] = lower ? min(x[e], ya) : max(x[e], ya);
+      if (E - 1 - e != e) x[E - 1 - e] = lower ? min(x[E - 1 - e], yb) : max(x[E - 1 - e], yb);
+    }
+  } else if constexpr (J == K / 2) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if ((e & J) == 0) {
+        const int32_t a = x[e], b = x[e ^ (K - 1)];
+        x[e] = min(a, b);
+        x[e ^ (K - 1)] = max(a, b);
+      }
+    }
+  } else if constexpr (J >= E) {
     constexpr int lm = J / E;
-    const bool up = ((lane * E) & K) == 0;
     const bool lower = (lane & lm) == 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int32_t y = xor_lane<lm>(x[e]);
-      x[e] = (lower == up) ? min(x[e], y) : max(x[e], y);
+      x[e] = lower ? min(x[e], y) : max(x[e], y);
     }
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       if ((e & J) == 0) {
-        const bool up = ((lane * E + e) & K) == 0;
         const int32_t a = x[e], b = x[e ^ J];
-        const bool sw = up ? (a > b) : (a < b);
-        x[e] = sw ? b : a;
-        x[e ^ J] = sw ? a : b;
+        x[e] = min(a, b);
+        x[e ^ J] = max(a, b);
       }
     }
   }
   if constexpr (J > 1) wave_bitonic_stage<E, K, J / 2>(x);
-  else if constexpr (K < kWave * E) wave_bitonic_stage<E, 2 * K, K>(x);
+}
+
+// Levels K .. 64 E; levels below `from` are skipped (their blocks of
+// from / 2 keys are sorted already).
+template <int E, int K>
+__device__ __forceinline__ void wave_bitonic_levels(int32_t (&x)[E], int32_t from) {
+  if (K >= from) wave_bitonic_stage<E, K, K / 2>(x);
+  if constexpr (K < kWave * E) wave_bitonic_levels<E, 2 * K>(x, from);
 }
 
 template <int E>
-__device__ __forceinline__ void wave_bitonic(int32_t (&x)[E]) {
-  wave_bitonic_stage<E, 2, 1>(x);
+__device__ __forceinline__ void wave_bitonic(int32_t (&x)[E], int32_t from = 2) {
+  wave_bitonic_levels<E, 2>(x, from);
 }
 
 // Sorted write-out of a hashed row whose n keys were compacted (in slot
@@ -1453,18 +1475,20 @@ __device__ void wave_sort_out(const WaveTable &tb, int32_t n, int32_t *buf, int3
   wave_clear(tb);
 }
 
-// Sorts buf[0..n) (n <= 64 E) ascending in the wave's registers.
+// Sorts buf[0..nload) (nload <= 64 E) ascending in the wave's registers,
+// where each aligned block of from / 2 keys is sorted already, and writes
+// back the n smallest.
 template <int E>
-__device__ __forceinline__ void wave_sort_buf(int32_t *buf, int32_t n) {
+__device__ __forceinline__ void wave_sort_buf(int32_t *buf, int32_t nload, int32_t n, int32_t from) {
   const int lane = threadIdx.x;
   int32_t x[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int32_t pos = lane * E + e;
-    x[e] = pos < n ? buf[pos] : kColMax;
+    x[e] = pos < nload ? buf[pos] : kColMax;
   }
   wave_sync();
-  wave_bitonic<E>(x);
+  wave_bitonic<E>(x, from);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int32_t pos = lane * E + e;
@@ -1490,16 +1514,19 @@ __device__ int32_t wave_esc_sort(const Operands &op, int64_t as, int64_t ae, int
   const int bits = __builtin_ctz((unsigned)T);
   const int lw = lanes_log2(maxb);
   const int per = kWave >> lw, sub = lane >> lw, bp = lane & ((1 << lw) - 1);
+  // every B row is sorted: where one block of P = pow2(maxb) indices per
+  // entry of A fits the T slots, entry j's products take indices j P + bp
+  // (the rest of its block a sentinel above every word), and the sort
+  // starts from sorted blocks of P
+  int32_t P = 1;
+  while (P < maxb) P <<= 1;
+  const bool blocks = (ae - as) * P <= T;
   int32_t pbase = 0;
   for (int64_t g0 = as; g0 < ae; g0 += kWave) {
     const int gn = (int)min((int64_t)kWave, ae - g0);
     int32_t bl = 0;
     int64_t bs = 0;
-    if (lane < gn) {
-      const int32_t k = op.a_col[g0 + lane];
-      bs = op.b_rp[k];
-      bl = (int32_t)(op.b_rp[k + 1] - bs);
-    }
+    if (lane < gn) b_row_of(op, g0 + lane, bs, bl);
     const int32_t inc = wave_inclusive_sum32(bl);
     if (lane < gn) {
       re.bs[lane] = bs;
@@ -1518,12 +1545,15 @@ __device__ int32_t wave_esc_sort(const Operands &op, int64_t as, int64_t ae, int
         const int e = e0 + u * per + sub;
         pi[u] = -1;
         const int32_t w = e < gn ? re.bl[e] : 0;
+        const int32_t at_pi = blocks ? (int32_t)(g0 - as + e) * P + bp : (w >> 16) + bp;
         if (bp < (w & 0xffff)) {
           const int64_t at = re.bs[e] + bp;
           jj[u] = op.b_col[at];
           bb[u] = op.b_val[at];
           ab[u] = re.av[e];
-          pi[u] = (w >> 16) + bp;
+          pi[u] = at_pi;
+        } else if (blocks && e < gn && bp < P) {
+          buf[at_pi] = kColMax;
         }
       }
 #pragma unroll
@@ -1541,10 +1571,11 @@ __device__ int32_t wave_esc_sort(const Operands &op, int64_t as, int64_t ae, int
     wave_sync();
   }
   const int32_t n = pbase;
-  if (n <= 64) wave_sort_buf<1>(buf, n);
-  else if (n <= 128) wave_sort_buf<2>(buf, n);
-  else if (n <= 256) wave_sort_buf<4>(buf, n);
-  else wave_sort_buf<8>(buf, n);   // n <= kEscMax
+  const int32_t nl = blocks ? (int32_t)(ae - as) * P : n, from = blocks ? 2 * P : 2;
+  if (nl <= 64) wave_sort_buf<1>(buf, nl, n, from);
+  else if (nl <= 128) wave_sort_buf<2>(buf, nl, n, from);
+  else if (nl <= 256) wave_sort_buf<4>(buf, nl, n, from);
+  else wave_sort_buf<8>(buf, nl, n, from);   // nl <= T <= kEscMax
   return n;
 }
 
@@ -1682,8 +1713,14 @@ __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots,
 // ESCO: every hashed row of the launch is an expand-sort row (numeric or
 // one pass, no merge rows): the table path is not compiled, which frees
 // registers.
+// Resident waves per SIMD: seven for the counting pass (no values: it fits
+// 70 registers without spills, and more waves hide its chain of dependent
+// loads), five for expand-sort launches, fewer where the merge lists and the
+// values take registers.
 template <int MODE, int M, bool MERGE, bool ESCO = false>
-__global__ void __launch_bounds__(kWave, ESCO ? 5 : (MODE == kOnePass ? (MERGE ? 2 : 3) : (MERGE && M == 8 ? 3 : 4)))
+__global__ void __launch_bounds__(kWave, ESCO ? 5
+                                         : MODE == kSymbolic ? 7
+                                         : (MODE == kOnePass ? (MERGE ? 2 : 3) : (MERGE && M == 8 ? 3 : 4)))
 k_wt(WaveTileParams p) {
   constexpr bool VALUES = (MODE != kSymbolic);
   extern __shared__ __align__(16) unsigned char lds[];
