@@ -159,10 +159,12 @@ struct spgemm_plan {
   int64_t spill_cap;       // one pass, learned: entries of the spill arena after it
   int table_launch;        // LDS table slots of the wave-tile launch
   int stage_launch;        // LDS staging entries of the wave-tile launch
+  int64_t staged_rows;     // rows the last sized pass stages
   int merge_only;      // every row takes the register-merge tier: row-per-thread kernels
   int merge_m;         // lists of the row-per-thread merge (4, 6, 8, 10 or 16)
   int merge_stage;     // staged entries per merge wave
-  int merge_off;       // one pass sized without the register-merge tier
+  int merge_off;       // numeric or one pass sized without the register-merge tier
+  int stage_off;       // numeric or one pass sized without staging hashed rows
   spgemm_info info;
   hipError_t last_err;
   const spgemm_model *model;
@@ -237,11 +239,11 @@ constexpr int kMergeOnlyLists = 16;
 constexpr double kMergeOnlyRowEst = 128.0;
 constexpr int64_t kMergeStageMax = 2048;
 
-// Hashed rows of at most this many entries are staged in LDS by the numeric
-// pass (copied out with the tile's other rows); larger rows are written to C
-// by their own wave directly.
-constexpr int kStageRowMax = 128;
-constexpr int64_t kMergeFewRows = 64;   // merge rows under 1/64 of the rows: one pass without them
+// Hashed rows of at most this many entries (a wave's width) are staged in
+// LDS by the numeric pass (copied out with the tile's other rows); larger
+// rows are written to C by their own wave directly, with full-wave stores.
+constexpr int kStageRowMax = 64;
+constexpr int64_t kMergeFewRows = 64;   // merge rows under 1/64 of the rows: numeric / one pass without them
 constexpr int64_t kSpillMin = 4096;   // smallest spill arena (entries)
 
 // Sizing of one pass (tiers, capacities, tile costs) plus tile bounds.
@@ -249,6 +251,7 @@ constexpr int64_t kSpillMin = 4096;   // smallest spill arena (entries)
 // capacity carries the sizing margin: the limit scales with it, so that a
 // row predicted at kStageRowMax entries is staged like an exact one.
 static int stage_row_max(const spgemm_plan *p, int mode) {
+  if (p->stage_off) return 0;
   if (mode == kOnePass && p->opts.sizer == SPGEMM_SIZER_LEARNED)
     return (int)std::ceil(kStageRowMax * (1.0 + (double)p->tune.margin)) + p->tune.slack;
   return kStageRowMax;
@@ -292,6 +295,7 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   p->table_launch = (int)h[kCtrTable];
   // staging: every row of a one-pass tile; merge rows only in the numeric pass
   p->stage_launch = (mode != kSymbolic && h[kCtrStaged] > 0) ? stage : 0;
+  p->staged_rows = mode != kSymbolic ? h[kCtrStaged] : 0;
   p->cur_mode = mode;
   p->info.rows_merge = h[kCtrMerge];
   p->info.rows_hash = h[kCtrHash];
@@ -300,6 +304,19 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   p->info.tiles = p->ntiles;
   if (mode != kNumeric) p->info.c_capacity_hint = h[kCtrCapSum];
   return SPGEMM_OK;
+}
+
+// Staging buys contiguous copy-outs for rows shorter than a wave, but the
+// launch then reserves the whole stage in every wave's LDS (fewer resident
+// waves).  Where only a few rows would be staged (a stencil's boundary
+// rows, say), the pass is sized again without staging hashed rows: they are
+// written straight to their place like the longer ones.
+static spgemm_status unstage_if_few(spgemm_plan *p, int mode, hipStream_t s) {
+  if (p->stage_off || p->info.rows_merge > 0 || p->staged_rows == 0 ||
+      p->staged_rows * kMergeFewRows >= p->A.rows)
+    return SPGEMM_OK;
+  p->stage_off = 1;
+  return size_pass(p, mode, s);
 }
 
 static void timing_begin(spgemm_plan *p, hipStream_t s, hipError_t *e) {
@@ -654,6 +671,7 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
       p->merge_off = 1;
       st = size_pass(p, p->first_mode, s);
     }
+    if (st == SPGEMM_OK && p->first_mode == kOnePass) st = unstage_if_few(p, p->first_mode, s);
     if (st != SPGEMM_OK) return fail(st);
     if (p->first_mode == kOnePass &&
         launch_scan_i32(p->pa.cap, p->pa.pad_rp, A->rows, p->pa.scan_status, p->pa.counters + kCtrScanTicket,
@@ -719,9 +737,17 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
     const int64_t span = std::max<int64_t>(h[kCtrWaveSpan], 64);
     p->merge_stage = (int)std::min<int64_t>((span + 63) & ~(int64_t)63, kMergeStageMax);
   }
-  // size the numeric pass from the exact counts
+  // size the numeric pass from the exact counts; with only a handful of
+  // merge rows (a stencil's corners, say) sized again without the merge
+  // tier, as for the one pass
   if (!p->merge_only) {
     st = size_pass(p, kNumeric, s);
+    if (st == SPGEMM_OK && !p->merge_off && p->info.rows_merge > 0 &&
+        p->info.rows_merge * kMergeFewRows < p->A.rows) {
+      p->merge_off = 1;
+      st = size_pass(p, kNumeric, s);
+    }
+    if (st == SPGEMM_OK) st = unstage_if_few(p, kNumeric, s);
     if (st != SPGEMM_OK) return st;
   }
   p->info.c_capacity_hint = nnz;
