@@ -173,6 +173,38 @@ def test_workgroup_tier_row_with_a_long_run(sizer):
     assert got[3]["rows_global"] >= 2
 
 
+def _banded(n, half, seed):
+    # row k holds columns k - half .. k + half (clipped): B rows longer than a
+    # wave whose products fall in a narrow window
+    rng = np.random.default_rng(seed)
+    rows = [np.arange(max(0, k - half), min(n, k + half + 1), dtype=np.int32) for k in range(n)]
+    ptr = np.zeros(n + 1, np.int64)
+    ptr[1:] = np.cumsum([r.size for r in rows])
+    col = np.concatenate(rows)
+    return synth.CSR(n, n, ptr, col, rng.uniform(-1, 1, col.size))
+
+
+@pytest.mark.parametrize("half", [20, 50, 90])
+def test_counting_bitmap_rows(half):
+    # exact sizing counts rows whose columns lie in a narrow window with one
+    # bit per column; with B rows of up to 181 entries the rows longer than
+    # a wave take the bitmap's second loop; A rows of 1..24 entries
+    n = 3000
+    B = _banded(n, half, 5)
+    A = synth.random_uniform_lengths(n, 1, 24, 9)
+    # A's columns near the row index, so the window stays narrow
+    rng = np.random.default_rng(11)
+    col = np.empty_like(A.col)
+    for i in range(n):
+        s, e = A.row_ptr[i], A.row_ptr[i + 1]
+        lo, hi = max(0, i - 100), min(n, i + 100)
+        col[s:e] = np.sort(rng.choice(np.arange(lo, hi), e - s, replace=False))
+    A = synth.CSR(n, n, A.row_ptr, col.astype(np.int32), A.val)
+    want = oracle.spgemm(A, B)
+    for tier in ("default", "hash_only", "small_table"):
+        assert_bit_exact(gpu_product(A, B, "exact", tuning=TIERS[tier]), want)
+
+
 @pytest.mark.parametrize("m,k,n", [(0, 0, 0), (0, 5, 3), (4, 0, 3), (4, 5, 0), (5, 4, 3)])
 def test_empty_operands(m, k, n):
     A = synth.CSR(m, k, np.zeros(m + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
