@@ -1714,13 +1714,14 @@ __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots,
 // one pass, no merge rows): the table path is not compiled, which frees
 // registers.
 // Resident waves per SIMD: seven for the counting pass (no values: it fits
-// 70 registers without spills, and more waves hide its chain of dependent
-// loads), five for expand-sort launches, fewer where the merge lists and the
-// values take registers.
+// 70 registers without spills), five for expand-sort launches, four for the
+// table launches (the one pass spills a few registers there, which costs
+// less than the fourth wave gains: 24.0 -> 19.7 ms on the 27-point
+// product), fewer where the merge lists take registers.
 template <int MODE, int M, bool MERGE, bool ESCO = false>
 __global__ void __launch_bounds__(kWave, ESCO ? 5
                                          : MODE == kSymbolic ? 7
-                                         : (MODE == kOnePass ? (MERGE ? 2 : 3) : (MERGE && M == 8 ? 3 : 4)))
+                                         : (MODE == kOnePass ? (MERGE ? 2 : 4) : (MERGE && M == 8 ? 3 : 4)))
 k_wt(WaveTileParams p) {
   constexpr bool VALUES = (MODE != kSymbolic);
   extern __shared__ __align__(16) unsigned char lds[];
