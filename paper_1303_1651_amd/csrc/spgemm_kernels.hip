@@ -333,6 +333,7 @@ __device__ __forceinline__ int64_t global_table_bound(int64_t c) { return 3 * c 
 
 constexpr int64_t kSortMax = 1024;   // keys a wave sorts in registers (64 lanes x 16)
 constexpr int64_t kEscMax = 512;    // products of an expand-sort row (64 lanes x 8)
+constexpr int64_t kSortCountMax = 256;  // slots of a row counted by sorting (64 lanes x 4)
 
 // Smallest power of two >= x, at least kMinTable.
 __device__ __forceinline__ int64_t table_pow2(int64_t x) {
@@ -416,6 +417,17 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
       // and whose column offsets pack with a product index into one word:
       // expand, sort, combine (T slots hold the products)
       bool esc = false;
+      if (sym && !dense && mx <= kWave) {
+        // counting: the row's columns in blocks of pow2(mx) per entry of A,
+        // sorted; T slots hold the blocks
+        int64_t P = 1;
+        while (P < mx) P <<= 1;
+        const int64_t te = table_pow2((int64_t)m * P);
+        if ((int64_t)m * P <= kSortCountMax && te <= sp.table_max) {
+          esc = true;
+          T = te;
+        }
+      }
       if (!dense && !sym && mx <= kWave && ub <= kEscMax && ub < op.b_cols && 4 * ub <= 5 * c) {
         const int64_t te = table_pow2(ub);
         if (te <= sp.table_max && (((int64_t)op.b_cols - pa.f.lo[i]) << __builtin_ctzll((uint64_t)te)) < ((int64_t)1 << 31)) {
@@ -1579,6 +1591,65 @@ __device__ int32_t wave_esc_sort(const Operands &op, int64_t as, int64_t ae, int
   return n;
 }
 
+// Counting pass by sorting: the columns of row [as, ae) go to buf in one
+// block of P = pow2(maxb) slots per entry of A (each block sorted, as B's
+// rows are, the rest of it a sentinel above every column; at most
+// kSortCountMax slots), are sorted from those blocks, and the row's size is
+// the number of runs.  buf (the wave's table) is left empty.
+__device__ int32_t wave_sort_count(const Operands &op, int64_t as, int64_t ae, int32_t maxb, const RowEntries &re,
+                                   int32_t *buf) {
+  const int lane = threadIdx.x;
+  const int lw = lanes_log2(maxb);
+  const int per = kWave >> lw, sub = lane >> lw, bp = lane & ((1 << lw) - 1);
+  int32_t P = 1;
+  while (P < maxb) P <<= 1;
+  int32_t tot = 0;
+  for (int64_t g0 = as; g0 < ae; g0 += kWave) {
+    const int gn = (int)min((int64_t)kWave, ae - g0);
+    if (lane < gn) {
+      int64_t bs;
+      int32_t bl;
+      b_row_of(op, g0 + lane, bs, bl);
+      re.bs[lane] = bs;
+      re.bl[lane] = bl;
+      tot += bl;
+    }
+    wave_sync();
+    for (int e0 = 0; e0 < gn; e0 += 4 * per) {
+      int32_t jj[4], at[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * per + sub;
+        at[u] = -1;
+        jj[u] = kColMax;
+        if (e < gn && bp < P) {
+          at[u] = (int32_t)(g0 - as + e) * P + bp;
+          if (bp < re.bl[e]) jj[u] = op.b_col[re.bs[e] + bp];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (at[u] >= 0) buf[at[u]] = jj[u];
+    }
+    wave_sync();
+  }
+  const int32_t n = (int32_t)wave_sum((int64_t)tot);
+  const int32_t nl = (int32_t)(ae - as) * P;
+  if (nl <= 64) wave_sort_buf<1>(buf, nl, n, 2 * P);
+  else if (nl <= 128) wave_sort_buf<2>(buf, nl, n, 2 * P);
+  else wave_sort_buf<4>(buf, nl, n, 2 * P);   // nl <= kSortCountMax
+  int32_t runs = 0;
+  for (int32_t q0 = 0; q0 < n; q0 += kWave) {
+    const int32_t q = q0 + lane;
+    const bool head = q < n && (q == 0 || buf[q - 1] != buf[q]);
+    runs += __popcll(ballot(head));
+  }
+  wave_sync();
+  for (int32_t q = lane; q < nl; q += kWave) buf[q] = kEmpty;
+  wave_sync();
+  return runs;
+}
+
 // wave_esc_emit: combines the runs of one column of the n sorted products;
 // the rank of a run's head is its place.  WRITE: writes the row (at most lim
 // entries) to ocol/oval in column order.  Returns the row's size.
@@ -1843,6 +1914,11 @@ k_wt(WaveTileParams p) {
           fits = keep;
           if (spill) spos = o;
         }
+        continue;
+      }
+      if (MODE == kSymbolic && info_esc(__shfl(inf, r, kWave))) {
+        const int32_t c = wave_sort_count(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], re, tkeys);
+        if (lane == r) n = c;
         continue;
       }
       const WaveTable tb = wave_table(tkeys, tvals, __shfl(inf, r, kWave), p.lo[hrow], op.b_cols);
