@@ -46,7 +46,7 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace carve-up: every array 256-byte aligned.
 struct Layout {
-  size_t counters, model, partials, keys, nnz_a, ub, maxb, lo, hi, pred, cnt, info, cap, cost, tile_row, status, scan_status, big, ovf, pad_rp, pad_src, brow, total;
+  size_t counters, model, partials, keys, nnz_a, ub, maxb, lo, hi, pred, cnt, info, cap, cost, tile_row, status, scan_status, big, ovf, pad_rp, pad_src, brow, parts, total;
 };
 
 Layout layout_for(int64_t rows, int64_t brows) {
@@ -83,6 +83,7 @@ Layout layout_for(int64_t rows, int64_t brows) {
   L.pad_src = take(8 * R);
   const size_t BR = (size_t)std::max<int64_t>(brows, 0);
   L.brow = take(16 * BR);
+  L.parts = take(8 * (size_t)kMaxSplitRows * (kSplitParts + 1));
   L.total = o;
   return L;
 }
@@ -403,8 +404,12 @@ static spgemm_status run_big(spgemm_plan *p, int mode, bool overflow_list, void 
   bp.scratch = static_cast<char *>(scratch) + off;
   bp.scratch_slots = p->scratch_slots;
   bp.fast = (p->opts.flags & SPGEMM_OPT_FAST) ? 1 : 0;
+  // the list's huge rows are split into column ranges (the rows listed for
+  // the exact path after a one pass are not)
+  bp.split = overflow_list ? 0 : 1;
+  bp.parts = p->pa.parts;
   int64_t g = (int64_t)device_cus() * p->tune.blocks_per_cu;
-  g = std::min(g, nrows);
+  g = std::min(g, nrows * (bp.split ? kSplitParts : 1));
   if (per > 0) g = std::min<int64_t>(g, (int64_t)((scratch_bytes - off) / per));
   HIPCK(p, launch_big_rows(bp, mode == kSymbolic ? kSymbolic : kNumeric, (int)g, s));
   return SPGEMM_OK;
@@ -578,6 +583,7 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   p->pa.ovf = (int32_t *)(w + L.ovf);
   p->pa.pad_rp = (int64_t *)(w + L.pad_rp);
   p->pa.pad_src = (int64_t *)(w + L.pad_src);
+  p->pa.parts = (int64_t *)(w + L.parts);
   p->pa.f.brow = (int32_t *)(w + L.brow);
   p->keys = (uint64_t *)(w + L.keys);
   hipStream_t s = (hipStream_t)stream;

@@ -117,11 +117,15 @@ struct PlanArrays {
   int32_t *ovf;         // one pass: rows that outgrew their capacity (any order)
   int64_t *pad_rp;      // one pass: exclusive scan of the capacities (rows + 1)
   int64_t *pad_src;     // one pass: where a row sits in the padded buffer
+  int64_t *parts;       // workgroup tier: part words of the split rows
                         // (-1: computed straight into C)
 };
 
 constexpr int64_t kMinTable = 64;   // smallest hashed wave table (slots)
 constexpr int64_t kHugeWork = 8192;  // workgroup-tier rows of this many products start first
+constexpr int kSplitParts = 16;       // column ranges of a split huge row
+constexpr int64_t kSplitWork = 65536;  // huge rows of this many products are split
+constexpr int64_t kMaxSplitRows = 2048;  // huge rows split per launch, at most
 
 struct WaveTileParams {
   Operands op;
@@ -176,6 +180,13 @@ struct BigParams {
   char *scratch;            // per-workgroup device tables
   int64_t scratch_slots;    // slots per workgroup
   int fast;                 // reordered accumulation allowed
+  int split;                // the first kMaxSplitRows rows of the huge front of
+                            // the list take kSplitParts tickets each; those of
+                            // kSplitWork products or more are computed as
+                            // kSplitParts column ranges
+  int64_t *parts;           // per split row: kSplitParts words (done flag |
+                            // part size) and a finished-parts counter; cleared
+                            // by the launcher
 };
 
 // ---- launchers (spgemm_kernels.hip) ----

@@ -92,6 +92,28 @@ __device__ __forceinline__ void b_row_of(const Operands &op, int64_t e, int64_t 
   bl = (int32_t)(op.b_rp[k + 1] - bs);
 }
 
+// The slice of that B row whose columns lie in [c0, c1) (c1 < 0: all of
+// it), found by binary search (B's rows are sorted).
+__device__ __forceinline__ void b_row_part(const Operands &op, int64_t e, int32_t c0, int32_t c1, int64_t &bs,
+                                           int32_t &bl) {
+  b_row_of(op, e, bs, bl);
+  if (c1 < 0) return;
+  int64_t s[2];
+  const int32_t x[2] = {c0, c1};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    int64_t l = bs, h = bs + bl;
+    while (l < h) {
+      const int64_t m = (l + h) >> 1;
+      if (op.b_col[m] < x[k]) l = m + 1;
+      else h = m;
+    }
+    s[k] = l;
+  }
+  bs = s[0];
+  bl = (int32_t)(s[1] - s[0]);
+}
+
 // Features of row i (see above); the stored entries are taken eight at a
 // time, each group's loads issued at once (three dependent gather rounds).
 template <bool SPAN>
@@ -489,8 +511,11 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
     else if (big) pa.big[op.rows - 1 - (rbase + __popcll(rb & lanemask_lt()))] = (int32_t)i;
   }
   const int w = threadIdx.x / kWave;
+  // workgroups that may want a table: one per row, one per part of a
+  // split huge row
   // sums, except the two maxima (scratch, tmax) at 6 and 7
-  int64_t v[kSizeParts] = {n_tier[kTierMerge], n_tier[kTierHash], n_tier[kTierEmpty], capsum, scratch > 0 ? 1 : 0,
+  const int64_t want = scratch > 0 ? ((big && (int64_t)pa.f.ub[i] >= kSplitWork) ? kSplitParts : 1) : 0;
+  int64_t v[kSizeParts] = {n_tier[kTierMerge], n_tier[kTierHash], n_tier[kTierEmpty], capsum, want,
                            staged ? 1 : 0, scratch, tmax, esc_row ? 1 : 0};
 #pragma unroll
   for (int j = 0; j < kSizeParts; ++j) {
@@ -793,10 +818,11 @@ struct WgScratch {
   int32_t first, last;   // entries of an ordered chunk
 };
 
-// Products of the row enumerated flat over the workgroup, 256 A entries at
-// a time; fn(q_a_index, b_position, a_value) is called once per product.
+// Products of the row (those of columns in [c0, c1); c1 < 0: all)
+// enumerated flat over the workgroup, 256 A entries at a time;
+// fn(b_position, a_value) is called once per product.
 template <typename Fn>
-__device__ void wg_for_products(const Operands &op, int64_t row, WgScratch &ws, Fn fn) {
+__device__ void wg_for_products(const Operands &op, int64_t row, int32_t c0, int32_t c1, WgScratch &ws, Fn fn) {
   const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
   for (int64_t eb = as; eb < ae; eb += kBlock) {
     const int64_t e = eb + threadIdx.x;
@@ -805,7 +831,7 @@ __device__ void wg_for_products(const Operands &op, int64_t row, WgScratch &ws, 
     if (e < ae) {
       av = op.a_val ? op.a_val[e] : 0.0;
       int32_t l;
-      b_row_of(op, e, bs, l);
+      b_row_part(op, e, c0, c1, bs, l);
       bl = l;
     }
     int64_t tot;
@@ -856,8 +882,9 @@ __device__ __forceinline__ int64_t global_find(const int32_t *keys, int64_t allo
 // has room for every product (c >= the row's multiplication count or its
 // exact size), so no probe leaves it; a key that would is reported through
 // *err (kErrInconsistent) rather than dropped silently.
-__device__ int32_t wg_global_keys(const Operands &op, int64_t row, int32_t *keys, int64_t alloc,
-                                  const RowHash &hs, WgScratch &ws, double *vals_or_null, int64_t *err) {
+__device__ int32_t wg_global_keys(const Operands &op, int64_t row, int32_t c0, int32_t c1, int32_t *keys,
+                                  int64_t alloc, const RowHash &hs, WgScratch &ws, double *vals_or_null,
+                                  int64_t *err) {
   for (int64_t s = threadIdx.x; s < alloc; s += kBlock) {
     keys[s] = kEmpty;
     if (vals_or_null) vals_or_null[s] = 0.0;
@@ -867,7 +894,7 @@ __device__ int32_t wg_global_keys(const Operands &op, int64_t row, int32_t *keys
     ws.dmax = 0;
   }
   wg_sync_global();
-  wg_for_products(op, row, ws, [&](int64_t bpos, double) {
+  wg_for_products(op, row, c0, c1, ws, [&](int64_t bpos, double) {
     int32_t j = op.b_col[bpos];
     bool nw;
     int32_t disp;
@@ -922,10 +949,10 @@ __device__ __forceinline__ void wave_sync() {
 // stores of a chunk complete before the next chunk reads, so every slot is
 // accumulated in A's column order.  Fast: every product at once with atomic
 // adds.
-__device__ void wg_global_values(const Operands &op, int64_t row, const int32_t *keys, double *vals,
-                                 int64_t alloc, const RowHash &hs, WgScratch &ws, bool fast) {
+__device__ void wg_global_values(const Operands &op, int64_t row, int32_t c0, int32_t c1, const int32_t *keys,
+                                 double *vals, int64_t alloc, const RowHash &hs, WgScratch &ws, bool fast) {
   if (fast) {
-    wg_for_products(op, row, ws, [&](int64_t bpos, double av) {
+    wg_for_products(op, row, c0, c1, ws, [&](int64_t bpos, double av) {
       int32_t j = op.b_col[bpos];
       int64_t s = global_find(keys, alloc, hs, j);
       double p;
@@ -948,7 +975,7 @@ __device__ void wg_global_values(const Operands &op, int64_t row, const int32_t 
     if (e < ae) {
       av = op.a_val[e];
       int32_t l;
-      b_row_of(op, e, bs, l);
+      b_row_part(op, e, c0, c1, bs, l);
       bl = l;
     }
     int64_t tot;
@@ -2112,6 +2139,22 @@ hipError_t launch_compact(const CompactParams &cp, hipStream_t s) {
 
 // Workgroup-tier rows: one workgroup per listed row, the table in the
 // workgroup's slice of device scratch (sized by the plan).
+// Part words of a split row: done flag above the part's size.
+constexpr int64_t kPartDone = 1ll << 40;
+constexpr int64_t kPartSize = kPartDone - 1;
+
+// Workgroup-tier rows from an atomic ticket.  The first kMaxSplitRows rows of
+// the list's huge front are taken as kSplitParts items each: a row of at
+// least kSplitWork products as one item per column range (B row slices
+// found by binary search; every column is still accumulated by one
+// workgroup in A's order), a smaller one whole by its first item (the
+// others end at once).  Counting pass: each part
+// publishes its size and the last part of the row to finish writes the row's
+// count.  Numeric pass: a part publishes its size after its key pass and
+// writes its columns after those of the earlier parts, whose sizes it waits
+// for; those parts hold earlier tickets, so their workgroups are running and
+// wait on nothing later (a wait that exceeds kSpinLimit polls raises
+// kErrLookback instead of hanging).
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
   __shared__ WgScratch ws;
@@ -2123,36 +2166,105 @@ __global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
                                              (size_t)p.scratch_slots * 4);
   int64_t *err = p.counters + kCtrError;
   const int64_t nh = p.huge_ctr >= 0 ? p.counters[p.huge_ctr] : nbig;
-  __shared__ int64_t s_i;
+  const int64_t ns = p.split ? min(nh, kMaxSplitRows) : 0;
+  const int64_t nitems = nbig + ns * (kSplitParts - 1);
+  __shared__ int64_t s_i, s_off;
   while (true) {
-    // the next row from the ticket: workgroups that finish early take more
+    // the next item from the ticket: workgroups that finish early take more
     if (threadIdx.x == 0)
       s_i = (int64_t)atomicAdd((unsigned long long *)&p.counters[kCtrBigTicket], 1ull);
     __syncthreads();
     const int64_t i = s_i;
     __syncthreads();
-    if (i >= nbig) break;
-    const int64_t row = i < nh ? p.list[i] : p.list[p.list_len - 1 - (i - nh)];
-    const int64_t c = (MODE == kNumeric) ? (int64_t)p.cnt[row] : (int64_t)p.ub[row];
-    const int64_t span = (int64_t)p.hi[row] - (int64_t)p.lo[row] + 1;
-    bool dense;
-    int64_t slots;
-    const int64_t alloc = global_table_alloc(span, c, &dense, &slots);
-    if (alloc > p.scratch_slots) {
-      if (threadIdx.x == 0) atomicOr((unsigned long long *)err, (unsigned long long)kErrScratch);
-      continue;
-    }
-    const RowHash hs = make_hash(p.lo[row], p.hi[row], slots, dense);
-    const int32_t n = wg_global_keys(op, row, gkeys, alloc, hs, ws, MODE == kNumeric ? gvals : nullptr, err);
-    if (MODE == kSymbolic) {
-      if (threadIdx.x == 0) p.cnt[row] = n;
+    if (i >= nitems) break;
+    int64_t row, slot = -1;
+    int g = 0;
+    if (i < ns * kSplitParts) {
+      slot = i / kSplitParts;
+      g = (int)(i % kSplitParts);
+      row = p.list[slot];
+      if ((int64_t)p.ub[row] < kSplitWork) {
+        if (g > 0) continue;   // uniform: the row is its first item's
+        slot = -1;
+      }
     } else {
-      if (threadIdx.x == 0 && n != c) atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
-      wg_global_values(op, row, gkeys, gvals, alloc, hs, ws, p.fast != 0);
-      const int64_t o = p.c_rp[row];
+      const int64_t j = i - ns * (kSplitParts - 1);
+      row = j < nh ? p.list[j] : p.list[p.list_len - 1 - (j - nh)];
+    }
+    // the row's (or the part's) column range and its table
+    const int64_t c = (MODE == kNumeric) ? (int64_t)p.cnt[row] : (int64_t)p.ub[row];
+    int32_t lo = p.lo[row], hi = p.hi[row], c0 = 0, c1 = -1;
+    if (slot >= 0) {
+      const int64_t span = (int64_t)hi - lo + 1;
+      c0 = (int32_t)(lo + span * g / kSplitParts);
+      c1 = (int32_t)(lo + span * (g + 1) / kSplitParts);
+      lo = c0;
+      hi = c1 - 1;
+    }
+    bool work = slot < 0 || c1 > c0;
+    bool dense = false;
+    int64_t slots = 0, alloc = 0;
+    if (work) {
+      alloc = global_table_alloc((int64_t)hi - lo + 1, c, &dense, &slots);
+      if (alloc > p.scratch_slots) {
+        if (threadIdx.x == 0) atomicOr((unsigned long long *)err, (unsigned long long)kErrScratch);
+        work = false;
+      }
+    }
+    RowHash hs{};
+    if (work) hs = make_hash(lo, hi, slots, dense);
+    const int32_t n = work ? wg_global_keys(op, row, c0, c1, gkeys, alloc, hs, ws, MODE == kNumeric ? gvals : nullptr,
+                                            err)
+                           : 0;
+    int64_t *pp = slot >= 0 ? p.parts + slot * (kSplitParts + 1) : nullptr;
+    if (MODE == kSymbolic) {
+      if (threadIdx.x == 0) {
+        if (!pp) {
+          p.cnt[row] = n;
+        } else {
+          __hip_atomic_store(pp + g, kPartDone | (int64_t)n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          const int64_t done =
+              __hip_atomic_fetch_add(pp + kSplitParts, (int64_t)1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+          if (done == kSplitParts - 1) {
+            int64_t tot = 0;
+            for (int k = 0; k < kSplitParts; ++k)
+              tot += __hip_atomic_load(pp + k, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) & kPartSize;
+            p.cnt[row] = (int32_t)tot;
+          }
+        }
+      }
+    } else {
+      if (threadIdx.x == 0 && pp)
+        __hip_atomic_store(pp + g, kPartDone | (int64_t)n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (work) wg_global_values(op, row, c0, c1, gkeys, gvals, alloc, hs, ws, p.fast != 0);
+      if (threadIdx.x == 0) {
+        int64_t pre = 0;
+        if (pp) {
+          for (int k = 0; k < g; ++k) {
+            int64_t v = 0;
+            for (int64_t polls = 0;; ++polls) {
+              v = __hip_atomic_load(pp + k, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+              if (v & kPartDone) break;
+              if (polls > kSpinLimit) {
+                atomicOr((unsigned long long *)err, (unsigned long long)kErrLookback);
+                break;
+              }
+              __builtin_amdgcn_s_sleep(2);
+            }
+            pre += v & kPartSize;
+          }
+          if (g == kSplitParts - 1 && pre + n != c)
+            atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
+        } else if (n != c) {
+          atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
+        }
+        s_off = pre;
+      }
+      __syncthreads();
+      const int64_t o = p.c_rp[row] + s_off;
       const int64_t lim = max((int64_t)0, min((int64_t)n, p.c_capacity - o));
       if (threadIdx.x == 0 && lim < n) atomicOr((unsigned long long *)err, (unsigned long long)kErrCapacity);
-      wg_global_extract(gkeys, gvals, alloc, ws.dmax, ws, xl, p.c_col + o, p.c_val + o, lim);
+      if (work) wg_global_extract(gkeys, gvals, alloc, ws.dmax, ws, xl, p.c_col + o, p.c_val + o, lim);
     }
     __syncthreads();
   }
@@ -2408,6 +2520,10 @@ hipError_t launch_big_rows(const BigParams &bp, int mode, int grid, hipStream_t 
   if (grid <= 0) return hipSuccess;
   hipError_t e = launch_fill_i64(bp.counters + kCtrBigTicket, 0, 1, s);
   if (e != hipSuccess) return e;
+  if (bp.split) {
+    e = launch_fill_i64(bp.parts, 0, kMaxSplitRows * (kSplitParts + 1), s);
+    if (e != hipSuccess) return e;
+  }
   if (mode == kSymbolic) hipLaunchKernelGGL(k_big<kSymbolic>, dim3(grid), dim3(kBlock), 0, s, bp);
   else hipLaunchKernelGGL(k_big<kNumeric>, dim3(grid), dim3(kBlock), 0, s, bp);
   return hipGetLastError();

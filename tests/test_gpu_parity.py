@@ -173,6 +173,41 @@ def test_workgroup_tier_row_with_a_long_run(sizer):
     assert got[3]["rows_global"] >= 2
 
 
+@pytest.mark.parametrize("sizer", SIZERS)
+@pytest.mark.parametrize("bcols", [10, 100_000])
+def test_split_huge_rows(sizer, bcols):
+    # every fourth row of A has 1,500-3,000 entries (narrow B: 7,500-9,000),
+    # over B rows of 8-10 (narrow B, 10 columns) or 10-40 entries: rows of
+    # 65,536 or more products are computed by the workgroup tier in 16
+    # column ranges (with 10 columns most ranges are empty); the other huge
+    # rows take one range
+    rng = np.random.default_rng(bcols)
+    k = 12000 if bcols == 10 else 4000
+    lens_b = rng.integers(8, 11, k) if bcols == 10 else rng.integers(10, 41, k)
+    bptr = np.zeros(k + 1, np.int64)
+    bptr[1:] = np.cumsum(lens_b)
+    bcol = np.concatenate([np.sort(rng.choice(bcols, l, replace=False)) for l in lens_b]).astype(np.int32)
+    B = synth.CSR(k, bcols, bptr, bcol, rng.uniform(-1, 1, bcol.size))
+    big = (7500, 9001) if bcols == 10 else (1500, 3001)
+    lens_a = np.where(np.arange(40) % 4 == 0, rng.integers(*big, 40), rng.integers(1, 30, 40))
+    aptr = np.zeros(41, np.int64)
+    aptr[1:] = np.cumsum(lens_a)
+    acol = np.concatenate([np.sort(rng.choice(k, l, replace=False)) for l in lens_a]).astype(np.int32)
+    A = synth.CSR(40, k, aptr, acol, rng.uniform(-1, 1, acol.size))
+    want = oracle.spgemm(A, B)
+    for tier in ("default", "global_only", "small_table"):
+        got = gpu_product(A, B, sizer, tuning=TIERS[tier])
+        assert_bit_exact(got, want)
+    # fast mode reorders each sum: within 2 n u of the sum of the products'
+    # magnitudes (n <= 9,000 terms per entry), values of either sign
+    got = gpu_product(A, B, sizer, fast=True)
+    mag = oracle.spgemm(synth.CSR(A.rows, A.cols, A.row_ptr, A.col, np.abs(A.val)),
+                        synth.CSR(B.rows, B.cols, B.row_ptr, B.col, np.abs(B.val)))
+    np.testing.assert_array_equal(got[0], want[0])
+    np.testing.assert_array_equal(got[1], want[1])
+    assert np.all(np.abs(got[2] - want[2]) <= 2 * 9000 * 2.0 ** -53 * mag[2])
+
+
 def _banded(n, half, seed):
     # row k holds columns k - half .. k + half (clipped): B rows longer than a
     # wave whose products fall in a narrow window
