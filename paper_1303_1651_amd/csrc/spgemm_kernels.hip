@@ -815,7 +815,7 @@ struct WgScratch {
   int32_t cnt, dmax;
   int64_t run;
   int32_t dset[kDupSlots];
-  int32_t first, last;   // entries of an ordered chunk
+  int32_t first;   // extraction: the end of a chunk
 };
 
 // Products of the row (those of columns in [c0, c1); c1 < 0: all)
@@ -943,14 +943,19 @@ __device__ __forceinline__ void wave_sync() {
 
 // Values of the row into the table built by wg_global_keys.  Ordered: the
 // products are taken in A's stored order, 256 at a time over the workgroup
-// (entries of A 256 at a time, their B rows enumerated flat).  Products of
-// one chunk that share no slot (checked through an LDS set) update their
-// slots at once; a chunk where a slot repeats updates entry by entry.  The
-// stores of a chunk complete before the next chunk reads, so every slot is
+// (entries of A 256 at a time, their B rows enumerated flat), so within a
+// chunk the thread index follows A's order.  Products of one chunk that
+// share no slot (checked through an LDS set) update their slots at once; a
+// chunk where a slot repeats updates in rounds, in each of which the
+// lowest-indexed pending product of every slot applies (an LDS minimum per
+// slot in `cellmin`, kDupSlots words that hold INT32_MAX between uses): as
+// many rounds as the chunk's largest repeat count.  The stores of a round
+// complete before the next round or chunk reads, so every slot is
 // accumulated in A's column order.  Fast: every product at once with atomic
 // adds.
 __device__ void wg_global_values(const Operands &op, int64_t row, int32_t c0, int32_t c1, const int32_t *keys,
-                                 double *vals, int64_t alloc, const RowHash &hs, WgScratch &ws, bool fast) {
+                                 double *vals, int64_t alloc, const RowHash &hs, WgScratch &ws, int32_t *cellmin,
+                                 bool fast) {
   if (fast) {
     wg_for_products(op, row, c0, c1, ws, [&](int64_t bpos, double av) {
       int32_t j = op.b_col[bpos];
@@ -966,7 +971,10 @@ __device__ void wg_global_values(const Operands &op, int64_t row, int32_t c0, in
     return;
   }
   const int t = threadIdx.x;
-  for (int q = t; q < kDupSlots; q += kBlock) ws.dset[q] = -1;
+  for (int q = t; q < kDupSlots; q += kBlock) {
+    ws.dset[q] = -1;
+    cellmin[q] = 0x7fffffff;
+  }
   const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
   for (int64_t eb = as; eb < ae; eb += kBlock) {
     const int64_t e = eb + t;
@@ -986,7 +994,6 @@ __device__ void wg_global_values(const Operands &op, int64_t row, int32_t c0, in
     __syncthreads();
     for (int64_t q0 = 0; q0 < tot; q0 += kBlock) {
       const int64_t q = q0 + t;
-      int ent = kBlock;   // the product's entry within this block of A entries
       int64_t sl = -1;
       double a = 0.0, b = 0.0;
       if (q < tot) {
@@ -996,7 +1003,6 @@ __device__ void wg_global_values(const Operands &op, int64_t row, int32_t c0, in
           if (ws.pref[mid] <= q) lo = mid;
           else hi = mid - 1;
         }
-        ent = lo;
         const int64_t bpos = ws.bs[lo] + (q - ws.pref[lo]);
         a = ws.av[lo];
         b = op.b_val[bpos];
@@ -1004,7 +1010,7 @@ __device__ void wg_global_values(const Operands &op, int64_t row, int32_t c0, in
       }
       // does a slot repeat within the chunk?
       bool dup = false;
-      int32_t at = -1;
+      int32_t at = -1, cell = 0;
       if (sl >= 0) {
         uint32_t h = ((uint32_t)sl * 0x9E3779B1u) >> (32 - 10);
         while (true) {
@@ -1019,6 +1025,7 @@ __device__ void wg_global_values(const Operands &op, int64_t row, int32_t c0, in
           }
           h = (h + 1) & (kDupSlots - 1);
         }
+        cell = (int32_t)h;
       }
       const bool ordered = __syncthreads_or(dup ? 1 : 0) != 0;
       if (at >= 0) ws.dset[at] = -1;
@@ -1027,20 +1034,19 @@ __device__ void wg_global_values(const Operands &op, int64_t row, int32_t c0, in
         wave_mem_wait();
         __syncthreads();
       } else {
-        // entry by entry: the chunk's entries lie in [first, last] (its
-        // first product is thread 0's)
-        if (t == 0) {
-          ws.first = ent;
-          ws.last = 0;
-        }
-        __syncthreads();
-        if (q < tot) atomicMax(&ws.last, ent);
-        __syncthreads();
-        const int first = ws.first, last = ws.last;
-        for (int u = first; u <= last; ++u) {
-          if (ent == u && sl >= 0) gstored(vals + sl, mul_add_rn(gloadd(vals + sl), a, b));
+        // rounds: the first pending product of every slot applies
+        bool pending = sl >= 0;
+        while (__syncthreads_or(pending ? 1 : 0)) {
+          if (pending) atomicMin(&cellmin[cell], t);
+          __syncthreads();
+          const bool go = pending && cellmin[cell] == t;
+          if (go) gstored(vals + sl, mul_add_rn(gloadd(vals + sl), a, b));
           wave_mem_wait();
           __syncthreads();
+          if (go) {
+            cellmin[cell] = 0x7fffffff;
+            pending = false;
+          }
         }
       }
     }
@@ -2236,7 +2242,9 @@ __global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
     } else {
       if (threadIdx.x == 0 && pp)
         __hip_atomic_store(pp + g, kPartDone | (int64_t)n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      if (work) wg_global_values(op, row, c0, c1, gkeys, gvals, alloc, hs, ws, p.fast != 0);
+      // the extraction buffer is free until the extraction: it holds the
+      // ordered values' per-slot minima
+      if (work) wg_global_values(op, row, c0, c1, gkeys, gvals, alloc, hs, ws, xl.k, p.fast != 0);
       if (threadIdx.x == 0) {
         int64_t pre = 0;
         if (pp) {
