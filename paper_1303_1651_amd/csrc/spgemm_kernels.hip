@@ -790,19 +790,33 @@ __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, 
 // the whole table sorted in slot order, so a key's rank is the number of
 // occupied slots before it.  Tables where no key was displaced are sorted
 // already.
+// A workgroup's device table is its own (one region of the scratch per
+// workgroup): its accesses are atomics at workgroup scope, which keep the
+// waves of the workgroup coherent through the CU's L1 instead of going to
+// L2 for every access.
 __device__ __forceinline__ int32_t gload(const int32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ double gloadd(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void gstored(double *p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+__device__ __forceinline__ void gstore(int32_t *p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int32_t gcas(int32_t *p, int32_t expected, int32_t desired) {
+  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+  return expected;
+}
+// The table's writes before the barrier are seen by every wave of the
+// workgroup after it.
 __device__ __forceinline__ void wg_sync_global() {
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __syncthreads();
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 }
 
 // Write the sorted row held by an LDS table (G lanes).
@@ -859,7 +873,7 @@ __device__ __forceinline__ int32_t global_probe_insert(int32_t *keys, int64_t al
   int64_t s = h;
   *is_new = false;
   while (s < alloc) {
-    int32_t old = atomicCAS(&keys[s], kEmpty, j);
+    int32_t old = gcas(&keys[s], kEmpty, j);
     if (old == kEmpty) {
       *is_new = true;
       break;
@@ -886,8 +900,8 @@ __device__ int32_t wg_global_keys(const Operands &op, int64_t row, int32_t c0, i
                                   int64_t alloc, const RowHash &hs, WgScratch &ws, double *vals_or_null,
                                   int64_t *err) {
   for (int64_t s = threadIdx.x; s < alloc; s += kBlock) {
-    keys[s] = kEmpty;
-    if (vals_or_null) vals_or_null[s] = 0.0;
+    gstore(keys + s, kEmpty);
+    if (vals_or_null) gstored(vals_or_null + s, 0.0);
   }
   if (threadIdx.x == 0) {
     ws.cnt = 0;
@@ -1055,9 +1069,6 @@ __device__ void wg_global_values(const Operands &op, int64_t row, int32_t c0, in
   wg_sync_global();
 }
 
-__device__ __forceinline__ void gstore(int32_t *p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Run sorting (see lds_sort_runs) on a device table, one thread per run.
 __device__ void wg_sort_runs(int32_t *keys, double *vals, int64_t alloc) {
