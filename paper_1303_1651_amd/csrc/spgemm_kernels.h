@@ -124,7 +124,7 @@ struct PlanArrays {
 constexpr int64_t kMinTable = 64;   // smallest hashed wave table (slots)
 constexpr int64_t kHugeWork = 8192;  // workgroup-tier rows of this many products start first
 constexpr int kSplitParts = 16;       // column ranges of a split huge row
-constexpr int64_t kSplitWork = 65536;  // huge rows of this many products are split
+constexpr int64_t kSplitWork = 32768;  // huge rows of this many products are split
 constexpr int64_t kMaxSplitRows = 2048;  // huge rows split per launch, at most
 
 struct WaveTileParams {

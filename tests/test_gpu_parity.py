@@ -176,11 +176,12 @@ def test_workgroup_tier_row_with_a_long_run(sizer):
 @pytest.mark.parametrize("sizer", SIZERS)
 @pytest.mark.parametrize("bcols", [10, 100_000])
 def test_split_huge_rows(sizer, bcols):
-    # every fourth row of A has 1,500-3,000 entries (narrow B: 7,500-9,000),
-    # over B rows of 8-10 (narrow B, 10 columns) or 10-40 entries: rows of
-    # 65,536 or more products are computed by the workgroup tier in 16
-    # column ranges (with 10 columns most ranges are empty); the other huge
-    # rows take one range
+    # every fourth row of A has 1,500-3,000 entries (narrow B: 7,500-9,000)
+    # and every fourth, offset by two, 400-1,000 (narrow B: 1,000-3,000), over
+    # B rows of 8-10 (narrow B, 10 columns) or 10-40 entries: rows of 32,768
+    # or more products are computed by the workgroup tier in 16 column
+    # ranges (with 10 columns most ranges are empty); the other huge rows
+    # (8,192 or more) take one range
     rng = np.random.default_rng(bcols)
     k = 12000 if bcols == 10 else 4000
     lens_b = rng.integers(8, 11, k) if bcols == 10 else rng.integers(10, 41, k)
@@ -189,7 +190,9 @@ def test_split_huge_rows(sizer, bcols):
     bcol = np.concatenate([np.sort(rng.choice(bcols, l, replace=False)) for l in lens_b]).astype(np.int32)
     B = synth.CSR(k, bcols, bptr, bcol, rng.uniform(-1, 1, bcol.size))
     big = (7500, 9001) if bcols == 10 else (1500, 3001)
-    lens_a = np.where(np.arange(40) % 4 == 0, rng.integers(*big, 40), rng.integers(1, 30, 40))
+    mid = (1000, 3001) if bcols == 10 else (400, 1001)
+    sel = np.arange(40) % 4
+    lens_a = np.where(sel == 0, rng.integers(*big, 40), np.where(sel == 2, rng.integers(*mid, 40), rng.integers(1, 30, 40)))
     aptr = np.zeros(41, np.int64)
     aptr[1:] = np.cumsum(lens_a)
     acol = np.concatenate([np.sort(rng.choice(k, l, replace=False)) for l in lens_a]).astype(np.int32)
