@@ -425,6 +425,24 @@ def main():
                 details[p.name]["capacity_over_nnz_" + other] = round(
                     oper[-1][i][1]["c_capacity_hint"] / max(oper[-1][i][0], 1), 3)
         details["step_ms_" + args.sizer] = round(ms, 4)
+        # a right-hand operand given by columns (Section IV-A converts it to
+        # rows first): the transpose kernels turn B's CSC arrays (the CSR of
+        # B^T) into B by rows before the same product
+        conv = 0.0
+        for p in products:
+            b_csc = P.transpose(p.dB)
+            P.transpose(b_csc)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                P.transpose(b_csc)
+            e1.record()
+            torch.cuda.synchronize()
+            tms = e0.elapsed_time(e1) / args.steps
+            details[p.name]["csc_to_csr_ms"] = round(tms, 4)
+            conv += tms
+            del b_csc
+        details["step_ms_exact_csc_operand"] = round(details["step_ms_exact"] + conv, 4)
 
     name, dms, dbytes, dinfo = dominant
     achieved = dbytes / (dms * 1e-3) / 1e9

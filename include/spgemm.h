@@ -234,6 +234,28 @@ spgemm_status spgemm_batched(spgemm_batch *batch, void *scratch, size_t scratch_
 int spgemm_batched_uses_graph(const spgemm_batch *batch);
 void spgemm_batched_destroy(spgemm_batch *batch);
 
+/* ------------------------------------------------------ operand by columns
+ * Section IV-A takes a right-hand operand stored by columns (CSC) by
+ * converting it to rows first.  The arrays of a CSC matrix (column
+ * pointers, row indices, values) are those of the CSR of its transpose, so
+ * the conversion is a transpose: pass the CSC arrays of B as the CSR of B^T
+ * (rows = B.cols, cols = B.rows) and get B in CSR.
+ *
+ * spgemm_transpose writes the CSR of M^T (M->cols rows, M->rows columns):
+ * t_row_ptr (device, M->cols + 1 int64), t_col and t_val (device, M->nnz
+ * each; t_val may be NULL, then no values are moved and M->val may be
+ * NULL).  M must be canonical (see spgemm_csr); the columns of every row of
+ * the transpose then come out strictly increasing.  scratch: device,
+ * spgemm_transpose_scratch(M) bytes, 256-byte aligned.  Errors:
+ * SPGEMM_E_NULL, SPGEMM_E_DIM (negative sizes, or row_ptr[rows] != nnz),
+ * SPGEMM_E_INDEX_OVERFLOW (rows or cols >= 2^31), SPGEMM_E_WORKSPACE,
+ * SPGEMM_E_NOT_CANONICAL (a column index outside [0, cols): such entries
+ * are skipped and the output is not the transpose), SPGEMM_E_HIP,
+ * SPGEMM_E_STATE.  Synchronises `stream`. */
+size_t spgemm_transpose_scratch(const spgemm_csr *M);
+spgemm_status spgemm_transpose(const spgemm_csr *M, int64_t *t_row_ptr, int32_t *t_col, double *t_val,
+                               void *scratch, size_t scratch_bytes, void *stream);
+
 /* ------------------------------------------------------------- learned sizer
  * A 3-32-32-1 perceptron (ReLU, logistic output, FP32, 1217 parameters)
  * mapping per-row features (entries of the A row, multiplication count,

@@ -16,6 +16,9 @@ Contents
                    (Section IV-B) taken row by row.
 ``multiplications`` the paper's multiplication count (Section III):
                    sum over k of nnz(column k of A) * nnz(row k of B).
+``transpose``      the CSR of M^T: the conversion of an operand stored by
+                   columns (CSC) to rows, which Section IV-A applies before the
+                   row-major product.
 ``mlp_ref``        FP64 reference of the row-size network, its loss, backward
                    pass and Adam step (not part of the paper; parity for the
                    project's own learned sizer).
@@ -127,6 +130,21 @@ def multiplications(A, B) -> int:
     abar = np.bincount(A.col.astype(np.int64), minlength=A.cols).astype(np.int64)
     bbar = np.diff(B.row_ptr).astype(np.int64)
     return int(np.dot(abar, bbar))
+
+
+def transpose(M):
+    """The CSR of M^T (a CSC matrix's arrays are the CSR of its transpose;
+    Section IV-A converts a right-hand operand stored by columns to rows).
+    Plain definition: M's entries (r, c, v) in row order, stably sorted by c,
+    so every row of the transpose lists its columns r in increasing order."""
+    from types import SimpleNamespace
+    rows = np.repeat(np.arange(M.rows, dtype=np.int64), np.diff(M.row_ptr).astype(np.int64))
+    col = np.asarray(M.col, dtype=np.int64)
+    order = np.argsort(col, kind="stable")
+    ptr = np.zeros(M.cols + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum(np.bincount(col, minlength=M.cols))
+    return SimpleNamespace(rows=M.cols, cols=M.rows, row_ptr=ptr, col=rows[order].astype(np.int32),
+                           val=np.asarray(M.val, dtype=np.float64)[order], nnz=int(ptr[-1]))
 
 
 def flops(A, B) -> int:

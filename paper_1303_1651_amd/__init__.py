@@ -285,6 +285,31 @@ def spgemm(A: DeviceCSR, B: DeviceCSR, sizer="exact", model: Model | None = None
         plan.close()
 
 
+def transpose(M: DeviceCSR, values=True, stream=None) -> DeviceCSR:
+    """The CSR of M^T, by the library's transpose kernels.  A matrix stored by
+    columns (CSC) has the arrays of the CSR of its transpose, so
+    ``transpose(B_csc)`` gives B by rows (the conversion Section IV-A applies
+    to a right-hand operand stored by columns).  ``values=False`` moves the
+    structure only (the values of the result are then unset)."""
+    dev = M.row_ptr.device
+    t_rp = torch.empty(M.cols + 1, dtype=torch.int64, device=dev)
+    t_col = torch.empty(max(M.nnz, 1), dtype=torch.int32, device=dev)
+    t_val = torch.empty(max(M.nnz, 1), dtype=torch.float64, device=dev)
+    d = M.descriptor()
+    scratch = _bytes(_lib.spgemm_transpose_scratch(ctypes.byref(d)), dev)
+    check(_lib.spgemm_transpose(ctypes.byref(d), t_rp.data_ptr(), t_col.data_ptr(),
+                                t_val.data_ptr() if values else None, scratch.data_ptr(), scratch.numel(),
+                                _stream_ptr(stream)), "spgemm_transpose")
+    return DeviceCSR(M.cols, M.rows, t_rp, t_col[:M.nnz], t_val[:M.nnz])
+
+
+def spgemm_csc(A: DeviceCSR, B_csc: DeviceCSR, sizer="exact", **kw) -> Result:
+    """C = A * B with B stored by columns: ``B_csc`` holds B's CSC arrays as
+    the CSR of B^T (rows = B.cols).  B is converted to rows first, then the
+    row-major product runs (Section IV-A)."""
+    return spgemm(A, transpose(B_csc, stream=kw.get("stream")), sizer=sizer, **kw)
+
+
 class Batch:
     """Many independent products C_i = A_i * B_i in one plan and one
     persistent launch (graph-replayed after the first run).  Argument

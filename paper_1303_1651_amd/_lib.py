@@ -130,6 +130,10 @@ spgemm_batched_destroy = _sig("spgemm_batched_destroy", None, [P])
 EXPORTED += ["spgemm_batched_plan", "spgemm_batched_reserve", "spgemm_batched", "spgemm_batched_uses_graph",
              "spgemm_batched_destroy"]
 
+spgemm_transpose_scratch = _sig("spgemm_transpose_scratch", SZ, [CSR_P])
+spgemm_transpose = _sig("spgemm_transpose", ctypes.c_int, [CSR_P, P, P, P, P, SZ, P])
+EXPORTED += ["spgemm_transpose_scratch", "spgemm_transpose"]
+
 
 class SpgemmError(RuntimeError):
     def __init__(self, code: int, where: str, extra: str = ""):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspgemm.so")
-SOURCES = ["spgemm_kernels.hip", "spgemm_host.hip", "mlp.hip", "batched.hip"]
+SOURCES = ["spgemm_kernels.hip", "spgemm_host.hip", "mlp.hip", "batched.hip", "transpose.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,185 @@
+// Transpose of a CSR matrix: the conversion of a right-hand operand given by
+// columns (CSC) to rows (CSR).  Section IV-A multiplies CSR by CSR row by row
+// and takes a CSC right-hand side by converting it to CSR first; the arrays
+// of a CSC matrix are those of the CSR of its transpose, so the conversion is
+// this transpose.
+//
+// Steps: count the entries of every column; scan the counts into the row
+// pointers of the transpose; place every entry of M in its column's row of
+// the transpose (an atomic cursor per row, so the order inside a row is not
+// yet fixed), into scratch; then each row of the transpose is written in
+// increasing column order, every entry at the number of smaller columns in
+// its row (the columns of a row are distinct for a canonical M).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device_common.h"
+#include "spgemm_internal.h"
+#include "spgemm_kernels.h"
+
+namespace spg {
+namespace {
+
+constexpr int64_t kTrErrRange = 1;     // a column index outside [0, cols)
+constexpr int64_t kTrErrRowPtr = 2;    // row_ptr[rows] differs from nnz
+
+__global__ void __launch_bounds__(kBlock) k_tr_zero(int32_t *p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_tr_check(const int64_t *rp, int64_t rows, int64_t nnz, int64_t *err) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && rp[rows] != nnz)
+    atomicOr((unsigned long long *)err, (unsigned long long)kTrErrRowPtr);
+}
+
+// Entries per column of M (rows of the transpose).
+__global__ void __launch_bounds__(kBlock) k_tr_count(const int32_t *col, int64_t nnz, int64_t cols, int32_t *cnt,
+                                                     int64_t *err) {
+  for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kBlock) {
+    const int32_t c = col[e];
+    if (c < 0 || (int64_t)c >= cols) {
+      atomicOr((unsigned long long *)err, (unsigned long long)kTrErrRange);
+      continue;
+    }
+    atomicAdd(&cnt[c], 1);
+  }
+}
+
+// One wave per row r of M: entry (r, c) takes the next place of row c of the
+// transpose (in scratch).
+__global__ void __launch_bounds__(kBlock) k_tr_scatter(const int64_t *rp, const int32_t *col, const double *val,
+                                                       int64_t rows, int64_t cols, const int64_t *t_rp,
+                                                       int32_t *cursor, int32_t *tmp_col, double *tmp_val) {
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+  for (int64_t r = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave; r < rows; r += nw) {
+    const int64_t e1 = rp[r + 1];
+    for (int64_t e = rp[r] + lane; e < e1; e += kWave) {
+      const int32_t c = col[e];
+      if (c < 0 || (int64_t)c >= cols) continue;   // reported by the count
+      const int64_t at = t_rp[c] + atomicAdd(&cursor[c], 1);
+      tmp_col[at] = (int32_t)r;
+      if (tmp_val) tmp_val[at] = val[e];
+    }
+  }
+}
+
+// One wave per row of the transpose: each entry goes to the number of
+// smaller columns in the row, counted 64 columns at a time (every lane
+// holds one of them, shared by shuffles).
+__global__ void __launch_bounds__(kBlock) k_tr_order(const int64_t *t_rp, int64_t t_rows, const int32_t *tmp_col,
+                                                     const double *tmp_val, int32_t *t_col, double *t_val) {
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+  for (int64_t q = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave; q < t_rows; q += nw) {
+    const int64_t s = t_rp[q], len = t_rp[q + 1] - s;
+    for (int64_t i0 = 0; i0 < len; i0 += kWave) {
+      const int64_t i = i0 + lane;
+      const int32_t key = i < len ? tmp_col[s + i] : 0x7fffffff;
+      int64_t rank = 0;
+      for (int64_t j0 = 0; j0 < len; j0 += kWave) {
+        const int32_t other = j0 + lane < len ? tmp_col[s + j0 + lane] : 0x7fffffff;
+#pragma unroll 8
+        for (int d = 0; d < kWave; ++d) rank += __shfl(other, d, kWave) < key ? 1 : 0;
+      }
+      if (i < len) {
+        t_col[s + rank] = key;
+        if (t_val) t_val[s + rank] = tmp_val[s + i];
+      }
+    }
+  }
+}
+
+struct TrLayout {
+  size_t cnt, cursor, tmp_col, tmp_val, status, ctr, total;
+};
+
+TrLayout tr_layout(int64_t cols, int64_t nnz) {
+  TrLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = (o + std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    return at;
+  };
+  const size_t C = (size_t)std::max<int64_t>(cols, 0), N = (size_t)std::max<int64_t>(nnz, 0);
+  L.cnt = take(4 * C);
+  L.cursor = take(4 * C);
+  L.tmp_col = take(4 * N);
+  L.tmp_val = take(8 * N);
+  L.status = take(8 * (C / 2048 + 2));   // scan tiles (at most one per 2048 entries)
+  L.ctr = take(8 * 4);                    // error word, scan ticket, scan total
+  L.total = o;
+  return L;
+}
+
+int grid_for(int64_t work, int per_block) {
+  const int64_t b = (work + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1 << 16));
+}
+
+}  // namespace
+}  // namespace spg
+
+using namespace spg;
+
+extern "C" {
+
+size_t spgemm_transpose_scratch(const spgemm_csr *M) {
+  if (!M) return 0;
+  return tr_layout(M->cols, M->nnz).total;
+}
+
+spgemm_status spgemm_transpose(const spgemm_csr *M, int64_t *t_row_ptr, int32_t *t_col, double *t_val,
+                               void *scratch, size_t scratch_bytes, void *stream) {
+  if (!M || !t_row_ptr || !scratch) return SPGEMM_E_NULL;
+  if (M->rows < 0 || M->cols < 0 || M->nnz < 0) return SPGEMM_E_DIM;
+  if (!M->row_ptr || (M->nnz > 0 && (!M->col_idx || !t_col)) || (M->nnz > 0 && t_val && !M->val))
+    return SPGEMM_E_NULL;
+  if (M->rows >= ((int64_t)1 << 31) || M->cols >= ((int64_t)1 << 31)) return SPGEMM_E_INDEX_OVERFLOW;
+  const TrLayout L = tr_layout(M->cols, M->nnz);
+  if (scratch_bytes < L.total || !aligned256(scratch)) return SPGEMM_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char *w = static_cast<char *>(scratch);
+  int32_t *cnt = reinterpret_cast<int32_t *>(w + L.cnt);
+  int32_t *cursor = reinterpret_cast<int32_t *>(w + L.cursor);
+  int32_t *tmp_col = reinterpret_cast<int32_t *>(w + L.tmp_col);
+  double *tmp_val = t_val ? reinterpret_cast<double *>(w + L.tmp_val) : nullptr;
+  uint64_t *status = reinterpret_cast<uint64_t *>(w + L.status);
+  int64_t *ctr = reinterpret_cast<int64_t *>(w + L.ctr);   // [0] error, [1] ticket, [2] total
+  const int64_t rows = M->rows, cols = M->cols, nnz = M->nnz;
+  if (launch_fill_i64(ctr, 0, 4, s) != hipSuccess) return SPGEMM_E_HIP;
+  // the row pointers must cover nnz before any row is walked
+  hipLaunchKernelGGL(k_tr_check, dim3(1), dim3(kBlock), 0, s, M->row_ptr, rows, nnz, ctr);
+  if (hipGetLastError() != hipSuccess) return SPGEMM_E_HIP;
+  int64_t herr = 0;
+  if (hipMemcpyAsync(&herr, ctr, sizeof(herr), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return SPGEMM_E_HIP;
+  if (herr & kTrErrRowPtr) return SPGEMM_E_DIM;
+  hipLaunchKernelGGL(k_tr_zero, dim3(grid_for(cols, kBlock)), dim3(kBlock), 0, s, cnt, cols);
+  hipLaunchKernelGGL(k_tr_zero, dim3(grid_for(cols, kBlock)), dim3(kBlock), 0, s, cursor, cols);
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_tr_count, dim3(grid_for(nnz, kBlock)), dim3(kBlock), 0, s, M->col_idx, nnz, cols, cnt,
+                       ctr);
+  if (hipGetLastError() != hipSuccess) return SPGEMM_E_HIP;
+  if (launch_scan_i32(cnt, t_row_ptr, cols, status, ctr + 1, ctr + 2, ctr, s) != hipSuccess) return SPGEMM_E_HIP;
+  const int waves_per_block = kBlock / kWave;
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_tr_scatter, dim3(grid_for(rows, waves_per_block)), dim3(kBlock), 0, s, M->row_ptr,
+                       M->col_idx, t_val ? M->val : nullptr, rows, cols, (const int64_t *)t_row_ptr, cursor, tmp_col,
+                       tmp_val);
+    hipLaunchKernelGGL(k_tr_order, dim3(grid_for(cols, waves_per_block)), dim3(kBlock), 0, s,
+                       (const int64_t *)t_row_ptr, cols, tmp_col, tmp_val, t_col, t_val);
+  }
+  if (hipGetLastError() != hipSuccess) return SPGEMM_E_HIP;
+  if (hipMemcpyAsync(&herr, ctr, sizeof(herr), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return SPGEMM_E_HIP;
+  if (herr & kTrErrRange) return SPGEMM_E_NOT_CANONICAL;
+  if (herr) return SPGEMM_E_STATE;
+  return SPGEMM_OK;
+}
+
+}  // extern "C"

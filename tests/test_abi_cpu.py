@@ -131,3 +131,20 @@ def test_batched_plan_checks_descriptors_without_a_device():
     # learned sizing without a model
     lo = L.spgemm_options(2, 0, None, None)
     assert L.spgemm_batched_plan(1, A, B, ctypes.byref(lo), rb, ctypes.byref(ws), ctypes.byref(h)) == 7
+
+
+def test_transpose_host_checks():
+    # refused before any device work
+    from paper_1303_1651_amd import _lib as L
+    M = L.spgemm_csr(4, 3, 0, 256, None, None)
+    assert L.spgemm_transpose_scratch(ctypes.byref(M)) > 0
+    assert L.spgemm_transpose(None, 256, 256, None, 256, 1 << 20, None) == 1
+    assert L.spgemm_transpose(ctypes.byref(M), None, 256, None, 256, 1 << 20, None) == 1
+    bad = L.spgemm_csr(-1, 3, 0, 256, None, None)
+    assert L.spgemm_transpose(ctypes.byref(bad), 256, 256, None, 256, 1 << 20, None) == 2
+    big = L.spgemm_csr(1 << 31, 3, 0, 256, None, None)
+    assert L.spgemm_transpose(ctypes.byref(big), 256, 256, None, 256, 1 << 20, None) == 4
+    assert L.spgemm_transpose(ctypes.byref(M), 256, 256, None, 264, 1 << 20, None) == 5   # unaligned
+    assert L.spgemm_transpose(ctypes.byref(M), 256, 256, None, 256, 16, None) == 5       # too small
+    withnnz = L.spgemm_csr(4, 3, 5, 256, None, None)                                     # no columns
+    assert L.spgemm_transpose(ctypes.byref(withnnz), 256, 256, None, 256, 1 << 20, None) == 1

@@ -254,6 +254,39 @@ def test_transpose_identity_bit_exact(seed):
     assert_same(D, (CT.row_ptr, CT.col, CT.val))
 
 
+@pytest.mark.parametrize("seed,m,n,dens", [(1, 40, 30, 0.15), (2, 1, 50, 0.5), (3, 60, 1, 0.5), (4, 25, 25, 0.0),
+                                            (5, 120, 70, 0.05)])
+def test_oracle_transpose_pins(seed, m, n, dens):
+    # the oracle's transpose (a stable sort by column) against the dense
+    # transpose, the lexsort formulation above, and T(T(M)) == M
+    M = synth.random_sparse(m, n, dens, seed + 50)
+    T = oracle.transpose(M)
+    dense = np.zeros((n, m))
+    r = np.repeat(np.arange(T.rows), np.diff(T.row_ptr))
+    dense[r, T.col] = T.val
+    np.testing.assert_array_equal(dense, M.to_dense().T)
+    L = transpose(M)
+    np.testing.assert_array_equal(T.row_ptr, L.row_ptr)
+    np.testing.assert_array_equal(T.col, L.col)
+    np.testing.assert_array_equal(bits(T.val), bits(L.val))
+    for i in range(T.rows):
+        assert np.all(np.diff(T.col[T.row_ptr[i]:T.row_ptr[i + 1]]) > 0)
+    TT = oracle.transpose(T)
+    np.testing.assert_array_equal(TT.row_ptr, M.row_ptr)
+    np.testing.assert_array_equal(TT.col, M.col)
+    np.testing.assert_array_equal(bits(TT.val), bits(M.val))
+
+
+def test_oracle_transpose_product_identity():
+    # (AB)^T = B^T A^T bit for bit, with the oracle's own transpose
+    A = synth.random_sparse(50, 40, 0.12, 71)
+    B = synth.random_sparse(40, 60, 0.12, 72)
+    C = oracle.spgemm_csr(A, B)
+    CT = oracle.transpose(C)
+    D = oracle.spgemm(oracle.transpose(B), oracle.transpose(A))
+    assert_same(D, (CT.row_ptr, CT.col, CT.val))
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_freivalds_exact_on_integers(seed):
     A = synth.random_sparse(80, 60, 0.2, seed + 30, integer=True)
