@@ -4,12 +4,13 @@
 // of a CSC matrix are those of the CSR of its transpose, so the conversion is
 // this transpose.
 //
-// Steps: count the entries of every column; scan the counts into the row
-// pointers of the transpose; place every entry of M in its column's row of
-// the transpose (an atomic cursor per row, so the order inside a row is not
-// yet fixed), into scratch; then each row of the transpose is written in
-// increasing column order, every entry at the number of smaller columns in
-// its row (the columns of a row are distinct for a canonical M).
+// Steps: count the entries of every column, each entry keeping the count it
+// found as its place in its column (an atomic add, so the order inside a
+// column is not yet fixed); scan the counts into the row pointers of the
+// transpose; move every entry of M to its place, into scratch; then each row
+// of the transpose is written in increasing column order, every entry at the
+// number of smaller columns in its row (the columns of a row are distinct
+// for a canonical M).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,32 +34,34 @@ __global__ void __launch_bounds__(kBlock) k_tr_check(const int64_t *rp, int64_t 
     atomicOr((unsigned long long *)err, (unsigned long long)kTrErrRowPtr);
 }
 
-// Entries per column of M (rows of the transpose).
+// Entries per column of M (rows of the transpose); each entry keeps its
+// place in its column.
 __global__ void __launch_bounds__(kBlock) k_tr_count(const int32_t *col, int64_t nnz, int64_t cols, int32_t *cnt,
-                                                     int64_t *err) {
+                                                     int32_t *place, int64_t *err) {
   for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kBlock) {
     const int32_t c = col[e];
     if (c < 0 || (int64_t)c >= cols) {
       atomicOr((unsigned long long *)err, (unsigned long long)kTrErrRange);
+      place[e] = -1;
       continue;
     }
-    atomicAdd(&cnt[c], 1);
+    place[e] = atomicAdd(&cnt[c], 1);
   }
 }
 
-// One wave per row r of M: entry (r, c) takes the next place of row c of the
+// One wave per row r of M: entry (r, c) goes to its place in row c of the
 // transpose (in scratch).
 __global__ void __launch_bounds__(kBlock) k_tr_scatter(const int64_t *rp, const int32_t *col, const double *val,
-                                                       int64_t rows, int64_t cols, const int64_t *t_rp,
-                                                       int32_t *cursor, int32_t *tmp_col, double *tmp_val) {
+                                                       int64_t rows, const int64_t *t_rp, const int32_t *place,
+                                                       int32_t *tmp_col, double *tmp_val) {
   const int lane = (int)(threadIdx.x & (kWave - 1));
   const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
   for (int64_t r = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave; r < rows; r += nw) {
     const int64_t e1 = rp[r + 1];
     for (int64_t e = rp[r] + lane; e < e1; e += kWave) {
-      const int32_t c = col[e];
-      if (c < 0 || (int64_t)c >= cols) continue;   // reported by the count
-      const int64_t at = t_rp[c] + atomicAdd(&cursor[c], 1);
+      const int32_t q = place[e];
+      if (q < 0) continue;   // a column out of range, reported by the count
+      const int64_t at = t_rp[col[e]] + q;
       tmp_col[at] = (int32_t)r;
       if (tmp_val) tmp_val[at] = val[e];
     }
@@ -80,8 +83,8 @@ __global__ void __launch_bounds__(kBlock) k_tr_order(const int64_t *t_rp, int64_
       int64_t rank = 0;
       for (int64_t j0 = 0; j0 < len; j0 += kWave) {
         const int32_t other = j0 + lane < len ? tmp_col[s + j0 + lane] : 0x7fffffff;
-#pragma unroll 8
-        for (int d = 0; d < kWave; ++d) rank += __shfl(other, d, kWave) < key ? 1 : 0;
+        const int dn = (int)min((int64_t)kWave, len - j0);   // uniform: the lanes holding columns
+        for (int d = 0; d < dn; ++d) rank += __shfl(other, d, kWave) < key ? 1 : 0;
       }
       if (i < len) {
         t_col[s + rank] = key;
@@ -92,7 +95,7 @@ __global__ void __launch_bounds__(kBlock) k_tr_order(const int64_t *t_rp, int64_
 }
 
 struct TrLayout {
-  size_t cnt, cursor, tmp_col, tmp_val, status, ctr, total;
+  size_t cnt, place, tmp_col, tmp_val, status, ctr, total;
 };
 
 TrLayout tr_layout(int64_t cols, int64_t nnz) {
@@ -105,7 +108,7 @@ TrLayout tr_layout(int64_t cols, int64_t nnz) {
   };
   const size_t C = (size_t)std::max<int64_t>(cols, 0), N = (size_t)std::max<int64_t>(nnz, 0);
   L.cnt = take(4 * C);
-  L.cursor = take(4 * C);
+  L.place = take(4 * N);
   L.tmp_col = take(4 * N);
   L.tmp_val = take(8 * N);
   L.status = take(8 * (C / 2048 + 2));   // scan tiles (at most one per 2048 entries)
@@ -143,7 +146,7 @@ spgemm_status spgemm_transpose(const spgemm_csr *M, int64_t *t_row_ptr, int32_t 
   hipStream_t s = (hipStream_t)stream;
   char *w = static_cast<char *>(scratch);
   int32_t *cnt = reinterpret_cast<int32_t *>(w + L.cnt);
-  int32_t *cursor = reinterpret_cast<int32_t *>(w + L.cursor);
+  int32_t *place = reinterpret_cast<int32_t *>(w + L.place);
   int32_t *tmp_col = reinterpret_cast<int32_t *>(w + L.tmp_col);
   double *tmp_val = t_val ? reinterpret_cast<double *>(w + L.tmp_val) : nullptr;
   uint64_t *status = reinterpret_cast<uint64_t *>(w + L.status);
@@ -159,17 +162,16 @@ spgemm_status spgemm_transpose(const spgemm_csr *M, int64_t *t_row_ptr, int32_t 
     return SPGEMM_E_HIP;
   if (herr & kTrErrRowPtr) return SPGEMM_E_DIM;
   hipLaunchKernelGGL(k_tr_zero, dim3(grid_for(cols, kBlock)), dim3(kBlock), 0, s, cnt, cols);
-  hipLaunchKernelGGL(k_tr_zero, dim3(grid_for(cols, kBlock)), dim3(kBlock), 0, s, cursor, cols);
   if (nnz > 0)
     hipLaunchKernelGGL(k_tr_count, dim3(grid_for(nnz, kBlock)), dim3(kBlock), 0, s, M->col_idx, nnz, cols, cnt,
-                       ctr);
+                       place, ctr);
   if (hipGetLastError() != hipSuccess) return SPGEMM_E_HIP;
   if (launch_scan_i32(cnt, t_row_ptr, cols, status, ctr + 1, ctr + 2, ctr, s) != hipSuccess) return SPGEMM_E_HIP;
   const int waves_per_block = kBlock / kWave;
   if (nnz > 0) {
     hipLaunchKernelGGL(k_tr_scatter, dim3(grid_for(rows, waves_per_block)), dim3(kBlock), 0, s, M->row_ptr,
-                       M->col_idx, t_val ? M->val : nullptr, rows, cols, (const int64_t *)t_row_ptr, cursor, tmp_col,
-                       tmp_val);
+                       M->col_idx, t_val ? M->val : nullptr, rows, (const int64_t *)t_row_ptr, (const int32_t *)place,
+                       tmp_col, tmp_val);
     hipLaunchKernelGGL(k_tr_order, dim3(grid_for(cols, waves_per_block)), dim3(kBlock), 0, s,
                        (const int64_t *)t_row_ptr, cols, tmp_col, tmp_val, t_col, t_val);
   }
