@@ -334,7 +334,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-lo", type=int, default=256)
     ap.add_argument("--batch-hi", type=int, default=4096)
-    ap.add_argument("--batch-sizer", default="upper_bound", choices=["learned", "upper_bound", "exact"])
+    ap.add_argument("--batch-sizer", default="exact", choices=["learned", "upper_bound", "exact"])
     ap.add_argument("--calibrate", action="store_true", help="also run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
                     help="write the traffic summary from two rocprofv3 --pmc runs and exit")
