@@ -49,16 +49,19 @@ __global__ void __launch_bounds__(kBlock) k_tr_count(const int32_t *col, int64_t
   }
 }
 
-// One wave per row r of M: entry (r, c) goes to its place in row c of the
-// transpose (in scratch).
+// A group of 2^lg lanes per row (2^lg at least the mean row length, at most
+// a wave), 64 >> lg rows per wave at a time.
+// Entry (r, c) of M goes to its place in row c of the transpose (in
+// scratch).
 __global__ void __launch_bounds__(kBlock) k_tr_scatter(const int64_t *rp, const int32_t *col, const double *val,
                                                        int64_t rows, const int64_t *t_rp, const int32_t *place,
-                                                       int32_t *tmp_col, double *tmp_val) {
-  const int lane = (int)(threadIdx.x & (kWave - 1));
-  const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
-  for (int64_t r = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave; r < rows; r += nw) {
+                                                       int32_t *tmp_col, double *tmp_val, int lg) {
+  const int G = 1 << lg;
+  const int gl = (int)(threadIdx.x & (G - 1));
+  const int64_t ng = (int64_t)gridDim.x * (kBlock >> lg);
+  for (int64_t r = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> lg; r < rows; r += ng) {
     const int64_t e1 = rp[r + 1];
-    for (int64_t e = rp[r] + lane; e < e1; e += kWave) {
+    for (int64_t e = rp[r] + gl; e < e1; e += G) {
       const int32_t q = place[e];
       if (q < 0) continue;   // a column out of range, reported by the count
       const int64_t at = t_rp[col[e]] + q;
@@ -68,23 +71,26 @@ __global__ void __launch_bounds__(kBlock) k_tr_scatter(const int64_t *rp, const 
   }
 }
 
-// One wave per row of the transpose: each entry goes to the number of
-// smaller columns in the row, counted 64 columns at a time (every lane
-// holds one of them, shared by shuffles).
+// Each row of the transpose (a group of 2^lg lanes): every entry goes to the
+// number of smaller columns in the row, counted 2^lg columns at a time
+// (every lane of the group holds one of them, shared by shuffles inside
+// the group; the group's lanes share the row, so they run the same loops).
 __global__ void __launch_bounds__(kBlock) k_tr_order(const int64_t *t_rp, int64_t t_rows, const int32_t *tmp_col,
-                                                     const double *tmp_val, int32_t *t_col, double *t_val) {
+                                                     const double *tmp_val, int32_t *t_col, double *t_val, int lg) {
+  const int G = 1 << lg;
   const int lane = (int)(threadIdx.x & (kWave - 1));
-  const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
-  for (int64_t q = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave; q < t_rows; q += nw) {
+  const int gl = lane & (G - 1), gbase = lane & ~(G - 1);
+  const int64_t ng = (int64_t)gridDim.x * (kBlock >> lg);
+  for (int64_t q = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> lg; q < t_rows; q += ng) {
     const int64_t s = t_rp[q], len = t_rp[q + 1] - s;
-    for (int64_t i0 = 0; i0 < len; i0 += kWave) {
-      const int64_t i = i0 + lane;
+    for (int64_t i0 = 0; i0 < len; i0 += G) {
+      const int64_t i = i0 + gl;
       const int32_t key = i < len ? tmp_col[s + i] : 0x7fffffff;
       int64_t rank = 0;
-      for (int64_t j0 = 0; j0 < len; j0 += kWave) {
-        const int32_t other = j0 + lane < len ? tmp_col[s + j0 + lane] : 0x7fffffff;
-        const int dn = (int)min((int64_t)kWave, len - j0);   // uniform: the lanes holding columns
-        for (int d = 0; d < dn; ++d) rank += __shfl(other, d, kWave) < key ? 1 : 0;
+      for (int64_t j0 = 0; j0 < len; j0 += G) {
+        const int32_t other = j0 + gl < len ? tmp_col[s + j0 + gl] : 0x7fffffff;
+        const int dn = (int)min((int64_t)G, len - j0);   // the group's lanes holding columns
+        for (int d = 0; d < dn; ++d) rank += __shfl(other, gbase + d, kWave) < key ? 1 : 0;
       }
       if (i < len) {
         t_col[s + rank] = key;
@@ -115,6 +121,15 @@ TrLayout tr_layout(int64_t cols, int64_t nnz) {
   L.ctr = take(8 * 4);                    // error word, scan ticket, scan total
   L.total = o;
   return L;
+}
+
+// log2 of the lanes per row: the power of two at least the mean length,
+// at most a wave.
+int lanes_log2_for(int64_t entries, int64_t rows) {
+  const int64_t mean = rows > 0 ? (entries + rows - 1) / rows : 1;
+  int lg = 0;
+  while ((1 << lg) < mean && lg < 6) ++lg;
+  return lg;
 }
 
 int grid_for(int64_t work, int per_block) {
@@ -167,13 +182,16 @@ spgemm_status spgemm_transpose(const spgemm_csr *M, int64_t *t_row_ptr, int32_t 
                        place, ctr);
   if (hipGetLastError() != hipSuccess) return SPGEMM_E_HIP;
   if (launch_scan_i32(cnt, t_row_ptr, cols, status, ctr + 1, ctr + 2, ctr, s) != hipSuccess) return SPGEMM_E_HIP;
-  const int waves_per_block = kBlock / kWave;
   if (nnz > 0) {
-    hipLaunchKernelGGL(k_tr_scatter, dim3(grid_for(rows, waves_per_block)), dim3(kBlock), 0, s, M->row_ptr,
+    // the ordering's work grows with the square of a row over its lanes: at
+    // least 16 lanes per row there, so that a long row in a matrix of short
+    // ones stays cheap
+    const int lg_m = lanes_log2_for(nnz, rows), lg_t = std::max(lanes_log2_for(nnz, cols), 4);
+    hipLaunchKernelGGL(k_tr_scatter, dim3(grid_for(rows, kBlock >> lg_m)), dim3(kBlock), 0, s, M->row_ptr,
                        M->col_idx, t_val ? M->val : nullptr, rows, (const int64_t *)t_row_ptr, (const int32_t *)place,
-                       tmp_col, tmp_val);
-    hipLaunchKernelGGL(k_tr_order, dim3(grid_for(cols, waves_per_block)), dim3(kBlock), 0, s,
-                       (const int64_t *)t_row_ptr, cols, tmp_col, tmp_val, t_col, t_val);
+                       tmp_col, tmp_val, lg_m);
+    hipLaunchKernelGGL(k_tr_order, dim3(grid_for(cols, kBlock >> lg_t)), dim3(kBlock), 0, s,
+                       (const int64_t *)t_row_ptr, cols, tmp_col, tmp_val, t_col, t_val, lg_t);
   }
   if (hipGetLastError() != hipSuccess) return SPGEMM_E_HIP;
   if (hipMemcpyAsync(&herr, ctr, sizeof(herr), hipMemcpyDeviceToHost, s) != hipSuccess ||
