@@ -272,18 +272,33 @@ struct PartialSpec {
 __global__ void __launch_bounds__(kBlock) k_sum_partials(const int64_t *partials, int64_t nblocks, PartialSpec ps,
                                                          int64_t *counters) {
   __shared__ int64_t red[kMaxPartials][kWavesPerBlock];
-  for (int j = 0; j < ps.n; ++j) {
-    int64_t acc = 0;
-    for (int64_t b = threadIdx.x; b < nblocks; b += kBlock) {
-      int64_t v = partials[b * ps.stride + j];
-      acc = ps.is_max[j] ? max(acc, v) : acc + v;
+  // every block's record read once for all the sums, four records in flight
+  int64_t acc[kMaxPartials];
+#pragma unroll
+  for (int j = 0; j < kMaxPartials; ++j) acc[j] = 0;
+  for (int64_t b0 = threadIdx.x; b0 < nblocks; b0 += 4 * kBlock) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t b = b0 + (int64_t)u * kBlock;
+      if (b >= nblocks) break;
+#pragma unroll
+      for (int j = 0; j < kMaxPartials; ++j) {
+        if (j >= ps.n) break;
+        const int64_t v = partials[b * ps.stride + j];
+        acc[j] = ps.is_max[j] ? max(acc[j], v) : acc[j] + v;
+      }
     }
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxPartials; ++j) {
+    if (j >= ps.n) break;
+    int64_t a = acc[j];
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) {
-      int64_t o = __shfl_xor(acc, d, kWave);
-      acc = ps.is_max[j] ? max(acc, o) : acc + o;
+      const int64_t o = __shfl_xor(a, d, kWave);
+      a = ps.is_max[j] ? max(a, o) : a + o;
     }
-    if (lane_id() == 0) red[j][threadIdx.x / kWave] = acc;
+    if (lane_id() == 0) red[j][threadIdx.x / kWave] = a;
   }
   __syncthreads();
   if (threadIdx.x < ps.n) {
