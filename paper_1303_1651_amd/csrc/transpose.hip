@@ -24,6 +24,8 @@ namespace {
 
 constexpr int64_t kTrErrRange = 1;     // a column index outside [0, cols)
 constexpr int64_t kTrErrRowPtr = 2;    // row_ptr[rows] differs from nnz
+constexpr int64_t kTrLong = 256;       // rows longer than this are ordered by a workgroup
+constexpr int kTrSortMax = 4096;       // ... by a bitonic sort in LDS up to this length
 
 __global__ void __launch_bounds__(kBlock) k_tr_zero(int32_t *p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = 0;
@@ -83,6 +85,7 @@ __global__ void __launch_bounds__(kBlock) k_tr_order(const int64_t *t_rp, int64_
   const int64_t ng = (int64_t)gridDim.x * (kBlock >> lg);
   for (int64_t q = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> lg; q < t_rows; q += ng) {
     const int64_t s = t_rp[q], len = t_rp[q + 1] - s;
+    if (len > kTrLong) continue;   // k_tr_order_long's
     for (int64_t i0 = 0; i0 < len; i0 += G) {
       const int64_t i = i0 + gl;
       const int32_t key = i < len ? tmp_col[s + i] : 0x7fffffff;
@@ -93,6 +96,62 @@ __global__ void __launch_bounds__(kBlock) k_tr_order(const int64_t *t_rp, int64_
         for (int d = 0; d < dn; ++d) rank += __shfl(other, gbase + d, kWave) < key ? 1 : 0;
       }
       if (i < len) {
+        t_col[s + rank] = key;
+        if (t_val) t_val[s + rank] = tmp_val[s + i];
+      }
+    }
+  }
+}
+
+// Rows of the transpose longer than kTrLong, one workgroup each: up to
+// kTrSortMax entries sorted as (column, source index) pairs by a bitonic
+// network in LDS (columns distinct, so the order is unique); longer rows by
+// counting the smaller columns of every entry over the whole row.
+__global__ void __launch_bounds__(kBlock) k_tr_order_long(const int64_t *t_rp, int64_t t_rows, const int32_t *tmp_col,
+                                                          const double *tmp_val, int32_t *t_col, double *t_val) {
+  __shared__ int32_t sk[kTrSortMax];
+  __shared__ int32_t si[kTrSortMax];
+  const int t = threadIdx.x;
+  for (int64_t q = blockIdx.x; q < t_rows; q += gridDim.x) {
+    const int64_t s = t_rp[q], len = t_rp[q + 1] - s;
+    if (len <= kTrLong) continue;   // uniform over the workgroup
+    if (len <= kTrSortMax) {
+      int n = 1;
+      while (n < len) n <<= 1;
+      for (int i = t; i < n; i += kBlock) {
+        sk[i] = i < len ? tmp_col[s + i] : 0x7fffffff;
+        si[i] = i;
+      }
+      __syncthreads();
+      for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          for (int i = t; i < n; i += kBlock) {
+            const int p = i ^ j;
+            if (p > i) {
+              const bool up = (i & k) == 0;
+              const int32_t a = sk[i], b = sk[p];
+              if ((a > b) == up) {
+                sk[i] = b;
+                sk[p] = a;
+                const int32_t x = si[i];
+                si[i] = si[p];
+                si[p] = x;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (int i = t; i < len; i += kBlock) {
+        t_col[s + i] = sk[i];
+        if (t_val) t_val[s + i] = tmp_val[s + si[i]];
+      }
+      __syncthreads();
+    } else {
+      for (int64_t i = t; i < len; i += kBlock) {
+        const int32_t key = tmp_col[s + i];
+        int64_t rank = 0;
+        for (int64_t j = 0; j < len; ++j) rank += tmp_col[s + j] < key ? 1 : 0;
         t_col[s + rank] = key;
         if (t_val) t_val[s + rank] = tmp_val[s + i];
       }
@@ -192,6 +251,8 @@ spgemm_status spgemm_transpose(const spgemm_csr *M, int64_t *t_row_ptr, int32_t 
                        tmp_col, tmp_val, lg_m);
     hipLaunchKernelGGL(k_tr_order, dim3(grid_for(cols, kBlock >> lg_t)), dim3(kBlock), 0, s,
                        (const int64_t *)t_row_ptr, cols, tmp_col, tmp_val, t_col, t_val, lg_t);
+    hipLaunchKernelGGL(k_tr_order_long, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(cols, 1024))),
+                       dim3(kBlock), 0, s, (const int64_t *)t_row_ptr, cols, tmp_col, tmp_val, t_col, t_val);
   }
   if (hipGetLastError() != hipSuccess) return SPGEMM_E_HIP;
   if (hipMemcpyAsync(&herr, ctr, sizeof(herr), hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -25,7 +25,15 @@ def _dense_column(n_rows, n_cols, heavy, seed):
     return synth.CSR(n_rows, n_cols, ptr, col, np.random.default_rng(seed).uniform(-1, 1, col.size))
 
 
+def _by_columns(M):
+    # the CSR of M^T: transposing it gives rows as long as M's
+    T = oracle.transpose(M)
+    return synth.CSR(T.rows, T.cols, T.row_ptr, T.col, T.val)
+
+
 CASES = {
+    # rows of the transpose of up to a few thousand entries (sorted in LDS)
+    "zipf_by_columns": lambda: _by_columns(synth.zipf_matrix(20000, 5)),
     "random_rect": lambda: synth.random_sparse(700, 300, 0.02, 3),
     "stencil27": lambda: synth.stencil(12, 3, 27),
     "zipf": lambda: synth.zipf_matrix(20000, 5),
