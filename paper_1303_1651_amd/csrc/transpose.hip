@@ -77,15 +77,21 @@ __global__ void __launch_bounds__(kBlock) k_tr_scatter(const int64_t *rp, const 
 // number of smaller columns in the row, counted 2^lg columns at a time
 // (every lane of the group holds one of them, shared by shuffles inside
 // the group; the group's lanes share the row, so they run the same loops).
+// Rows longer than kTrLong are listed (longs, counted in *nlong) for
+// k_tr_order_long.
 __global__ void __launch_bounds__(kBlock) k_tr_order(const int64_t *t_rp, int64_t t_rows, const int32_t *tmp_col,
-                                                     const double *tmp_val, int32_t *t_col, double *t_val, int lg) {
+                                                     const double *tmp_val, int32_t *t_col, double *t_val, int lg,
+                                                     int64_t *longs, int64_t *nlong) {
   const int G = 1 << lg;
   const int lane = (int)(threadIdx.x & (kWave - 1));
   const int gl = lane & (G - 1), gbase = lane & ~(G - 1);
   const int64_t ng = (int64_t)gridDim.x * (kBlock >> lg);
   for (int64_t q = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> lg; q < t_rows; q += ng) {
     const int64_t s = t_rp[q], len = t_rp[q + 1] - s;
-    if (len > kTrLong) continue;   // k_tr_order_long's
+    if (len > kTrLong) {
+      if (gl == 0) longs[atomicAdd((unsigned long long *)nlong, 1ull)] = q;
+      continue;
+    }
     for (int64_t i0 = 0; i0 < len; i0 += G) {
       const int64_t i = i0 + gl;
       const int32_t key = i < len ? tmp_col[s + i] : 0x7fffffff;
@@ -103,18 +109,20 @@ __global__ void __launch_bounds__(kBlock) k_tr_order(const int64_t *t_rp, int64_
   }
 }
 
-// Rows of the transpose longer than kTrLong, one workgroup each: up to
+// The listed rows of the transpose (longer than kTrLong), one workgroup each: up to
 // kTrSortMax entries sorted as (column, source index) pairs by a bitonic
 // network in LDS (columns distinct, so the order is unique); longer rows by
 // counting the smaller columns of every entry over the whole row.
-__global__ void __launch_bounds__(kBlock) k_tr_order_long(const int64_t *t_rp, int64_t t_rows, const int32_t *tmp_col,
+__global__ void __launch_bounds__(kBlock) k_tr_order_long(const int64_t *t_rp, const int64_t *longs,
+                                                          const int64_t *nlong, const int32_t *tmp_col,
                                                           const double *tmp_val, int32_t *t_col, double *t_val) {
   __shared__ int32_t sk[kTrSortMax];
   __shared__ int32_t si[kTrSortMax];
   const int t = threadIdx.x;
-  for (int64_t q = blockIdx.x; q < t_rows; q += gridDim.x) {
+  const int64_t nl = *nlong;
+  for (int64_t li = blockIdx.x; li < nl; li += gridDim.x) {
+    const int64_t q = longs[li];
     const int64_t s = t_rp[q], len = t_rp[q + 1] - s;
-    if (len <= kTrLong) continue;   // uniform over the workgroup
     if (len <= kTrSortMax) {
       int n = 1;
       while (n < len) n <<= 1;
@@ -160,7 +168,7 @@ __global__ void __launch_bounds__(kBlock) k_tr_order_long(const int64_t *t_rp, i
 }
 
 struct TrLayout {
-  size_t cnt, place, tmp_col, tmp_val, status, ctr, total;
+  size_t cnt, place, tmp_col, tmp_val, status, ctr, longs, total;
 };
 
 TrLayout tr_layout(int64_t cols, int64_t nnz) {
@@ -177,7 +185,8 @@ TrLayout tr_layout(int64_t cols, int64_t nnz) {
   L.tmp_col = take(4 * N);
   L.tmp_val = take(8 * N);
   L.status = take(8 * (C / 2048 + 2));   // scan tiles (at most one per 2048 entries)
-  L.ctr = take(8 * 4);                    // error word, scan ticket, scan total
+  L.ctr = take(8 * 4);                    // error word, scan ticket, scan total, long rows
+  L.longs = take(8 * (N / (kTrLong + 1) + 1));   // rows longer than kTrLong, at most
   L.total = o;
   return L;
 }
@@ -224,7 +233,8 @@ spgemm_status spgemm_transpose(const spgemm_csr *M, int64_t *t_row_ptr, int32_t 
   int32_t *tmp_col = reinterpret_cast<int32_t *>(w + L.tmp_col);
   double *tmp_val = t_val ? reinterpret_cast<double *>(w + L.tmp_val) : nullptr;
   uint64_t *status = reinterpret_cast<uint64_t *>(w + L.status);
-  int64_t *ctr = reinterpret_cast<int64_t *>(w + L.ctr);   // [0] error, [1] ticket, [2] total
+  int64_t *ctr = reinterpret_cast<int64_t *>(w + L.ctr);   // [0] error, [1] ticket, [2] total, [3] long rows
+  int64_t *longs = reinterpret_cast<int64_t *>(w + L.longs);
   const int64_t rows = M->rows, cols = M->cols, nnz = M->nnz;
   if (launch_fill_i64(ctr, 0, 4, s) != hipSuccess) return SPGEMM_E_HIP;
   // the row pointers must cover nnz before any row is walked
@@ -250,9 +260,10 @@ spgemm_status spgemm_transpose(const spgemm_csr *M, int64_t *t_row_ptr, int32_t 
                        M->col_idx, t_val ? M->val : nullptr, rows, (const int64_t *)t_row_ptr, (const int32_t *)place,
                        tmp_col, tmp_val, lg_m);
     hipLaunchKernelGGL(k_tr_order, dim3(grid_for(cols, kBlock >> lg_t)), dim3(kBlock), 0, s,
-                       (const int64_t *)t_row_ptr, cols, tmp_col, tmp_val, t_col, t_val, lg_t);
-    hipLaunchKernelGGL(k_tr_order_long, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(cols, 1024))),
-                       dim3(kBlock), 0, s, (const int64_t *)t_row_ptr, cols, tmp_col, tmp_val, t_col, t_val);
+                       (const int64_t *)t_row_ptr, cols, tmp_col, tmp_val, t_col, t_val, lg_t, longs, ctr + 3);
+    hipLaunchKernelGGL(k_tr_order_long, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(nnz / (kTrLong + 1) + 1, 1024))),
+                       dim3(kBlock), 0, s, (const int64_t *)t_row_ptr, (const int64_t *)longs, (const int64_t *)(ctr + 3),
+                       tmp_col, tmp_val, t_col, t_val);
   }
   if (hipGetLastError() != hipSuccess) return SPGEMM_E_HIP;
   if (hipMemcpyAsync(&herr, ctr, sizeof(herr), hipMemcpyDeviceToHost, s) != hipSuccess ||
