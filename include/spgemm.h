@@ -161,11 +161,21 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B,
 
 /* Symbolic pass (SPGEMM_SIZER_EXACT only): exact entries per row of C and
  * their exclusive scan, written to c_row_ptr (device, rows + 1).  *c_nnz
- * (host) receives nnz(C).  Synchronises `stream`. */
+ * (host) receives nnz(C).  Row r of C holds one entry per distinct column
+ * among the selected rows of B (Section IV-A, the row-major algorithm: the
+ * entries the dense temporary row receives); the scan gives the row
+ * offsets of the output block that Section IV-B's append/finalize contract
+ * fills in row order.  scratch: device, spgemm_info.scratch_bytes,
+ * 256-byte aligned (SPGEMM_E_WORKSPACE otherwise).  Errors: SPGEMM_E_NULL,
+ * SPGEMM_E_STATE (not an EXACT plan, or called twice), SPGEMM_E_HIP.
+ * Synchronises `stream`. */
 spgemm_status spgemm_symbolic(spgemm_plan *plan, void *scratch, size_t scratch_bytes,
                               int64_t *c_row_ptr, int64_t *c_nnz, void *stream);
 
-/* Numeric pass: writes C.  For SPGEMM_SIZER_EXACT, c_row_ptr must hold the
+/* Numeric pass: writes C, each entry accumulated from +0.0 by one FP64
+ * multiply and one FP64 add per product in A's column order (Section IV-A,
+ * the listing of the row-major kernel), each row's columns ascending
+ * (Section IV-B, append/finalize).  For SPGEMM_SIZER_EXACT, c_row_ptr must hold the
  * result of spgemm_symbolic.  For the one-pass sizers it is written here:
  * the rows are computed into a padded buffer in `scratch` (laid out by the
  * capacities), counted, scanned into c_row_ptr and moved into C.
@@ -186,7 +196,7 @@ const char *spgemm_status_string(spgemm_status s);
 
 /* ---------------------------------------------------------------- batched
  * Many independent products C_i = A_i * B_i (each as in spgemm_plan_create:
- * Section II's C = A * B row by row) computed together: the instances are
+ * Section IV-A's C = A * B row by row) computed together: the instances are
  * laid side by side in one row space (A_i's columns shifted past the B rows
  * of the instances before it, the B_i stacked), so one plan and one
  * persistent numeric launch cover every row of every instance, and C comes
@@ -264,7 +274,10 @@ spgemm_status spgemm_transpose(const spgemm_csr *M, int64_t *t_row_ptr, int32_t 
  * reaches.  Not part of the paper. */
 
 /* Model from host arrays: theta[1217] (W1 32x3, b1, W2 32x32, b2, w3, b3),
- * mu[3], sd[3]. */
+ * mu[3], sd[3].  SPGEMM_E_INVALID when a parameter is not finite or an sd
+ * is not positive (spgemm_model_load and spgemm_model_train report such a
+ * model the same way).  A finite model whose prediction still overflows to
+ * a NaN sizes that row by its multiplication count. */
 spgemm_status spgemm_model_create(const float *theta, const float *mu, const float *sd,
                                   spgemm_model **out);
 spgemm_status spgemm_model_get(const spgemm_model *m, float *theta, float *mu, float *sd);

@@ -206,7 +206,10 @@ __global__ void __launch_bounds__(kBlock) k_mlp_predict(const float *__restrict_
       const int32_t a = (int32_t)(k & ((1u << 21) - 1));
       const int32_t b = (int32_t)((k >> 21) & ((1u << 22) - 1));
       const int32_t c = (int32_t)(k >> 43);
-      const float pr = predict_coop(W, hbuf[half], a, b, c);
+      float pr = predict_coop(W, hbuf[half], a, b, c);
+      // finite weights can still overflow to a NaN: such a row is sized by
+      // its bound, which never underestimates
+      if (!(pr >= (float)c && pr <= (float)b)) pr = (float)b;
       if ((threadIdx.x & 31) == 0) upred[u] = pr;
     }
   }
@@ -524,6 +527,13 @@ extern "C" {
 
 spgemm_status spgemm_model_create(const float *theta, const float *mu, const float *sd, spgemm_model **out) {
   if (!theta || !mu || !sd || !out) return SPGEMM_E_NULL;
+  // a model whose parameters are not finite (or whose scales are not
+  // positive) would predict NaN: refused, whether it comes from the caller,
+  // a file or a training run that diverged
+  for (int i = 0; i < kMlpParams; ++i)
+    if (!std::isfinite(theta[i])) return SPGEMM_E_INVALID;
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(mu[i]) || !std::isfinite(sd[i]) || !(sd[i] > 0.0f)) return SPGEMM_E_INVALID;
   spgemm_model *m = (spgemm_model *)malloc(sizeof(spgemm_model));
   if (!m) return SPGEMM_E_INVALID;
   memcpy(m->theta, theta, sizeof(m->theta));

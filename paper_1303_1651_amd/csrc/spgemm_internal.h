@@ -41,8 +41,11 @@ hipError_t launch_mlp_capacity(const float *dev_params, const uint64_t *rowkeys,
 
 // Capacity of a row sized by the learned prediction: ceil(pred * (1 +
 // margin)) + slack, clamped to [longest selected B row, multiplication
-// count].  Shared by the sizing kernel and the prediction kernel.
+// count] (the bound itself for a prediction that is not a number in
+// [0, bound]).  Shared by the sizing kernel and the prediction kernel.
 __host__ __device__ inline int64_t learned_capacity(float pred, int32_t ub, int32_t maxb, float margin, int slack) {
+  // a prediction that is not a number in [0, ub] gives the bound
+  if (!(pred >= 0.0f && pred <= (float)ub)) return ub;
   double want = ceil((double)pred * (1.0 + (double)margin)) + (double)slack;
   double c = want < (double)maxb ? (double)maxb : want;
   return (int64_t)(c > (double)ub ? (double)ub : c);

@@ -441,7 +441,9 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
         // (the capacity without its margin), and a row whose table fills is
         // computed again by the exact path
         const bool learned1 = sp.mode == kOnePass && sp.sizer == 2;
-        const int64_t ct = learned1 ? min(max((int64_t)ceilf(sp.pred[i]), mx), ub) : c;
+        const float pf = learned1 ? sp.pred[i] : 0.0f;
+        const int64_t pc = (pf >= 0.0f && pf <= (float)ub) ? (int64_t)ceilf(pf) : ub;
+        const int64_t ct = learned1 ? min(max(pc, mx), ub) : c;
         const int64_t need = sym ? 2 * ub : ((sp.mode == kNumeric || learned1) ? 2 * ct : max(ub + 1, 2 * c));
         T = table_pow2(need);
         // one pass: a table just above the bound still never fills (the

@@ -117,6 +117,31 @@ def test_model_file_round_trip(tmp_path):
         Model.load(str(bad))
 
 
+def test_model_with_non_finite_or_bad_scale_is_rejected(tmp_path):
+    import numpy as np
+    from paper_1303_1651_amd import Model
+    from paper_1303_1651_amd._lib import SpgemmError
+    th = np.zeros(1217, np.float32)
+    for bad_th, mu, sd in [(np.nan, [0, 0, 0], [1, 1, 1]), (np.inf, [0, 0, 0], [1, 1, 1]),
+                           (0.0, [0, np.nan, 0], [1, 1, 1]), (0.0, [0, 0, 0], [1, 0, 1]),
+                           (0.0, [0, 0, 0], [1, 1, -2]), (0.0, [0, 0, 0], [1, np.inf, 1])]:
+        t = th.copy()
+        t[5] = bad_th
+        with pytest.raises(SpgemmError) as e:
+            Model.create(t, mu, sd)
+        assert e.value.code == 10          # SPGEMM_E_INVALID
+    # a file holding a NaN weight is refused by the loader the same way
+    good = Model.create(th, [0, 0, 0], [1, 1, 1])
+    p = str(tmp_path / "m.bin")
+    good.save(p)
+    raw = bytearray(open(p, "rb").read())
+    raw[12 + 4 * 7:12 + 4 * 8] = np.array([np.nan], np.float32).tobytes()
+    open(p, "wb").write(bytes(raw))
+    with pytest.raises(SpgemmError) as e:
+        Model.load(p)
+    assert e.value.code == 10
+
+
 def test_batched_plan_checks_descriptors_without_a_device():
     from paper_1303_1651_amd import _lib as L
     opts = L.spgemm_options(1, 0, None, None)

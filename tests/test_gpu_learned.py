@@ -152,6 +152,29 @@ def test_bad_model_still_gives_exact_product():
         assert got[3]["overflow_rows"] > 0 and got[3]["spilled_rows"] == 0
 
 
+@pytest.mark.parametrize("case", ["zipf", "stencil"])
+def test_network_that_overflows_to_nan_sizes_rows_by_their_bound(case):
+    # every weight is finite (the model is accepted), but in FP32 the output
+    # layer adds two products that each overflow to opposite infinities:
+    # z = 1e30 * h - 1e30 * h with h = 1e30 * relu(x0) is NaN (or, fused,
+    # infinite) on the device, 0 in exact arithmetic.  A prediction that is
+    # not a number inside [longest B row, bound] sizes the row by its bound;
+    # the product must still equal the oracle bit for bit.
+    import paper_1303_1651_amd as P
+    W1 = np.zeros((32, 3)); W1[0, 0] = 1.0; W1[1, 0] = 1.0
+    W2 = np.zeros((32, 32)); W2[0, 0] = 1e30; W2[1, 1] = 1e30
+    w3 = np.zeros(32); w3[0] = 1e30; w3[1] = -1e30
+    theta = mlp_ref.pack(W1, np.zeros(32), W2, np.zeros(32), w3, 0.0).astype(np.float32)
+    assert np.all(np.isfinite(theta))
+    model = P.Model.create(theta, [0, 0, 0], [1, 1, 1])
+    A = synth.zipf_matrix(30000, 8) if case == "zipf" else synth.stencil(64)
+    want = oracle.spgemm(A, A)
+    for tuning in (None, {"spill_ratio": -1}):
+        got = gpu_product(A, A, "learned", model=model, tuning=tuning)
+        assert_bit_exact(got, want)
+        assert got[3]["overflow_rows"] == 0
+
+
 @pytest.mark.parametrize("tuning", [None, {"merge_max_nnz": -1}])
 def test_short_capacities_spill_into_the_arena(tuning):
     # capacities of the longest selected B row for rows of several times

@@ -76,6 +76,40 @@ def test_targets_and_weights():
     np.testing.assert_array_equal(w, [1, 1, 0, 0])
 
 
+def test_inputs_by_hand():
+    # x = (log2(1 + f) - mu) / sd, feature by feature:
+    # f = (1, 3, 7): log2 = (1, 2, 3); mu = (0, 1, 1), sd = (1, 0.5, 4)
+    # -> x = (1, 2, 0.5); f = (0, 15, 0): log2 = (0, 4, 0) -> (0, 6, -0.25)
+    X = mlp_ref.inputs([1, 0], [3, 15], [7, 0], mu=[0.0, 1.0, 1.0], sd=[1.0, 0.5, 4.0])
+    np.testing.assert_array_equal(X, [[1.0, 2.0, 0.5], [0.0, 6.0, -0.25]])
+
+
+def test_prediction_maps_rho_onto_the_interval_from_the_longest_row():
+    # zero weights and b3 = ln 3: rho = 1 / (1 + 1/3) = 3/4 for every row,
+    # so the prediction is maxB + 3/4 (UB - maxB): (f3, f2) = (4, 12) -> 10,
+    # (2, 2) -> 2, (0, 8) -> 6
+    theta = np.zeros(mlp_ref.NPARAM)
+    theta[-1] = math.log(3.0)
+    p = mlp_ref.predict(theta, [0, 0, 0], [1, 1, 1], [3, 1, 4], [12, 2, 8], [4, 2, 0])
+    np.testing.assert_allclose(p, [10.0, 2.0, 6.0], rtol=1e-15)
+
+
+def test_prediction_through_the_standardised_input_by_hand():
+    # W1[0, 0] = 1, W2[0, 0] = 1, w3[0] = 1, everything else 0: z = relu(x0).
+    # f1 = 1 gives log2(2) = 1; mu0 = 0, sd0 = 1 / ln 3 -> x0 = ln 3,
+    # rho = 3/4, prediction = 4 + 0.75 * 8 = 10.  f1 = 0 gives x0 = 0 -> z = 0,
+    # rho = 1/2, prediction = 8.  mu0 = 2 with f1 = 1 gives x0 < 0: ReLU -> 8.
+    W1 = np.zeros((32, 3)); W1[0, 0] = 1.0
+    W2 = np.zeros((32, 32)); W2[0, 0] = 1.0
+    w3 = np.zeros(32); w3[0] = 1.0
+    theta = mlp_ref.pack(W1, np.zeros(32), W2, np.zeros(32), w3, 0.0)
+    sd = [1.0 / math.log(3.0), 1.0, 1.0]
+    p = mlp_ref.predict(theta, [0, 0, 0], sd, [1, 0], [12, 12], [4, 4])
+    np.testing.assert_allclose(p, [10.0, 8.0], rtol=1e-14)
+    p = mlp_ref.predict(theta, [2, 0, 0], sd, [1], [12], [4])
+    np.testing.assert_allclose(p, [8.0], rtol=1e-15)
+
+
 def test_prediction_stays_inside_bounds():
     theta = _rand_theta(9, scale=3.0)
     f3 = np.array([1, 5, 16, 0])

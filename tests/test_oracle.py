@@ -62,6 +62,58 @@ def test_hand_worked_examples(name):
     assert oracle.multiplications(A, B) == int(d["mults"][0])
     f1, ub, mx = oracle.features(A, B)
     assert list(ub) == [int(x) for x in d["row_mults"]]
+    if "row_maxb" in d:
+        assert list(f1) == [int(x) for x in d["row_nnz_a"]]
+        assert list(mx) == [int(x) for x in d["row_maxb"]]
+
+
+def test_longest_selected_row_of_the_five_point_stencil():
+    # Closed form: row i of the n x n five-point matrix selects the rows of
+    # its in-grid neighbours and itself; a row of the matrix has 1 + deg
+    # entries (deg = in-grid neighbours: 2 at a corner, 3 on an edge, 4
+    # inside).  The longest selected row is 5 wherever some selected point
+    # is interior, 4 at the corners of grids with n >= 3 (the corner selects
+    # itself (3) and two edge points (4)); every row selects five rows
+    # except corners (3) and edges (4).
+    n = 7
+    A = synth.stencil(n)
+    f1, ub, mx = oracle.features(A, A)
+    deg = lambda x, y: (x > 0) + (x < n - 1) + (y > 0) + (y < n - 1)
+    for y in range(n):
+        for x in range(n):
+            i = x + n * y
+            sel = [(x, y)] + [(x + dx, y + dy) for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1))
+                              if 0 <= x + dx < n and 0 <= y + dy < n]
+            assert f1[i] == len(sel) == 1 + deg(x, y)
+            corner = x in (0, n - 1) and y in (0, n - 1)
+            touches_interior = any(0 < a < n - 1 and 0 < b < n - 1 for a, b in sel)
+            assert touches_interior == (not corner)
+            assert mx[i] == (4 if corner else 5), (x, y)
+            assert ub[i] == sum(1 + deg(a, b) for a, b in sel)
+
+
+def test_longest_selected_row_equals_count_for_single_entry_rows():
+    # A row of A with one stored entry selects one row of B, so nnz(C_i), the
+    # bound and the longest selected row all equal that row's length
+    A = synth.random_uniform_lengths(400, 0, 1, 21)
+    B = synth.random_uniform_lengths(400, 0, 30, 22)
+    f1, ub, mx = oracle.features(A, B)
+    counts = oracle.row_counts(A, B)
+    one = f1 == 1
+    assert one.sum() > 100
+    np.testing.assert_array_equal(mx[one], counts[one])
+    np.testing.assert_array_equal(ub[one], counts[one])
+    assert np.all(mx[f1 == 0] == 0)
+
+
+def test_longest_selected_row_of_nested_rows():
+    # B rows 0..3 hold 1, 4, 2 and 3 entries; a row of A selecting {0, 2, 3}
+    # has longest selected row 3, one selecting {1} has 4, {0} has 1
+    B = synth.CSR(4, 5, np.array([0, 1, 5, 7, 10]),
+                  np.array([2, 0, 1, 2, 3, 1, 4, 0, 2, 4], np.int32), np.ones(10))
+    A = synth.CSR(3, 4, np.array([0, 3, 4, 5]), np.array([0, 2, 3, 1, 0], np.int32), np.ones(5))
+    f1, ub, mx = oracle.features(A, B)
+    assert list(f1) == [3, 1, 1] and list(ub) == [6, 4, 1] and list(mx) == [3, 4, 1]
 
 
 def test_cancelled_entry_is_kept_as_positive_zero():
