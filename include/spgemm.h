@@ -189,6 +189,27 @@ spgemm_status spgemm_numeric(spgemm_plan *plan, void *scratch, size_t scratch_by
                              int64_t *c_row_ptr, int32_t *c_col, double *c_val,
                              int64_t c_capacity, int64_t *c_nnz, void *stream);
 
+/* spgemm_numeric without a scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The scratch the numeric pass
+ * needs (the workgroup-tier device tables; for the one-pass sizers also the
+ * padded buffer and the spill arena) is taken from a static device array
+ * of spgemm_numeric_static_limit() bytes (64 MiB) that the library holds
+ * on every device it runs on until the process ends; its address is looked
+ * up once per device on the first call there.  The call allocates nothing
+ * and otherwise behaves as spgemm_numeric (same arguments, outputs and
+ * errors).  Extra errors: SPGEMM_E_WORKSPACE when the padded buffer plus one
+ * device table exceed the limit (when several tables do not fit, fewer
+ * workgroup-tier workgroups run), SPGEMM_E_STATE when the current device is
+ * not the one the plan was created on.  Every call on one device uses the
+ * same array: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller.  The counters are
+ * read back into host stack memory.  Synchronises `stream`. */
+spgemm_status spgemm_numeric_static(spgemm_plan *plan, const double *a_val, const double *b_val,
+                                    int64_t *c_row_ptr, int32_t *c_col, double *c_val,
+                                    int64_t c_capacity, int64_t *c_nnz, void *stream);
+size_t spgemm_numeric_static_limit(void);
+
 spgemm_status spgemm_plan_info(const spgemm_plan *plan, spgemm_info *info);
 int spgemm_plan_last_hip_error(const spgemm_plan *plan);
 void spgemm_plan_destroy(spgemm_plan *plan);

@@ -246,6 +246,18 @@ class Plan:
         self.refresh_info()
         return code, int(nnz.value)
 
+    def numeric_static(self, c_row_ptr, c_col, c_val, capacity=None):
+        """The numeric pass with the library's static scratch (no allocation
+        by the library; the outputs are the caller's)."""
+        cap = c_col.numel() if capacity is None else capacity
+        nnz = ctypes.c_int64()
+        code = _lib.spgemm_numeric_static(self.handle, None, None, c_row_ptr.data_ptr(),
+                                          c_col.data_ptr() if c_col.numel() else None,
+                                          c_val.data_ptr() if c_val.numel() else None, cap, ctypes.byref(nnz),
+                                          _stream_ptr(self.stream))
+        self.refresh_info()
+        return code, int(nnz.value)
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             _lib.spgemm_plan_destroy(self.handle)

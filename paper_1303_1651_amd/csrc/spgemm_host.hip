@@ -172,6 +172,7 @@ struct spgemm_plan {
   uint64_t *keys;        // packed feature triple per row
   hipEvent_t ev0, ev1;   // SPGEMM_OPT_TIMING
   int timing_pending;
+  int device;            // device current when the plan was created
 };
 
 #define HIPCK(plan, expr)                                  \
@@ -216,9 +217,10 @@ static spgemm_status device_errors(spgemm_plan *p, const int64_t *h) {
   return SPGEMM_OK;
 }
 
-// Read the device counters into the pinned host buffer (synchronises).
-static spgemm_status read_counters(spgemm_plan *p, hipStream_t s, int64_t **out) {
-  int64_t *h = host_counters();
+// Read the device counters into the pinned host buffer, or into `into`
+// (kNumCounters entries) when given (synchronises).
+static spgemm_status read_counters(spgemm_plan *p, hipStream_t s, int64_t **out, int64_t *into = nullptr) {
+  int64_t *h = into ? into : host_counters();
   if (!h) return SPGEMM_E_HIP;
   HIPCK(p, hipMemcpyAsync(h, ctr(p), sizeof(int64_t) * kNumCounters, hipMemcpyDeviceToHost, s));
   HIPCK(p, hipStreamSynchronize(s));
@@ -556,6 +558,10 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   p->ws_bytes = workspace_bytes;
   p->L = L;
   p->info.c_nnz = -1;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    free(p);
+    return SPGEMM_E_HIP;
+  }
   if (opts->flags & SPGEMM_OPT_TIMING) {
     if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess) {
       if (p->ev0) (void)hipEventDestroy(p->ev0);
@@ -761,9 +767,13 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
   return SPGEMM_OK;
 }
 
-spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes, const double *a_val,
-                             const double *b_val, int64_t *c_row_ptr, int32_t *c_col, double *c_val,
-                             int64_t c_capacity, int64_t *c_nnz, void *stream) {
+}  // extern "C"
+
+// The numeric call; `hbuf` (kNumCounters entries) receives the counters
+// when given, else the thread's pinned buffer does.
+static spgemm_status numeric_call(spgemm_plan *p, void *scratch, size_t scratch_bytes, const double *a_val,
+                                  const double *b_val, int64_t *c_row_ptr, int32_t *c_col, double *c_val,
+                                  int64_t c_capacity, int64_t *c_nnz, void *stream, int64_t *hbuf) {
   if (!p || !c_row_ptr || !c_nnz) return SPGEMM_E_NULL;
   if (c_capacity > 0 && (!c_col || !c_val)) return SPGEMM_E_NULL;
   if (c_capacity < 0) return SPGEMM_E_INVALID;
@@ -794,7 +804,7 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
   timing_end(p, s, &e);
   HIPCK(p, e);
   int64_t *h;
-  st = read_counters(p, s, &h);
+  st = read_counters(p, s, &h, hbuf);
   if (st != SPGEMM_OK) return st;
   st = device_errors(p, h);
   if (st != SPGEMM_OK) return st;
@@ -810,6 +820,63 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
   if (h[kCtrError] & kErrCapacity) return SPGEMM_E_CAPACITY;
   p->stage = 2;
   return SPGEMM_OK;
+}
+
+// ------------------------------------------- numeric pass without allocation
+// The device tables of spgemm_numeric_static live in this array, one copy
+// per device, held until the process ends.  In host code its name stands
+// for a host-side symbol, not a device address: kernels are given the
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kStaticDevices = 64;
+static __device__ __align__(256) char scratch_arena[kStaticScratchBytes];
+
+static std::mutex g_arena_mu;
+static void *g_arena_ptr[kStaticDevices];
+
+// Device address of the current device's arena, looked up once per device
+// (with that device current); nullptr when the lookup fails.
+static void *arena_of_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kStaticDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_arena_mu);
+  if (!g_arena_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch_arena)) != hipSuccess || !ptr) return nullptr;
+    g_arena_ptr[dev] = ptr;
+  }
+  return g_arena_ptr[dev];
+}
+
+extern "C" {
+
+size_t spgemm_numeric_static_limit(void) { return kStaticScratchBytes; }
+
+spgemm_status spgemm_numeric_static(spgemm_plan *p, const double *a_val, const double *b_val, int64_t *c_row_ptr,
+                                    int32_t *c_col, double *c_val, int64_t c_capacity, int64_t *c_nnz,
+                                    void *stream) {
+  if (!p || !c_row_ptr || !c_nnz) return SPGEMM_E_NULL;
+  int dev = -1;
+  HIPCK(p, hipGetDevice(&dev));
+  if (dev != p->device) return SPGEMM_E_STATE;
+  // the one pass's padded buffer and one workgroup-tier table must fit;
+  // fewer workgroup-tier workgroups run when not every table fits
+  if (pad_bytes(p) + (size_t)p->scratch_slots * 12 > kStaticScratchBytes) return SPGEMM_E_WORKSPACE;
+  void *arena = arena_of_current_device();
+  if (!arena) {
+    p->last_err = hipErrorInvalidSymbol;
+    return SPGEMM_E_HIP;
+  }
+  int64_t h[kNumCounters];
+  return numeric_call(p, arena, kStaticScratchBytes, a_val, b_val, c_row_ptr, c_col, c_val, c_capacity, c_nnz,
+                      stream, h);
+}
+
+spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes, const double *a_val,
+                             const double *b_val, int64_t *c_row_ptr, int32_t *c_col, double *c_val,
+                             int64_t c_capacity, int64_t *c_nnz, void *stream) {
+  return numeric_call(p, scratch, scratch_bytes, a_val, b_val, c_row_ptr, c_col, c_val, c_capacity, c_nnz, stream,
+                      nullptr);
 }
 
 spgemm_status spgemm_plan_info(const spgemm_plan *p, spgemm_info *info) {
