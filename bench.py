@@ -86,7 +86,8 @@ SIZER_FAMILIES = {"roofline": ("stencil", "random"), "stencil": ("stencil",), "s
 def sizer_sources(family, seed_base):
     import synth
     if family == "zipf":
-        return [(synth.zipf_matrix(1 << 18, seed_base + i),) * 2 for i in range(4)]
+        # four matrices of 2^20 rows: 2^22 rows of symbolic-pass output
+        return [(synth.zipf_matrix(1 << 20, seed_base + i),) * 2 for i in range(4)]
     if family == "stencil":
         out = [(synth.stencil(g),) * 2 for g in (64, 96, 128)]
         out += [(synth.stencil(g, dim, pts),) * 2 for pts, dim, g in ((9, 2, 64), (9, 2, 96), (27, 3, 16), (27, 3, 24))]
@@ -98,36 +99,21 @@ def sizer_sources(family, seed_base):
 def train_sizer(P, torch, workload, seed_base=1001):
     """Trains the row-size network on the GPU with the library's kernels, on
     the workload's family; labels are the exact row sizes from the symbolic
-    pass.  Every source matrix contributes the same number of rows (drawn
-    with replacement from a seeded generator), so that rare row shapes weigh
-    as much as common ones."""
-    import synth
-    feats, labels = [], []
-    pairs = [pr for fam in SIZER_FAMILIES[workload] for pr in sizer_sources(fam, seed_base)]
-    for A, B in pairs:
-        dA = P.DeviceCSR.from_host(A)
-        dB = dA if B is A else P.DeviceCSR.from_host(B)
-        f1, f2, f3 = P.row_features(dA, dB)
-        plan = P.Plan(dA, dB, "exact")
-        rp, nnz = plan.symbolic()
-        plan.close()
-        feats.append((f1, f2, f3))
-        labels.append((rp[1:] - rp[:-1]).to(torch.int32))
-    g = torch.Generator(device="cpu").manual_seed(seed_base)
-    per_source = 1 << 16
-    picks = [torch.randint(0, f[0].numel(), (per_source,), generator=g).to(f[0].device) for f in feats]
-    f1 = torch.cat([f[0][i] for f, i in zip(feats, picks)])
-    f2 = torch.cat([f[1][i] for f, i in zip(feats, picks)])
-    f3 = torch.cat([f[2][i] for f, i in zip(feats, picks)])
-    lab = torch.cat([l[i] for l, i in zip(labels, picks)])
-    # shuffle once so mini-batches mix the sources (permutation from a seed)
-    perm = torch.randperm(f1.numel(), generator=g).to(f1.device)
-    f1, f2, f3, lab = f1[perm].contiguous(), f2[perm].contiguous(), f3[perm].contiguous(), lab[perm].contiguous()
-    mu, sd = P.feature_stats(f1, f2, f3)
-    theta0 = synth.mlp_init(seed_base)
-    model, curve = P.train_model(theta0, mu, sd, f1, f2, f3, lab, epochs=30, batch_size=8192, lr=3e-3)
-    return model, {"families": list(SIZER_FAMILIES[workload]), "train_rows": int(f1.numel()),
-                   "loss_first": float(curve[0]), "loss_last": float(curve[-1])}
+    pass.  The power-law family trains on every row of its four sources
+    (2^22 rows); the others draw the same number of rows from every source
+    (with replacement, from a seeded generator), so that rare row shapes
+    weigh as much as common ones."""
+    pairs = []
+    for fam in SIZER_FAMILIES[workload]:
+        for A, B in sizer_sources(fam, seed_base):
+            dA = P.DeviceCSR.from_host(A)
+            pairs.append((dA, dA if B is A else P.DeviceCSR.from_host(B)))
+    every_row = SIZER_FAMILIES[workload] == ("zipf",)
+    model, facts = P.fit_model(pairs, seed=seed_base, per_source=None if every_row else 1 << 16,
+                               epochs=10 if every_row else 30, batch_size=16384 if every_row else 8192)
+    del pairs
+    facts["families"] = list(SIZER_FAMILIES[workload])
+    return model, facts
 
 
 class Product:

@@ -174,6 +174,55 @@ def train_model(theta0, mu, sd, f1, f2, f3, nnz_c, epochs=30, batch_size=65536, 
     return Model(h.value), curve
 
 
+def fit_model(pairs, seed=1001, per_source=None, epochs=30, batch_size=8192, lr=3e-3, theta0=None):
+    """Trains the row-size network on the device from products (A, B) of
+    DeviceCSR operands: features from the library's feature kernel, labels
+    (exact nnz(C_i)) from its symbolic pass.  ``per_source`` rows are drawn
+    from each source with replacement (a seeded generator), so that every
+    source weighs the same; None takes every row of every source.  Rows are
+    shuffled once, then trained in mini-batches by the library's kernels.
+    ``theta0``: starting parameters (1,217 floats), or None for a He-uniform
+    start drawn with ``seed``.  Returns (model, facts)."""
+    feats, labels = [], []
+    for dA, dB in pairs:
+        f1, f2, f3 = row_features(dA, dB)
+        plan = Plan(dA, dB, "exact")
+        rp, _ = plan.symbolic()
+        plan.close()
+        feats.append((f1, f2, f3))
+        labels.append((rp[1:] - rp[:-1]).to(torch.int32))
+        del rp
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    if per_source is None:
+        picks = [None] * len(feats)
+    else:
+        picks = [torch.randint(0, f[0].numel(), (per_source,), generator=g).to(f[0].device) for f in feats]
+    take = lambda x, i: x if i is None else x[i]
+    f1 = torch.cat([take(f[0], i) for f, i in zip(feats, picks)])
+    f2 = torch.cat([take(f[1], i) for f, i in zip(feats, picks)])
+    f3 = torch.cat([take(f[2], i) for f, i in zip(feats, picks)])
+    lab = torch.cat([take(l, i) for l, i in zip(labels, picks)])
+    del feats, labels
+    perm = torch.randperm(f1.numel(), generator=g).to(f1.device)
+    f1, f2, f3, lab = f1[perm].contiguous(), f2[perm].contiguous(), f3[perm].contiguous(), lab[perm].contiguous()
+    mu, sd = feature_stats(f1, f2, f3)
+    if theta0 is None:
+        theta0 = _he_uniform(seed)
+    model, curve = train_model(theta0, mu, sd, f1, f2, f3, lab, epochs=epochs, batch_size=batch_size, lr=lr)
+    return model, {"train_rows": int(f1.numel()), "loss_first": float(curve[0]), "loss_last": float(curve[-1])}
+
+
+def _he_uniform(seed, hidden=32):
+    """Start of the 3-32-32-1 network: weights uniform in +-sqrt(6 / fan_in)
+    (He et al., 2015, uniform form) from a seeded generator, biases zero."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.uniform(-1, 1, hidden * 3) * np.sqrt(6.0 / 3.0)
+    w2 = rng.uniform(-1, 1, hidden * hidden) * np.sqrt(6.0 / hidden)
+    w3 = rng.uniform(-1, 1, hidden) * np.sqrt(6.0 / hidden)
+    z = np.zeros(hidden)
+    return np.concatenate([w1, z, w2, z, w3, [0.0]]).astype(np.float32)
+
+
 @dataclass
 class Result:
     row_ptr: torch.Tensor

@@ -62,3 +62,43 @@ def sample_blocks(rows, nblocks, width, seed):
     starts = {0, max(0, rows - width)}
     starts |= set(int(x) for x in rng.integers(0, max(1, rows - width), nblocks))
     return sorted((s, min(rows, s + width)) for s in starts)
+
+
+def magnitudes(A, B, r0=0, r1=None):
+    """Per entry of C (rows r0..r1), the sum of |a_ik * b_kj| over its
+    products: the oracle's product of |A| and |B|."""
+    from types import SimpleNamespace
+    absA = SimpleNamespace(rows=A.rows, cols=A.cols, row_ptr=A.row_ptr, col=A.col, val=np.abs(A.val))
+    absB = SimpleNamespace(rows=B.rows, cols=B.cols, row_ptr=B.row_ptr, col=B.col, val=np.abs(B.val))
+    return oracle.spgemm(absA, absB, r0, r1)[2]
+
+
+def assert_fast_close(got, want, mag, rtol=1e-13):
+    """Structure bit-exact; each value within rtol * |c| of the oracle's,
+    except where the sum cancels heavily (|c| < 2^-20 * sum |a b|), where it
+    is held to rtol * sum |a b| instead.  Returns the number of such entries."""
+    gp, gc, gv = got[:3]
+    wp, wc, wv = want
+    assert_structure_equal(gp, gc, wp, wc)
+    d = np.abs(np.asarray(gv) - np.asarray(wv))
+    cancel = np.abs(wv) < 2.0 ** -20 * mag
+    bound = np.where(cancel, rtol * mag, rtol * np.abs(wv))
+    bad = d > bound
+    assert not np.any(bad), "values differ at %d entries, e.g. %s vs %s" % (
+        int(bad.sum()), np.asarray(gv)[bad][:3], np.asarray(wv)[bad][:3])
+    return int(cancel.sum())
+
+
+def check_device_blocks(rp_dev, col_dev, val_dev, A, B, blocks, base=0):
+    """Row blocks [r0, r1) of a product held on the device (row pointers
+    relative to `base` in the column and value arrays) against the oracle's
+    row-range product, bit for bit; only the blocks are copied to the host."""
+    for r0, r1 in blocks:
+        rp = rp_dev[r0:r1 + 1].cpu().numpy()
+        s, e = base + int(rp[0]), base + int(rp[-1])
+        col = col_dev[s:e].cpu().numpy()
+        val = val_dev[s:e].cpu().numpy()
+        wp, wc, wv = oracle.spgemm(A, B, r0, r1)
+        np.testing.assert_array_equal(rp - rp[0], wp)
+        np.testing.assert_array_equal(col, wc)
+        np.testing.assert_array_equal(bits(val), bits(wv))

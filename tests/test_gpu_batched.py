@@ -107,7 +107,8 @@ def test_batch_matches_per_instance_products():
     As, Bs = _dev(insts)
     batch = P.Batch(As, Bs, "upper_bound")
     batch.run()
-    for i in range(len(insts)):
+    for i, it in enumerate(insts):
+        want = oracle.spgemm(it.A, it.B)
         one = P.spgemm(As[i], Bs[i], "exact")
-        assert_bit_exact(batch.product(i), (one.row_ptr.cpu().numpy(), one.col.cpu().numpy(),
-                                            one.val.cpu().numpy()))
+        assert_bit_exact(batch.product(i), want)
+        assert_bit_exact((one.row_ptr.cpu().numpy(), one.col.cpu().numpy(), one.val.cpu().numpy()), want)

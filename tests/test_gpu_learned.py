@@ -55,7 +55,7 @@ def test_gradient_matches_fp64_oracle(seed):
     assert abs(loss - L) <= 1e-4 * abs(L) + 1e-7
     gg = grad.cpu().numpy().astype(np.float64)
     scale = np.max(np.abs(g))
-    np.testing.assert_allclose(gg, g, rtol=1e-3, atol=1e-4 * scale)
+    np.testing.assert_allclose(gg, g, rtol=1e-4, atol=1e-5 * scale)
 
 
 def test_prediction_matches_fp64_oracle():

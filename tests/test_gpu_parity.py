@@ -11,8 +11,8 @@ import pytest
 import oracle
 import synth
 from tests import golden_io
-from tests.gpu_util import (assert_bit_exact, assert_close, bits, check_row_blocks, gpu_product,
-                            sample_blocks)
+from tests.gpu_util import (assert_bit_exact, assert_close, assert_fast_close, bits, check_row_blocks,
+                            gpu_product, magnitudes, sample_blocks)
 
 pytestmark = pytest.mark.gpu
 
@@ -91,10 +91,14 @@ def test_power_law_rows():
 
 
 def test_fast_mode_within_tolerance():
+    # every row in the workgroup tier, whose FAST mode adds unordered: each
+    # entry within 1e-13 of the oracle's value (relative), or of the sum of
+    # its products' magnitudes where the sum cancels
     A = synth.zipf_matrix(20000, 12)
     want = oracle.spgemm(A, A)
-    got = gpu_product(A, A, "exact", fast=True, tuning=TIERS["global_only"])
-    assert_close(got, want, 1e-13)
+    for sizer in SIZERS:
+        got = gpu_product(A, A, sizer, fast=True, tuning=TIERS["global_only"])
+        assert_fast_close(got, want, magnitudes(A, A), 1e-13)
 
 
 def test_ordered_accumulation_on_gpu():
@@ -202,7 +206,10 @@ def test_split_huge_rows(sizer, bcols):
         got = gpu_product(A, B, sizer, tuning=TIERS[tier])
         assert_bit_exact(got, want)
     # fast mode reorders each sum: within 2 n u of the sum of the products'
-    # magnitudes (n <= 9,000 terms per entry), values of either sign
+    # magnitudes (n <= 9,000 terms per entry), values of either sign.  Sums of
+    # thousands of terms are not held to 1e-13 relative: a reordered sum of n
+    # terms can move by about n u times the magnitude sum, which for random
+    # signs is ~sqrt(n) times |c|
     got = gpu_product(A, B, sizer, fast=True)
     mag = oracle.spgemm(synth.CSR(A.rows, A.cols, A.row_ptr, A.col, np.abs(A.val)),
                         synth.CSR(B.rows, B.cols, B.row_ptr, B.col, np.abs(B.val)))
