@@ -123,9 +123,13 @@ typedef struct spgemm_options {
 
 /* Host-visible facts about a plan, filled by spgemm_plan. */
 typedef struct spgemm_info {
-    int64_t multiplications;   /* Section III count, sum over rows of the per-row bound   */
+    int64_t multiplications;   /* Section III count, sum over rows of the per-row bound
+                                  (-1 until spgemm_symbolic for an EXACT plan whose rows
+                                  all take the register merge: that pass counts them)   */
     int64_t c_capacity_hint;   /* entries to allocate for C: sum of per-row bounds
-                                  (EXACT, UPPER_BOUND) or of learned capacities (LEARNED) */
+                                  (EXACT, UPPER_BOUND) or of learned capacities (LEARNED);
+                                  -1 for an EXACT plan whose rows all take the register
+                                  merge (the exact size comes from spgemm_symbolic)     */
     int64_t c_nnz;             /* exact nnz(C) once known (after symbolic or numeric), else -1 */
     size_t scratch_bytes;      /* scratch the numeric (and symbolic) call needs            */
     int64_t rows_merge, rows_hash, rows_global, rows_empty;  /* tier histogram          */
@@ -178,7 +182,10 @@ spgemm_status spgemm_symbolic(spgemm_plan *plan, void *scratch, size_t scratch_b
  * (Section IV-B, append/finalize).  For SPGEMM_SIZER_EXACT, c_row_ptr must hold the
  * result of spgemm_symbolic.  For the one-pass sizers it is written here:
  * the rows are computed into a padded buffer in `scratch` (laid out by the
- * capacities), counted, scanned into c_row_ptr and moved into C.
+ * capacities), counted, scanned into c_row_ptr and moved into C; when every
+ * row of A has few enough entries to be merged in registers, the rows are
+ * counted, scanned and merged straight into C instead (no scratch), all on
+ * the device within this call.
  * c_col / c_val (device) have room for c_capacity entries.  If C needs more,
  * nothing past c_capacity is written, the call returns SPGEMM_E_CAPACITY and
  * *c_nnz holds the required size (call again with a larger C).  a_val and
@@ -243,8 +250,9 @@ spgemm_status spgemm_batched_plan(int64_t count, const spgemm_csr *A, const spge
  * concatenated operands in it, and plans them (features, learned or bound
  * sizing, tiers, tiles).  *c_capacity (host): entries the pools must hold
  * (sum of multiplication counts for EXACT and UPPER_BOUND, of learned
- * capacities for LEARNED); *scratch_bytes (host): device scratch the runs
- * need.  Synchronises `stream`. */
+ * capacities for LEARNED; for EXACT when every row takes the register merge,
+ * the exact total, from the symbolic pass run here); *scratch_bytes (host):
+ * device scratch the runs need.  Synchronises `stream`. */
 spgemm_status spgemm_batched_reserve(spgemm_batch *batch, void *workspace, size_t workspace_bytes,
                                      int64_t *c_capacity, size_t *scratch_bytes, void *stream);
 

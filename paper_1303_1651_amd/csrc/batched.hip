@@ -352,6 +352,15 @@ spgemm_status spgemm_batched_reserve(spgemm_batch *b, void *workspace, size_t wo
   spgemm_status st = spgemm_plan_create(&b->Acat, &b->Bcat, &o, b->ws + b->o_plan, b->plan_bytes, stream, &b->plan,
                                         &info);
   if (st != SPGEMM_OK) return st;
+  if (info.c_capacity_hint < 0) {
+    // an exact plan whose rows all merge in registers learns its sizes from
+    // its symbolic pass (which needs no scratch): the pools get the exact size
+    int64_t nnz = 0;
+    st = spgemm_symbolic(b->plan, nullptr, 0, at<int64_t>(b, b->o_crp), &nnz, stream);
+    if (st != SPGEMM_OK) return st;
+    b->symbolic_done = 1;
+    info.c_capacity_hint = nnz;
+  }
   *c_capacity = info.c_capacity_hint;
   *scratch_bytes = info.scratch_bytes;
   return SPGEMM_OK;

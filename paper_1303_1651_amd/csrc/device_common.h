@@ -80,6 +80,12 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v) {
   return v;
 }
 
+__device__ __forceinline__ int64_t wave_max64(int64_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, kWave));
+  return v;
+}
+
 __device__ __forceinline__ int32_t wave_max32(int32_t v) {
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, kWave));

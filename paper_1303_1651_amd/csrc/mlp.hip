@@ -100,9 +100,15 @@ __device__ __forceinline__ float predict_coop(const float *W, float *hbuf, int32
 // workgroup collects the distinct triples of its 2048 rows in an LDS hash,
 // evaluates the network once per distinct triple (one per lane), and hands
 // the results back to the rows.
-constexpr int kPredRowsPerThread = 4;
-constexpr int kPredRows = kBlock * kPredRowsPerThread;
-constexpr int kPredTab = 2 * kPredRows;
+// Rows per thread: four for the per-row arrays; one where the features
+// are gathered from the operands (their gathers are not overlapped across
+// a thread's rows, so more workgroups hide them better).
+template <bool FEAT>
+struct PredShape {
+  static constexpr int kRowsPerThread = FEAT ? 1 : 4;
+  static constexpr int kRows = kBlock * kRowsPerThread;
+  static constexpr int kTab = 2 * kRows;
+};
 constexpr uint64_t kNoKey = 1ull << 63;
 
 __device__ __forceinline__ uint64_t triple_key(int32_t f1, int32_t f2, int32_t f3) {
@@ -110,11 +116,11 @@ __device__ __forceinline__ uint64_t triple_key(int32_t f1, int32_t f2, int32_t f
   return (uint64_t)f1 | ((uint64_t)f2 << 21) | ((uint64_t)f3 << 43);
 }
 
-__device__ __forceinline__ uint32_t triple_hash(uint64_t k) {
+__device__ __forceinline__ uint32_t triple_hash(uint64_t k, int tab) {
   k ^= k >> 29;
   k *= 0xbf58476d1ce4e5b9ull;
   k ^= k >> 32;
-  return (uint32_t)k & (kPredTab - 1);
+  return (uint32_t)k & (uint32_t)(tab - 1);
 }
 
 // KEYS: the rows' packed feature triples come from `keys` (written by the
@@ -122,11 +128,23 @@ __device__ __forceinline__ uint32_t triple_hash(uint64_t k) {
 // per-workgroup partial sums of the learned capacity are written.
 // Otherwise the features come from the per-row arrays and the prediction
 // of every row is stored.
-template <bool KEYS>
-__global__ void __launch_bounds__(kBlock) k_mlp_predict(const float *__restrict__ dev, const uint64_t *rowkeys,
+// FEAT: the rows' feature triples are computed here from the operands (no
+// per-row arrays), only capacity sums are kept, and partials get kCapParts
+// words per workgroup: the summed capacities, their largest sum over 64
+// consecutive rows (a merge wave's rows), the multiplication count, the
+// longest row of A, the empty rows, and the summed bounds of the rows whose
+// triple does not pack (sized by their bound by the caller).  Otherwise the
+// features come from the per-row arrays and every row's prediction is stored.
+constexpr int kCapParts = 6;
+
+template <bool FEAT>
+__global__ void __launch_bounds__(kBlock) k_mlp_predict(const float *__restrict__ dev, Operands op,
                                                         const int32_t *f1a, const int32_t *f2a, const int32_t *f3a,
                                                         int64_t n, float *pred, float margin, int slack,
-                                                        int64_t *partials) {
+                                                        int64_t *partials, int64_t *err) {
+  constexpr int kPredRowsPerThread = PredShape<FEAT>::kRowsPerThread;
+  constexpr int kPredRows = PredShape<FEAT>::kRows;
+  constexpr int kPredTab = PredShape<FEAT>::kTab;
   __shared__ unsigned long long keys[kPredTab];
   __shared__ int32_t slot_idx[kPredTab];
   __shared__ uint64_t ukey[kPredRows];
@@ -139,14 +157,25 @@ __global__ void __launch_bounds__(kBlock) k_mlp_predict(const float *__restrict_
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kPredRows;
   uint64_t mine[kPredRowsPerThread];
+  int64_t mults = 0, max_a = 0, empty = 0, unpacked = 0;
+  if (FEAT && blockIdx.x == 0 && threadIdx.x == 0 &&
+      (op.a_rp[op.rows] != op.a_nnz || op.b_rp[op.b_rows] != op.b_nnz))
+    atomicOr((unsigned long long *)err, (unsigned long long)kErrDescriptor);
 #pragma unroll
   for (int j = 0; j < kPredRowsPerThread; ++j) {
     const int64_t r = base + j * kBlock + threadIdx.x;
     mine[j] = kNoKey;
     if (r < n) {
-      if (KEYS) {
-        const uint64_t k = rowkeys[r];
-        mine[j] = (k == ~0ull) ? kNoKey : k;
+      if (FEAT) {
+        int64_t m, ub;
+        int32_t mx, lo, hi;
+        row_features<false>(op, r, m, ub, mx, lo, hi);
+        const int64_t u = min(ub, (int64_t)op.b_cols);
+        mine[j] = triple_key((int32_t)min(m, (int64_t)0x7fffffff), (int32_t)u, mx);
+        if (mine[j] == kNoKey) unpacked += u;
+        mults += ub;
+        max_a = max(max_a, m);
+        empty += ub == 0 ? 1 : 0;
       } else {
         mine[j] = triple_key(f1a[r], f2a[r], f3a[r]);
       }
@@ -164,7 +193,7 @@ __global__ void __launch_bounds__(kBlock) k_mlp_predict(const float *__restrict_
       const uint64_t lk = __shfl(mine[j], leader, kWave);
       const uint64_t same = __ballot(mine[j] == lk);
       if (lane_id() == leader) {
-        uint32_t s = triple_hash(lk);
+        uint32_t s = triple_hash(lk, kPredTab);
         while (true) {
           unsigned long long cur = keys[s];
           if (cur == lk) break;
@@ -214,62 +243,92 @@ __global__ void __launch_bounds__(kBlock) k_mlp_predict(const float *__restrict_
     }
   }
   __syncthreads();
-  int64_t capsum = 0;
+  int64_t capsum = 0, wave_cap = 0;
 #pragma unroll
   for (int j = 0; j < kPredRowsPerThread; ++j) {
     const int64_t r = base + j * kBlock + threadIdx.x;
-    if (r >= n) continue;
-    const uint64_t k = mine[j];
-    float p;
-    int32_t b, c;
-    if (k == kNoKey) {
-      // features too large to pack: the row is sized by its bound (its
-      // multiplication count) instead of a prediction
-      if (KEYS) {
-        p = -1.0f;
-        b = c = 0;
+    int64_t rc = 0;   // this row's capacity
+    if (r < n) {
+      const uint64_t k = mine[j];
+      float p;
+      int32_t b, c;
+      if (k == kNoKey) {
+        // features too large to pack: the row is sized by its bound (its
+        // multiplication count) instead of a prediction
+        if (FEAT) {
+          p = -1.0f;
+          b = c = 0;
+        } else {
+          b = f2a[r];
+          c = f3a[r];
+          p = (float)b;
+        }
       } else {
-        b = f2a[r];
-        c = f3a[r];
-        p = (float)b;
+        uint32_t s = triple_hash(k, kPredTab);
+        while (keys[s] != k) s = (s + 1) & (kPredTab - 1);
+        p = upred[slot_idx[s]];
+        b = (int32_t)((k >> 21) & ((1u << 22) - 1));
+        c = (int32_t)(k >> 43);
       }
-    } else {
-      uint32_t s = triple_hash(k);
-      while (keys[s] != k) s = (s + 1) & (kPredTab - 1);
-      p = upred[slot_idx[s]];
-      b = (int32_t)((k >> 21) & ((1u << 22) - 1));
-      c = (int32_t)(k >> 43);
+      if (!FEAT) pred[r] = p;
+      if (p >= 0.0f) rc = learned_capacity(p, b, c, margin, slack);
     }
-    if (!KEYS) pred[r] = p;
-    if (p >= 0.0f) capsum += learned_capacity(p, b, c, margin, slack);
+    capsum += rc;
+    // rows base + j * kBlock + 64w .. + 63 are one merge wave's rows
+    if (FEAT) wave_cap = max(wave_cap, wave_sum(rc));
   }
-  if (partials) {
+  if (!partials) return;
+  if (FEAT) {
+    __shared__ int64_t s_part[kCapParts][kWavesPerBlock];
+    int64_t v[kCapParts] = {wave_sum(capsum), wave_cap, wave_sum(mults), wave_max64(max_a), wave_sum(empty),
+                            wave_sum(unpacked)};
+    if (lane_id() == 0)
+      for (int q = 0; q < kCapParts; ++q) s_part[q][threadIdx.x / kWave] = v[q];
+    __syncthreads();
+    if (threadIdx.x < kCapParts) {
+      const int q = threadIdx.x;
+      const bool is_max = q == 1 || q == 3;
+      int64_t t = 0;
+      for (int w = 0; w < kWavesPerBlock; ++w) t = is_max ? max(t, s_part[q][w]) : t + s_part[q][w];
+      partials[kCapParts * blockIdx.x + q] = t;
+    }
+  } else {
     int64_t tot;
     block_exclusive_sum(capsum, wtot, &tot);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
   }
 }
 
-int64_t mlp_predict_blocks(int64_t n) { return (n + kPredRows - 1) / kPredRows; }
+int64_t mlp_predict_blocks(int64_t n) { return (n + PredShape<false>::kRows - 1) / PredShape<false>::kRows; }
 
 hipError_t launch_mlp_predict(const float *dev, const int32_t *f1, const int32_t *f2, const int32_t *f3,
                               int64_t n, float *pred, hipStream_t s, float margin, int slack,
                               int64_t *partials) {
   if (n <= 0) return hipSuccess;
   int64_t blocks = mlp_predict_blocks(n);
-  hipLaunchKernelGGL(k_mlp_predict<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, dev, (const uint64_t *)nullptr,
-                     f1, f2, f3, n, pred, margin, slack, partials);
+  hipLaunchKernelGGL(k_mlp_predict<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, dev, Operands{}, f1, f2, f3, n,
+                     pred, margin, slack, partials, (int64_t *)nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_capacity(const float *dev, const uint64_t *rowkeys, int64_t n, hipStream_t s, float margin,
-                               int slack, int64_t *partials) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = mlp_predict_blocks(n);
-  hipLaunchKernelGGL(k_mlp_predict<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, dev, rowkeys,
-                     (const int32_t *)nullptr, (const int32_t *)nullptr, (const int32_t *)nullptr, n, (float *)nullptr,
-                     margin, slack, partials);
-  return hipGetLastError();
+hipError_t launch_mlp_capacity(const float *dev, const Operands &op, int64_t *counters, int64_t *partials,
+                               float margin, int slack, hipStream_t s) {
+  const int32_t dst[kCapParts] = {kCtrCapSum, kCtrWaveCap, kCtrMults, kCtrMaxA, kCtrEmpty, kCtrUnpacked};
+  const int32_t mx[kCapParts] = {0, 1, 0, 1, 0, 0};
+  if (op.rows <= 0) {
+    for (int q = 0; q < kCapParts; ++q) {
+      hipError_t e = launch_fill_i64(counters + dst[q], 0, 1, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  const int64_t blocks = (op.rows + PredShape<true>::kRows - 1) / PredShape<true>::kRows;
+  hipLaunchKernelGGL(k_mlp_predict<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, dev, op,
+                     (const int32_t *)nullptr, (const int32_t *)nullptr, (const int32_t *)nullptr, op.rows,
+                     (float *)nullptr, margin, slack, partials, counters + kCtrError);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_sum_partials(partials, blocks, kCapParts, kCapParts, dst, mx, counters, s);
 }
 
 // --------------------------------------------------------------- gradient

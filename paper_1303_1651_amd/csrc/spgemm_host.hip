@@ -46,7 +46,7 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace carve-up: every array 256-byte aligned.
 struct Layout {
-  size_t counters, model, partials, keys, nnz_a, ub, maxb, lo, hi, pred, cnt, info, cap, cost, tile_row, status, scan_status, big, ovf, pad_rp, pad_src, brow, parts, total;
+  size_t counters, model, partials, nnz_a, ub, maxb, lo, hi, pred, cnt, info, cap, cost, tile_row, status, scan_status, big, ovf, pad_rp, pad_src, brow, parts, total;
 };
 
 Layout layout_for(int64_t rows, int64_t brows) {
@@ -63,7 +63,6 @@ Layout layout_for(int64_t rows, int64_t brows) {
   L.counters = take(sizeof(int64_t) * kNumCounters);
   L.model = take(sizeof(float) * kMlpDevFloats);
   L.partials = take(sizeof(int64_t) * 10 * (R / 256 + 2));
-  L.keys = take(sizeof(uint64_t) * R);
   L.nnz_a = take(4 * R);
   L.ub = take(4 * R);
   L.maxb = take(4 * R);
@@ -169,7 +168,6 @@ struct spgemm_plan {
   spgemm_info info;
   hipError_t last_err;
   const spgemm_model *model;
-  uint64_t *keys;        // packed feature triple per row
   hipEvent_t ev0, ev1;   // SPGEMM_OPT_TIMING
   int timing_pending;
   int device;            // device current when the plan was created
@@ -241,6 +239,17 @@ static spgemm_status read_counters(spgemm_plan *p, hipStream_t s, int64_t **out,
 constexpr int kMergeOnlyLists = 16;
 constexpr double kMergeOnlyRowEst = 128.0;
 constexpr int64_t kMergeStageMax = 2048;
+
+// LDS staging (entries) of a merge wave for the largest output (numeric) or
+// capacity sum (one pass, at most kMergeOnePassStage for rows of up to 8
+// lists: capacities overstate the output) of a wave's 64 rows: rounded up to 8 entries so that
+// workgroups pack the LDS closely; waves whose output exceeds it write their
+// rows directly.
+constexpr int64_t kMergeOnePassStage = 1024;
+static int merge_stage_for(int64_t wave_max) {
+  const int64_t st = std::max<int64_t>((wave_max + 7) & ~(int64_t)7, 64);
+  return (int)std::min<int64_t>(st, kMergeStageMax);
+}
 
 // Hashed rows of at most this many entries (a wave's width) are staged in
 // LDS by the numeric pass (copied out with the tile's other rows); larger
@@ -418,11 +427,9 @@ static spgemm_status run_big(spgemm_plan *p, int mode, bool overflow_list, void 
 }
 
 static spgemm_status clear_run_counters(spgemm_plan *p, hipStream_t s) {
-  HIPCK(p, launch_fill_i64(ctr(p) + kCtrError, 0, 1, s));
-  HIPCK(p, launch_fill_i64(ctr(p) + kCtrOverflow, 0, 1, s));
-  HIPCK(p, launch_fill_i64(ctr(p) + kCtrTicket, 0, 1, s));
-  HIPCK(p, launch_fill_i64(ctr(p) + kCtrSpill, 0, 1, s));
-  HIPCK(p, launch_fill_i64(ctr(p) + kCtrSpillRows, 0, 1, s));
+  const uint32_t mask = (1u << kCtrError) | (1u << kCtrOverflow) | (1u << kCtrTicket) | (1u << kCtrSpill) |
+                        (1u << kCtrSpillRows);
+  HIPCK(p, launch_clear_counters(ctr(p), mask, s));
   return SPGEMM_OK;
 }
 
@@ -438,9 +445,18 @@ spgemm_status numeric_enqueue(spgemm_plan *p, void *scratch, size_t scratch_byte
   if (st != SPGEMM_OK) return st;
   const int mode = p->first_mode == kSymbolic ? kNumeric : kOnePass;
   if (p->merge_only) {
-    if (mode == kOnePass) HIPCK(p, launch_fill_u64(p->pa.status, 0, p->ntiles, s));
-    HIPCK(p, launch_wave_merge(operands_of(p, av, bv), mode, p->merge_m, p->merge_stage, ctr(p), p->pa.status, nullptr,
-                               c_row_ptr, c_col, c_val, c_capacity, s));
+    const Operands op = operands_of(p, av, bv);
+    if (mode == kOnePass) {
+      // counts, their scan into row_ptr and the numeric merge back to back
+      // on the device; the merge is staged by the capacities' largest wave
+      // sum, and a wave whose exact output exceeds it writes its rows directly
+      HIPCK(p, launch_wave_merge(op, kSymbolic, p->merge_m, 0, ctr(p), p->pa.cnt, p->pa.partials, nullptr, nullptr,
+                                 nullptr, 0, s));
+      HIPCK(p, launch_scan_i32(p->pa.cnt, c_row_ptr, p->A.rows, p->pa.scan_status, ctr(p) + kCtrScanTicket,
+                               ctr(p) + kCtrNnz, ctr(p) + kCtrError, s));
+    }
+    HIPCK(p, launch_wave_merge(op, kNumeric, p->merge_m, p->merge_stage, ctr(p), nullptr, nullptr, c_row_ptr, c_col,
+                               c_val, c_capacity, s));
     return SPGEMM_OK;
   }
   if (mode == kNumeric) {
@@ -591,7 +607,6 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   p->pa.pad_src = (int64_t *)(w + L.pad_src);
   p->pa.parts = (int64_t *)(w + L.parts);
   p->pa.f.brow = (int32_t *)(w + L.brow);
-  p->keys = (uint64_t *)(w + L.keys);
   hipStream_t s = (hipStream_t)stream;
 
   auto fail = [&](spgemm_status e) {
@@ -622,11 +637,18 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   // merges in registers when no row of A has more stored entries than the
   // merge tier's lists (and the tier is not switched off); then no per-row
   // plan arrays are needed.
-  if (launch_row_max(A->row_ptr, A->rows, p->pa.counters, p->pa.partials, s) != hipSuccess)
-    return fail(SPGEMM_E_HIP);
+  // The one-pass sizers get it with the sizes their merge path needs (the
+  // multiplication count, or the learned capacities, summed): the pass is
+  // wasted only for products that take the tiled path.
+  hipError_t he;
+  if (p->first_mode == kSymbolic) he = launch_row_max(op, p->pa.counters, p->pa.partials, s);
+  else if (learned) he = launch_mlp_capacity(dev, op, p->pa.counters, p->pa.partials, p->tune.margin, p->tune.slack, s);
+  else he = launch_features(op, p->pa.f, p->pa.counters, p->pa.partials, 0, s);
+  if (he != hipSuccess) return fail(SPGEMM_E_HIP);
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return fail(st);
+  if (h[kCtrError] & kErrDescriptor) return fail(SPGEMM_E_DIM);
   // The merge pays per output entry for every list: it takes rows with
   // few entries of A and short outputs (estimated from the mean row lengths
   // of A and B).
@@ -639,35 +661,34 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
     const int64_t ma = h[kCtrMaxA];
     p->merge_m = ma <= 4 ? 4 : ma <= 6 ? 6 : ma <= 8 ? 8 : ma <= 10 ? 10 : 16;
   }
-  // one pass: staging for 64 rows of up to 2 x 16 entries each (rows of at
-  // most 8 lists) or 2 x 32 (10 or 16 lists); the numeric pass sizes it from
-  // the exact counts
-  p->merge_stage = p->merge_m >= 10 ? 2048 : 1024;
   if (p->merge_only) {
-    // row sums (multiplications, empty rows) and, for the learned sizer, the
-    // packed feature triple of every row and the learned capacity
-    if (launch_features(op, p->pa.f, p->keys, p->pa.counters, p->pa.partials, learned ? 1 : 0, s) != hipSuccess)
-      return fail(SPGEMM_E_HIP);
-    if (learned) {
-      if (launch_mlp_capacity(dev, p->keys, A->rows, s, p->tune.margin, p->tune.slack, p->pa.partials) != hipSuccess)
-        return fail(SPGEMM_E_HIP);
-      const int32_t dst[1] = {kCtrCapSum};
-      if (launch_sum_partials(p->pa.partials, std::max<int64_t>(1, mlp_predict_blocks(A->rows)), 1, 1, dst, nullptr,
-                              p->pa.counters, s) != hipSuccess)
-        return fail(SPGEMM_E_HIP);
-    }
-    st = read_counters(p, s, &h);
-    if (st != SPGEMM_OK) return fail(st);
-    p->info.rows_empty = h[kCtrEmpty];
-    p->info.rows_merge = A->rows - h[kCtrEmpty];
     p->info.tiles = (A->rows + 63) / 64;
-    p->info.c_capacity_hint = learned ? h[kCtrCapSum] + h[kCtrUnpacked] : h[kCtrMults];
     p->ntiles = p->info.tiles;
     p->cur_mode = p->first_mode;
+    if (p->first_mode == kSymbolic) {
+      // the symbolic pass finds the multiplication counts and empty rows as
+      // it counts, and the staging of the numeric pass from the exact counts
+      p->info.multiplications = -1;
+      p->info.c_capacity_hint = -1;
+      p->scratch_slots_plan = 0;
+      p->info.scratch_bytes = 0;
+      if (info) *info = p->info;
+      *out = p;
+      return SPGEMM_OK;
+    }
+    // one pass: the capacities' sum (the size of C to allocate; the
+    // multiplication count, or the learned sizes) and their largest sum
+    // over a wave's 64 rows (the staging of the numeric merge), from the
+    // pass above
+    p->info.rows_empty = h[kCtrEmpty];
+    p->info.rows_merge = A->rows - h[kCtrEmpty];
+    p->info.c_capacity_hint = learned ? h[kCtrCapSum] + h[kCtrUnpacked] : h[kCtrMults];
+    p->merge_stage =
+        merge_stage_for(std::min<int64_t>(h[kCtrWaveCap], p->merge_m >= 10 ? kMergeStageMax : kMergeOnePassStage));
   } else {
     // per-row features (and their sums), the learned prediction, tiers
     if (launch_brow_ends(op, p->pa.f, s) != hipSuccess ||
-        launch_features(op, p->pa.f, p->keys, p->pa.counters, p->pa.partials, 2, s) != hipSuccess)
+        launch_features(op, p->pa.f, p->pa.counters, p->pa.partials, 2, s) != hipSuccess)
       return fail(SPGEMM_E_HIP);
     if (learned) {
       if (launch_mlp_predict(dev, p->pa.f.nnz_a, p->pa.f.ub, p->pa.f.maxb, A->rows, p->pa.pred, s, p->tune.margin,
@@ -721,8 +742,8 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
   timing_begin(p, s, &e);
   HIPCK(p, e);
   if (p->merge_only) {
-    HIPCK(p, launch_wave_merge(operands_of(p, nullptr, nullptr), kSymbolic, p->merge_m, 0, ctr(p),
-                               p->pa.status, p->pa.cnt, nullptr, nullptr, nullptr, 0, s));
+    HIPCK(p, launch_wave_merge(operands_of(p, nullptr, nullptr), kSymbolic, p->merge_m, 0, ctr(p), p->pa.cnt,
+                               p->pa.partials, nullptr, nullptr, nullptr, 0, s));
   } else {
     st = run_wave(p, kSymbolic, nullptr, nullptr, nullptr, nullptr, nullptr, 0, s);
     if (st == SPGEMM_OK)
@@ -731,8 +752,10 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
   }
   timing_end(p, s, &e);
   HIPCK(p, e);
+  // merge rows: the scan also finds the largest output of a wave's 64 rows
+  // (the staging of the numeric merge waves)
   HIPCK(p, launch_scan_i32(p->pa.cnt, c_row_ptr, p->A.rows, p->pa.scan_status, ctr(p) + kCtrScanTicket,
-                           ctr(p) + kCtrNnz, ctr(p) + kCtrError, s));
+                           ctr(p) + kCtrNnz, ctr(p) + kCtrError, s, p->merge_only ? ctr(p) + kCtrWaveSpan : nullptr));
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return st;
@@ -742,12 +765,10 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
   p->info.c_nnz = nnz;
   *c_nnz = nnz;
   if (p->merge_only) {
-    // staging of the numeric merge waves: the largest output of 64 rows
-    HIPCK(p, launch_wave_span(c_row_ptr, p->A.rows, ctr(p), p->pa.partials, s));
-    st = read_counters(p, s, &h);
-    if (st != SPGEMM_OK) return st;
-    const int64_t span = std::max<int64_t>(h[kCtrWaveSpan], 64);
-    p->merge_stage = (int)std::min<int64_t>((span + 63) & ~(int64_t)63, kMergeStageMax);
+    p->merge_stage = merge_stage_for(h[kCtrWaveSpan]);
+    p->info.multiplications = p->A.rows > 0 ? h[kCtrMults] : 0;
+    p->info.rows_empty = p->A.rows > 0 ? h[kCtrEmpty] : 0;
+    p->info.rows_merge = p->A.rows - p->info.rows_empty;
   }
   // size the numeric pass from the exact counts; with only a handful of
   // merge rows (a stencil's corners, say) sized again without the merge

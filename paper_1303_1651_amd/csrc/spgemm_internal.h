@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/spgemm.h"
+#include "spgemm_kernels.h"
 
 namespace spg {
 
@@ -33,11 +34,13 @@ hipError_t launch_mlp_predict(const float *dev_params, const int32_t *f1, const 
                               const int32_t *f3, int64_t n, float *pred, hipStream_t s, float margin = 0.f,
                               int slack = 0, int64_t *partials = nullptr);
 int64_t mlp_predict_blocks(int64_t n);
-// Learned capacity summed per workgroup (partials[b]) from the packed
-// feature triples of the rows (rows whose triple did not fit count 0 and
-// are covered by the caller).
-hipError_t launch_mlp_capacity(const float *dev_params, const uint64_t *rowkeys, int64_t n, hipStream_t s,
-                               float margin, int slack, int64_t *partials);
+// Learned capacity of every row of A * B, its features computed from the
+// operands: sums into counters[kCtrCapSum] (rows whose triple does not pack
+// count 0; their summed bounds go to kCtrUnpacked), the largest sum over 64
+// consecutive rows into kCtrWaveCap, and the multiplication count, longest
+// row of A and empty rows into kCtrMults, kCtrMaxA and kCtrEmpty.
+hipError_t launch_mlp_capacity(const float *dev_params, const Operands &op, int64_t *counters, int64_t *partials,
+                               float margin, int slack, hipStream_t s);
 
 // Capacity of a row sized by the learned prediction: ceil(pred * (1 +
 // margin)) + slack, clamped to [longest selected B row, multiplication

@@ -55,6 +55,7 @@ enum Counter : int {
   kCtrBigTail = 23,    // the other workgroup-tier rows (listed from the end of the list)
   kCtrBigTicket = 24,  // next list entry a k_big workgroup takes
   kCtrEsc = 25,        // numeric or one-pass sizing: hashed rows taken by expand-sort-combine
+  kCtrWaveCap = 26,    // largest sum of capacities over 64 consecutive rows (merge one pass)
   kNumCounters = 32
 };
 enum : int64_t {
@@ -189,21 +190,80 @@ struct BigParams {
                             // by the launcher
 };
 
+// Per row i of A: entries of the row (m), multiplication count (ub: the
+// paper's estimate of Section IV-B taken per row), the longest selected B
+// row (mx) and, with SPAN, the smallest/largest column any selected B row
+// touches (lo, hi; from the per-row records of B in brow).
+// The stored entries are taken eight at a time, each group's loads issued
+// at once (three dependent gather rounds).
+template <bool SPAN>
+__device__ __forceinline__ void row_features(const Operands &op, int64_t i, int64_t &m, int64_t &ub, int32_t &mx,
+                                             int32_t &lo, int32_t &hi, const int32_t *brow = nullptr) {
+  const int64_t s = op.a_rp[i], e = op.a_rp[i + 1];
+  m = e - s;
+  ub = 0;
+  mx = 0;
+  lo = 0x7fffffff;
+  hi = -1;
+  // eight entries at a time: their gathers are in flight together
+  for (int64_t q0 = s; q0 < e; q0 += 8) {
+    const int cnt = (int)min((int64_t)8, e - q0);
+    int32_t k[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) k[q] = q < cnt ? op.a_col[q0 + q] : 0;
+    if (SPAN) {
+      // one aligned 16-byte record per selected B row: length and span
+      int4 r[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        r[q] = q < cnt ? reinterpret_cast<const int4 *>(brow)[k[q]] : make_int4(0, 0x7fffffff, -1, 0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        ub += r[q].x;
+        mx = max(mx, r[q].x);
+        lo = min(lo, r[q].y);
+        hi = max(hi, r[q].z);
+      }
+    } else {
+      int64_t bs[8], be[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        bs[q] = q < cnt ? op.b_rp[k[q]] : 0;
+        be[q] = q < cnt ? op.b_rp[k[q] + 1] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int32_t len = (int32_t)(be[q] - bs[q]);
+        ub += len;
+        mx = max(mx, len);
+      }
+    }
+  }
+}
+
 // ---- launchers (spgemm_kernels.hip) ----
 hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_validate(const int64_t *rp, const int32_t *col, int64_t rows, int64_t cols,
                            int64_t nnz, int64_t *counters, hipStream_t s);
-// mode 0: sums only; 1: plus a packed feature triple per row (keys); 2: plus
-// the per-row plan arrays in f.
-hipError_t launch_features(const Operands &op, const Features &f, uint64_t *keys, int64_t *counters,
-                           int64_t *partials, int mode, hipStream_t s);
-hipError_t launch_row_max(const int64_t *rp, int64_t rows, int64_t *counters, int64_t *partials, hipStream_t s);
+// Sums into counters: kCtrMults, kCtrMaxA, kCtrEmpty, kCtrWaveCap (the
+// largest multiplication count summed over 64 consecutive rows).  mode 2
+// also writes the per-row plan arrays in f.
+hipError_t launch_features(const Operands &op, const Features &f, int64_t *counters, int64_t *partials, int mode,
+                           hipStream_t s);
+// Longest row of A into counters[kCtrMaxA]; raises kErrDescriptor when a
+// descriptor's nnz differs from its row_ptr[rows].
+hipError_t launch_row_max(const Operands &op, int64_t *counters, int64_t *partials, hipStream_t s);
+// Zeroes counters[i] for every bit i of mask.
+hipError_t launch_clear_counters(int64_t *counters, uint32_t mask, hipStream_t s);
 hipError_t launch_size_rows(const Operands &op, const PlanArrays &pa, const SizeParams &sp,
                             hipStream_t s);
 // exclusive scan of rows int32 (or int64 when in64) values into out[0..n], out[n] = total
+// group_max (may be null): receives the largest sum of 64 consecutive items
+// starting at a multiple of 64.
 hipError_t launch_scan_i32(const int32_t *in, int64_t *out, int64_t n, uint64_t *status,
-                           int64_t *ticket, int64_t *total_dst, int64_t *err, hipStream_t s);
+                           int64_t *ticket, int64_t *total_dst, int64_t *err, hipStream_t s,
+                           int64_t *group_max = nullptr);
 hipError_t launch_scan_i64_inplace(int64_t *inout, int64_t n, uint64_t *status, int64_t *ticket,
                                    int64_t *err, hipStream_t s);
 hipError_t launch_tile_bounds(const int64_t *cost, int64_t rows, int64_t half_pool,
@@ -218,11 +278,12 @@ hipError_t launch_big_rows(const BigParams &bp, int mode, int grid, hipStream_t 
 hipError_t launch_sum_partials(const int64_t *partials, int64_t nblocks, int n, int stride, const int32_t *dst,
                                const int32_t *is_max, int64_t *counters, hipStream_t s);
 // Row-per-thread merge kernels for matrices whose rows all take the merge
-// tier (merge_lists 4, 8 or 16); `stage` entries of LDS staging per wave.
+// tier (merge_lists 4, 6, 8, 10 or 16).  kSymbolic: counts into cnt_out,
+// multiplication count and empty rows into counters (through partials).
+// kNumeric: C from the exact row_ptr c_rp, `stage` entries of LDS staging
+// per wave.
 hipError_t launch_wave_merge(const Operands &op, int mode, int merge_lists, int stage, int64_t *counters,
-                             uint64_t *status, int32_t *cnt_out, int64_t *c_rp, int32_t *c_col, double *c_val,
-                             int64_t c_capacity, hipStream_t s);
-// counters[kCtrWaveSpan] = max over groups of 64 rows of rp[end] - rp[start]
-hipError_t launch_wave_span(const int64_t *rp, int64_t rows, int64_t *counters, int64_t *partials, hipStream_t s);
+                             int32_t *cnt_out, int64_t *partials, const int64_t *c_rp, int32_t *c_col,
+                             double *c_val, int64_t c_capacity, hipStream_t s);
 
 }  // namespace spg

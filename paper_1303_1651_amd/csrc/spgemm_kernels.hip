@@ -28,6 +28,18 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
     p[i] = v;
 }
 
+// Zeroes the counters whose bits are set in `mask` (one launch for the
+// per-run counters instead of one fill each).
+__global__ void k_clear_ctrs(int64_t *c, uint32_t mask) {
+  const int t = threadIdx.x;
+  if (t < 32 && ((mask >> t) & 1u)) c[t] = 0;
+}
+
+hipError_t launch_clear_counters(int64_t *counters, uint32_t mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_ctrs, dim3(1), dim3(kWave), 0, s, counters, mask);
+  return hipGetLastError();
+}
+
 static int grid_for(int64_t n, int cap = 65536) {
   int64_t g = (n + kBlock - 1) / kBlock;
   if (g < 1) g = 1;
@@ -114,81 +126,21 @@ __device__ __forceinline__ void b_row_part(const Operands &op, int64_t e, int32_
   bl = (int32_t)(s[1] - s[0]);
 }
 
-// Features of row i (see above); the stored entries are taken eight at a
-// time, each group's loads issued at once (three dependent gather rounds).
-template <bool SPAN>
-__device__ __forceinline__ void row_features(const Operands &op, int64_t i, int64_t &m, int64_t &ub, int32_t &mx,
-                                             int32_t &lo, int32_t &hi, const int32_t *brow = nullptr) {
-  const int64_t s = op.a_rp[i], e = op.a_rp[i + 1];
-  m = e - s;
-  ub = 0;
-  mx = 0;
-  lo = 0x7fffffff;
-  hi = -1;
-  // eight entries at a time: their gathers are in flight together
-  for (int64_t q0 = s; q0 < e; q0 += 8) {
-    const int cnt = (int)min((int64_t)8, e - q0);
-    int32_t k[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) k[q] = q < cnt ? op.a_col[q0 + q] : 0;
-    if (SPAN) {
-      // one aligned 16-byte record per selected B row: length and span
-      int4 r[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        r[q] = q < cnt ? reinterpret_cast<const int4 *>(brow)[k[q]] : make_int4(0, 0x7fffffff, -1, 0);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        ub += r[q].x;
-        mx = max(mx, r[q].x);
-        lo = min(lo, r[q].y);
-        hi = max(hi, r[q].z);
-      }
-    } else {
-      int64_t bs[8], be[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        bs[q] = q < cnt ? op.b_rp[k[q]] : 0;
-        be[q] = q < cnt ? op.b_rp[k[q] + 1] : 0;
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int32_t len = (int32_t)(be[q] - bs[q]);
-        ub += len;
-        mx = max(mx, len);
-      }
-    }
-  }
-}
-
-// Packed feature triple of a row (the learned sizer's input): entries of the
-// A row (21 bits), multiplication count saturated at B.cols (22 bits),
-// longest selected B row (20 bits); all ones when a field does not fit.
-__device__ __forceinline__ uint64_t pack_triple(int64_t m, int64_t ub, int32_t mx, int32_t b_cols) {
-  const int64_t u = min(ub, (int64_t)b_cols);
-  if (m >= (1 << 21) || u >= (1 << 22) || mx >= (1 << 20)) return ~0ull;
-  return (uint64_t)m | ((uint64_t)u << 21) | ((uint64_t)mx << 43);
-}
-
-// MODE 0: partial sums only.  MODE 1: also the packed triple of every row.
-// MODE 2: also the per-row plan arrays (entries, saturated count, longest
-// B row, column span) for tiled passes.
+// Partials per workgroup: multiplication count, longest row of A, empty
+// rows, largest multiplication count summed over 64 consecutive rows.
+// MODE 0: partial sums only.  MODE 2: also the per-row plan arrays
+// (entries, saturated count, longest B row, column span) for tiled passes.
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_features(Operands op, Features f, uint64_t *keys, int64_t *partials,
-                                                     int64_t *err) {
+__global__ void __launch_bounds__(kBlock) k_features(Operands op, Features f, int64_t *partials, int64_t *err) {
   __shared__ int64_t s_sum[4][kWavesPerBlock];
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   // arrays sized by the descriptors' nnz rely on it
   if (i == 0 && (op.a_rp[op.rows] != op.a_nnz || op.b_rp[op.b_rows] != op.b_nnz))
     atomicOr((unsigned long long *)err, (unsigned long long)kErrDescriptor);
-  int64_t ub = 0, m = 0, empty = 0, unpacked = 0;
+  int64_t ub = 0, m = 0, empty = 0;
   if (i < op.rows) {
     int32_t mx, lo, hi;
     row_features<MODE == 2>(op, i, m, ub, mx, lo, hi, f.brow);
-    if (MODE == 1) {
-      keys[i] = pack_triple(m, ub, mx, op.b_cols);
-      if (keys[i] == ~0ull) unpacked = min(ub, (int64_t)op.b_cols);
-    }
     if (MODE == 2) {
       f.nnz_a[i] = (int32_t)m;
       f.ub[i] = (int32_t)min(ub, (int64_t)op.b_cols);
@@ -198,28 +150,22 @@ __global__ void __launch_bounds__(kBlock) k_features(Operands op, Features f, ui
     }
     empty = ub == 0 ? 1 : 0;
   }
-  int64_t ws = wave_sum(ub), we = wave_sum(empty), wu = wave_sum(unpacked), wm = m;
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) wm = max(wm, __shfl_xor(wm, d, kWave));
+  // each wave's 64 rows are a merge wave's rows: its summed counts is the
+  // staging the bound sizer gives that wave
+  const int64_t ws = wave_sum(ub), we = wave_sum(empty), wm = wave_max64(m);
   if (lane_id() == 0) {
     s_sum[0][threadIdx.x / kWave] = ws;
     s_sum[1][threadIdx.x / kWave] = wm;
     s_sum[2][threadIdx.x / kWave] = we;
-    s_sum[3][threadIdx.x / kWave] = wu;
+    s_sum[3][threadIdx.x / kWave] = ws;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t t = 0, tm = 0, te = 0, tu = 0;
-    for (int j = 0; j < kWavesPerBlock; ++j) {
-      t += s_sum[0][j];
-      tm = max(tm, s_sum[1][j]);
-      te += s_sum[2][j];
-      tu += s_sum[3][j];
-    }
-    partials[blockIdx.x * 4 + 0] = t;
-    partials[blockIdx.x * 4 + 1] = tm;
-    partials[blockIdx.x * 4 + 2] = te;
-    partials[blockIdx.x * 4 + 3] = tu;
+  if (threadIdx.x < 4) {
+    const int q = threadIdx.x;
+    const bool is_max = q == 1 || q == 3;
+    int64_t t = 0;
+    for (int j = 0; j < kWavesPerBlock; ++j) t = is_max ? max(t, s_sum[q][j]) : t + s_sum[q][j];
+    partials[blockIdx.x * 4 + q] = t;
   }
 }
 
@@ -241,8 +187,13 @@ hipError_t launch_brow_ends(const Operands &op, Features f, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Longest row of A (row pointers only).
-__global__ void __launch_bounds__(kBlock) k_row_max(const int64_t *rp, int64_t rows, int64_t *partials) {
+// Longest row of A (row pointers only); also checks that the descriptors'
+// entry counts equal row_ptr[rows] (arrays sized by nnz rely on it).
+__global__ void __launch_bounds__(kBlock) k_row_max(Operands op, int64_t *partials, int64_t *err) {
+  const int64_t *rp = op.a_rp;
+  const int64_t rows = op.rows;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (op.a_rp[op.rows] != op.a_nnz || op.b_rp[op.b_rows] != op.b_nnz))
+    atomicOr((unsigned long long *)err, (unsigned long long)kErrDescriptor);
   int64_t m = 0;
   for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < rows; i += (int64_t)gridDim.x * kBlock)
     m = max(m, rp[i + 1] - rp[i]);
@@ -269,24 +220,29 @@ struct PartialSpec {
   int32_t is_max[kMaxPartials];
 };
 
-__global__ void __launch_bounds__(kBlock) k_sum_partials(const int64_t *partials, int64_t nblocks, PartialSpec ps,
-                                                         int64_t *counters) {
-  __shared__ int64_t red[kMaxPartials][kWavesPerBlock];
-  // every block's record read once for all the sums, four records in flight
+constexpr int kSumThreads = 1024;
+constexpr int kSumWaves = kSumThreads / kWave;
+__global__ void __launch_bounds__(kSumThreads) k_sum_partials(const int64_t *partials, int64_t nblocks, PartialSpec ps,
+                                                              int64_t *counters) {
+  __shared__ int64_t red[kMaxPartials][kSumWaves];
+  // strides follow the launch's width (at most kSumThreads threads); each
+  // sum's records eight at a time, their loads issued together
+  const int64_t nt = blockDim.x;
   int64_t acc[kMaxPartials];
 #pragma unroll
   for (int j = 0; j < kMaxPartials; ++j) acc[j] = 0;
-  for (int64_t b0 = threadIdx.x; b0 < nblocks; b0 += 4 * kBlock) {
+  for (int64_t b0 = threadIdx.x; b0 < nblocks; b0 += 8 * nt) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t b = b0 + (int64_t)u * kBlock;
-      if (b >= nblocks) break;
+    for (int j = 0; j < kMaxPartials; ++j) {
+      if (j >= ps.n) break;
+      int64_t v[8];
 #pragma unroll
-      for (int j = 0; j < kMaxPartials; ++j) {
-        if (j >= ps.n) break;
-        const int64_t v = partials[b * ps.stride + j];
-        acc[j] = ps.is_max[j] ? max(acc[j], v) : acc[j] + v;
+      for (int u = 0; u < 8; ++u) {
+        const int64_t b = b0 + (int64_t)u * nt;
+        v[u] = b < nblocks ? partials[b * ps.stride + j] : 0;
       }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[j] = ps.is_max[j] ? max(acc[j], v[u]) : acc[j] + v[u];
     }
   }
 #pragma unroll
@@ -304,11 +260,43 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(const int64_t *partials
   if (threadIdx.x < ps.n) {
     int j = threadIdx.x;
     int64_t acc = 0;
-    for (int q = 0; q < kWavesPerBlock; ++q) acc = ps.is_max[j] ? max(acc, red[j][q]) : acc + red[j][q];
+    for (int q = 0; q < (int)(nt / kWave); ++q) acc = ps.is_max[j] ? max(acc, red[j][q]) : acc + red[j][q];
     counters[ps.dst[j]] = acc;
   }
 }
 
+// Many partials are first folded kFold to one by as many workgroups (one
+// record per thread), into the space after them, so that the final
+// single-workgroup sum reads a few hundred records.
+constexpr int64_t kFold = kBlock;
+constexpr int64_t kFoldAbove = 4096;
+
+__global__ void __launch_bounds__(kBlock) k_fold_partials(const int64_t *partials, int64_t nblocks, PartialSpec ps,
+                                                          int64_t *out) {
+  __shared__ int64_t red[kMaxPartials][kWavesPerBlock];
+  const int64_t b = (int64_t)blockIdx.x * kFold + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < kMaxPartials; ++j) {
+    if (j >= ps.n) break;
+    int64_t a = b < nblocks ? partials[b * ps.stride + j] : 0;
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+      const int64_t o = __shfl_xor(a, d, kWave);
+      a = ps.is_max[j] ? max(a, o) : a + o;
+    }
+    if (lane_id() == 0) red[j][threadIdx.x / kWave] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < ps.n) {
+    const int j = threadIdx.x;
+    int64_t acc = 0;
+    for (int q = 0; q < kWavesPerBlock; ++q) acc = ps.is_max[j] ? max(acc, red[j][q]) : acc + red[j][q];
+    out[(int64_t)blockIdx.x * ps.stride + j] = acc;
+  }
+}
+
+// partials: every producer's array has room for the folded records after
+// its own (at most 9 words per workgroup in an array of 10 per workgroup).
 hipError_t launch_sum_partials(const int64_t *partials, int64_t nblocks, int n, int stride, const int32_t *dst,
                                const int32_t *is_max, int64_t *counters, hipStream_t s) {
   PartialSpec ps{};
@@ -318,29 +306,40 @@ hipError_t launch_sum_partials(const int64_t *partials, int64_t nblocks, int n, 
     ps.dst[j] = dst[j];
     ps.is_max[j] = is_max ? is_max[j] : 0;
   }
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, partials, nblocks, ps, counters);
+  if (nblocks > kFoldAbove) {
+    int64_t *folded = const_cast<int64_t *>(partials) + nblocks * stride;
+    const int64_t g = (nblocks + kFold - 1) / kFold;
+    hipLaunchKernelGGL(k_fold_partials, dim3((unsigned)g), dim3(kBlock), 0, s, partials, nblocks, ps, folded);
+    partials = folded;
+    nblocks = g;
+  }
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSumThreads), 0, s, partials, nblocks, ps, counters);
   return hipGetLastError();
 }
 
-hipError_t launch_features(const Operands &op, const Features &f, uint64_t *keys, int64_t *counters,
-                           int64_t *partials, int mode, hipStream_t s) {
-  if (op.rows <= 0) return launch_fill_i64(counters + kCtrMults, 0, 1, s);
+hipError_t launch_features(const Operands &op, const Features &f, int64_t *counters, int64_t *partials, int mode,
+                           hipStream_t s) {
+  const int32_t dst[4] = {kCtrMults, kCtrMaxA, kCtrEmpty, kCtrWaveCap};
+  const int32_t mx[4] = {0, 1, 0, 1};
+  if (op.rows <= 0) {
+    for (int q = 0; q < 4; ++q) {
+      hipError_t e = launch_fill_i64(counters + dst[q], 0, 1, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   const int64_t blocks = (op.rows + kBlock - 1) / kBlock;
   int64_t *err = counters + kCtrError;
-  if (mode == 2)
-    hipLaunchKernelGGL(k_features<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, keys, partials, err);
-  else if (mode == 1)
-    hipLaunchKernelGGL(k_features<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, keys, partials, err);
-  else hipLaunchKernelGGL(k_features<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, keys, partials, err);
-  const int32_t dst[4] = {kCtrMults, kCtrMaxA, kCtrEmpty, kCtrUnpacked};
-  const int32_t mx[4] = {0, 1, 0, 0};
+  if (mode == 2) hipLaunchKernelGGL(k_features<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, partials, err);
+  else hipLaunchKernelGGL(k_features<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, partials, err);
   return launch_sum_partials(partials, blocks, 4, 4, dst, mx, counters, s);
 }
 
-hipError_t launch_row_max(const int64_t *rp, int64_t rows, int64_t *counters, int64_t *partials, hipStream_t s) {
+hipError_t launch_row_max(const Operands &op, int64_t *counters, int64_t *partials, hipStream_t s) {
+  const int64_t rows = op.rows;
   if (rows <= 0) return launch_fill_i64(counters + kCtrMaxA, 0, 1, s);
   const int64_t blocks = std::min<int64_t>(1024, (rows + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_row_max, dim3((unsigned)blocks), dim3(kBlock), 0, s, rp, rows, partials);
+  hipLaunchKernelGGL(k_row_max, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, partials, counters + kCtrError);
   const int32_t dst[1] = {kCtrMaxA};
   const int32_t mx[1] = {1};
   return launch_sum_partials(partials, blocks, 1, 1, dst, mx, counters, s);
@@ -573,15 +572,17 @@ hipError_t launch_size_rows(const Operands &op, const PlanArrays &pa, const Size
   if (op.rows <= 0) {
     e = launch_fill_i64(pa.partials, 0, kSizeParts, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, (const int64_t *)pa.partials, (int64_t)1, ps,
-                       pa.counters);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSumThreads), 0, s, (const int64_t *)pa.partials, (int64_t)1,
+                       ps, pa.counters);
     return hipGetLastError();
   }
   const int64_t blocks = (op.rows + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_size_rows, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, pa, sp);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, (const int64_t *)pa.partials, blocks, ps,
-                     pa.counters);
-  return hipGetLastError();
+  hipError_t e2 = hipGetLastError();
+  if (e2 != hipSuccess) return e2;
+  int32_t mx[kSizeParts];
+  for (int j = 0; j < kSizeParts; ++j) mx[j] = ps.is_max[j];
+  return launch_sum_partials(pa.partials, blocks, kSizeParts, kSizeParts, ps.dst, mx, pa.counters, s);
 }
 
 
@@ -593,10 +594,12 @@ hipError_t launch_size_rows(const Operands &op, const PlanArrays &pa, const Size
 constexpr int kScanItems = 32;
 constexpr int kScanTile = kBlock * kScanItems;
 
+// group_max (may be null): the largest sum of 64 consecutive items starting
+// at a multiple of 64 (a merge wave's output) is raised into it.
 template <typename TIn>
 __global__ void __launch_bounds__(kBlock) k_scan(const TIn *in, int64_t *out, int64_t n,
                                                   uint64_t *status, int64_t *ticket,
-                                                  int64_t *total_dst, int64_t *err) {
+                                                  int64_t *total_dst, int64_t *err, int64_t *group_max) {
   __shared__ int64_t buf[kScanTile];
   __shared__ int64_t s_tile, s_excl;
   __shared__ int64_t s_wtot[kWavesPerBlock + 1];
@@ -613,8 +616,22 @@ __global__ void __launch_bounds__(kBlock) k_scan(const TIn *in, int64_t *out, in
   int64_t sum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) sum += buf[threadIdx.x * kScanItems + k];
+  __shared__ int64_t s_gmax[kWavesPerBlock];
+  if (group_max) {
+    // threads 2g and 2g+1 hold the 64 items of group g of the tile
+    static_assert(kScanItems * 2 == kWave, "a group of 64 items spans two threads");
+    int64_t g = sum + __shfl_xor(sum, 1, kWave);
+#pragma unroll
+    for (int d = kWave / 2; d > 1; d >>= 1) g = max(g, __shfl_xor(g, d, kWave));
+    if (lane_id() == 0) s_gmax[threadIdx.x / kWave] = g;
+  }
   int64_t agg;
-  int64_t excl = block_exclusive_sum(sum, s_wtot, &agg);
+  int64_t excl = block_exclusive_sum(sum, s_wtot, &agg);   // its barriers also order s_gmax
+  if (group_max && threadIdx.x == 0) {
+    int64_t m = 0;
+    for (int w = 0; w < kWavesPerBlock; ++w) m = max(m, s_gmax[w]);
+    atomicMax((unsigned long long *)group_max, (unsigned long long)m);
+  }
   if (threadIdx.x < kWave) {
     int64_t pre = lookback_exclusive(status, t, agg, err, kErrLookback);
     if (threadIdx.x == 0) s_excl = pre;
@@ -641,16 +658,30 @@ __global__ void __launch_bounds__(kBlock) k_scan(const TIn *in, int64_t *out, in
   }
 }
 
+// Clears the look-back status words and the ticket in one launch.
+__global__ void k_scan_reset(uint64_t *status, int64_t tiles, int64_t *ticket, int64_t *group_max) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < tiles; i += (int64_t)gridDim.x * kBlock)
+    status[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *ticket = 0;
+    if (group_max) *group_max = 0;
+  }
+}
+
 hipError_t launch_scan_i32(const int32_t *in, int64_t *out, int64_t n, uint64_t *status,
-                           int64_t *ticket, int64_t *total_dst, int64_t *err, hipStream_t s) {
-  if (n <= 0) return launch_fill_i64(out, 0, 1, s);
+                           int64_t *ticket, int64_t *total_dst, int64_t *err, hipStream_t s,
+                           int64_t *group_max) {
+  if (n <= 0) {
+    if (group_max) {
+      hipError_t e = launch_fill_i64(group_max, 0, 1, s);
+      if (e != hipSuccess) return e;
+    }
+    return launch_fill_i64(out, 0, 1, s);
+  }
   int64_t tiles = (n + kScanTile - 1) / kScanTile;
-  hipError_t e = launch_fill_u64(status, 0, tiles, s);
-  if (e != hipSuccess) return e;
-  e = launch_fill_i64(ticket, 0, 1, s);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_reset, dim3(grid_for(tiles, 1024)), dim3(kBlock), 0, s, status, tiles, ticket, group_max);
   hipLaunchKernelGGL(k_scan<int32_t>, dim3((unsigned)tiles), dim3(kBlock), 0, s, in, out, n, status,
-                     ticket, total_dst, err);
+                     ticket, total_dst, err, group_max);
   return hipGetLastError();
 }
 
@@ -663,7 +694,7 @@ hipError_t launch_scan_i64_inplace(int64_t *inout, int64_t n, uint64_t *status, 
   e = launch_fill_i64(ticket, 0, 1, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_scan<int64_t>, dim3((unsigned)tiles), dim3(kBlock), 0, s, inout, inout, n,
-                     status, ticket, (int64_t *)nullptr, err);
+                     status, ticket, (int64_t *)nullptr, err, (int64_t *)nullptr);
   return hipGetLastError();
 }
 
@@ -726,7 +757,7 @@ __device__ __forceinline__ RowHash make_hash(int32_t lo, int32_t hi, int64_t slo
 // the row-major kernel.  Writes min(count, lim) entries; returns the count.
 template <int M, bool VALUES, bool DBUF = true>
 __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, double *out_val,
-                             int64_t lim) {
+                             int64_t lim, int64_t *ub_out = nullptr) {
   const int64_t as = op.a_rp[row];
   const int m = (int)(op.a_rp[row + 1] - as);
   // per list: head (h, v), with DBUF the entry after it (h2, v2), the next
@@ -746,6 +777,12 @@ __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, 
       if (VALUES) a[l] = op.a_val[as + l];
       b_row_of(op, as + l, pos[l], rem[l]);
     }
+  }
+  if (ub_out) {
+    int64_t ub = 0;
+#pragma unroll
+    for (int l = 0; l < M; ++l) ub += rem[l];
+    *ub_out = ub;
   }
 #pragma unroll
   for (int l = 0; l < M; ++l) {
@@ -2310,206 +2347,132 @@ __global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
 // ===================================================== register-merge rows
 // Matrices whose every row is a register-merge row need no tiles and no
 // workgroup barriers: one thread per row, 64 consecutive rows per wave.
-//   symbolic: merge without values, write the count;
+//   symbolic: merge without values, write the count; per-workgroup partial
+//             sums of the multiplication counts and empty rows;
 //   numeric:  merge with values into the wave's LDS staging at the row's
-//             offset inside the wave's output, then copy the wave's
-//             contiguous output to C with all 64 lanes (coalesced stores;
-//             one store per lane per row would scatter over 64 cache lines);
-//   one pass: merge without values, scan the counts across the wave and
-//             publish the wave's total (the wave is the look-back tile);
-//             merge with values into the staging while predecessors
-//             publish; then resolve the wave's offset and copy out.
-// One-pass tickets are taken per workgroup; its waves are tiles 4t .. 4t+3.
-// Staging of a merge wave: `stage` entries per wave, columns of the
-// block's four waves first, then their values (16-byte aligned).
+//             offset inside the wave's output (known from row_ptr), then
+//             copy the wave's contiguous output to C with all 64 lanes
+//             (coalesced stores; one store per lane per row would scatter
+//             over many cache lines; staging decides how many waves a
+//             compute unit holds, so it is sized by the largest wave output).
+// The one pass of such matrices runs the two, with the scan between them,
+// back to back on the device (no host round trip): a single merge that
+// publishes its count only once its values are staged holds every later
+// wave in the look-back, and one that counts first merges twice.
 __host__ __device__ inline size_t wave_merge_vals_offset(int stage) {
   return (((size_t)kWavesPerBlock * stage * 4) + 15) & ~(size_t)15;
 }
-__host__ __device__ inline size_t wave_merge_lds(int stage) {
+__host__ __device__ inline size_t wave_merge_lds(int mode, int stage) {
+  if (mode == kSymbolic) return 0;
   return wave_merge_vals_offset(stage) + (size_t)kWavesPerBlock * stage * 8;
 }
 
-__device__ __forceinline__ void status_publish(uint64_t *status, int64_t tile, int64_t agg) {
-  if (lane_id() == 0) status_store(status + tile, (tile == 0 ? kFlagPre : kFlagAgg) | (uint64_t)agg);
-}
-
-// Exclusive prefix of a tile whose aggregate is already published: walk
-// back 64 predecessors at a time to the nearest inclusive prefix, then
-// publish this tile's inclusive prefix.  All 64 lanes of one wave.
-__device__ inline int64_t lookback_resolve(uint64_t *status, int64_t tile, int64_t aggregate, int64_t *err,
-                                           int64_t err_bit) {
-  const int l = lane_id();
-  if (tile == 0) return 0;
-  int64_t excl = 0, j = tile - 1, polls = 0;
-  while (true) {
-    const int64_t idx = j - l;
-    const uint64_t s = idx >= 0 ? status_load(status + idx) : (kFlagPre | 0ull);
-    const uint64_t flag = s & ~kValMask;
-    const uint64_t have_pre = ballot(flag == kFlagPre);
-    const uint64_t invalid = ballot(flag == 0);
-    const uint64_t upto = have_pre ? ((have_pre & (~have_pre + 1)) << 1) - 1ull : ~0ull;
-    if (invalid & upto) {
-      if (++polls > kSpinLimit) {
-        if (l == 0 && err) atomicOr((unsigned long long *)err, (unsigned long long)err_bit);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(2);
-      continue;
-    }
-    excl += wave_sum((upto >> l) & 1ull ? (int64_t)(s & kValMask) : 0);
-    if (have_pre) break;
-    j -= kWave;
-  }
-  if (l == 0) status_store(status + tile, kFlagPre | (uint64_t)(excl + aggregate));
-  return excl;
-}
-
 template <int M, int MODE>
-__global__ void __launch_bounds__(kBlock, M == 10 ? 3 : (M <= 8 ? 4 : 1)) k_wave_merge(Operands op, int64_t *counters, uint64_t *status,
-                                                       int32_t *cnt_out, int64_t *c_rp, int32_t *c_col,
-                                                       double *c_val, int64_t c_capacity, int stage) {
+__global__ void __launch_bounds__(kBlock, M == 10 ? 3 : (M <= 8 ? 4 : 1))
+k_wave_merge(Operands op, int64_t *counters, int32_t *cnt_out, int64_t *partials, const int64_t *c_rp,
+             int32_t *c_col, double *c_val, int64_t c_capacity, int stage) {
   extern __shared__ __align__(16) unsigned char wm_lds[];
-  __shared__ int64_t s_ticket;
   const int l = lane_id();
   const int w = threadIdx.x / kWave;
-  // this wave's staging: stage columns, then stage values
-  int32_t *scw = reinterpret_cast<int32_t *>(wm_lds) + (size_t)w * stage;
-  double *svw = reinterpret_cast<double *>(wm_lds + wave_merge_vals_offset(stage)) + (size_t)w * stage;
-  int64_t wt;
-  if (MODE == kOnePass) {
-    if (threadIdx.x == 0)
-      s_ticket = (int64_t)__hip_atomic_fetch_add((unsigned long long *)&counters[kCtrTicket], 1ull,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    wt = s_ticket * kWavesPerBlock + w;
-  } else {
-    wt = (int64_t)blockIdx.x * kWavesPerBlock + w;
-  }
-  const int64_t row0 = wt * kWave;
-  if (row0 >= op.rows) return;   // whole wave: its tile is past the end
-  const int64_t row = row0 + l;
-  const bool valid = row < op.rows;
   if (MODE == kSymbolic) {
-    if (valid) cnt_out[row] = (int32_t)merge_row<M, false>(op, row, nullptr, nullptr, 0);
+    // counts, and the workgroup's sums of multiplication counts and empty rows
+    __shared__ int64_t s_part[2][kWavesPerBlock];
+    const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t n = 0, ub = 0;
+    if (row < op.rows) {
+      n = merge_row<M, false>(op, row, nullptr, nullptr, 0, &ub);
+      cnt_out[row] = (int32_t)n;
+    }
+    const int64_t wu = wave_sum(ub), we = wave_sum(row < op.rows && ub == 0 ? 1 : 0);
+    if (l == 0) {
+      s_part[0][w] = wu;
+      s_part[1][w] = we;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t a = 0, b = 0;
+      for (int q = 0; q < kWavesPerBlock; ++q) {
+        a += s_part[0][q];
+        b += s_part[1][q];
+      }
+      partials[2 * blockIdx.x] = a;
+      partials[2 * blockIdx.x + 1] = b;
+    }
     return;
   }
-  int64_t base, o, n, tot;
-  if (MODE == kNumeric) {
-    base = c_rp[row0];
-    const int64_t end = c_rp[min(row0 + kWave, op.rows)];
-    tot = end - base;
-    o = valid ? c_rp[row] - base : 0;
-    n = valid ? c_rp[row + 1] - c_rp[row] : 0;
-  } else {
-    n = valid ? merge_row<M, false>(op, row, nullptr, nullptr, 0) : 0;
-    const int64_t inc = wave_inclusive_sum(n);
-    tot = __shfl(inc, kWave - 1, kWave);
-    o = inc - n;
-    status_publish(status, wt, tot);
-  }
+  // numeric: this wave's staging, `stage` columns, then `stage` values
+  int32_t *scw = reinterpret_cast<int32_t *>(wm_lds) + (size_t)w * stage;
+  double *svw = reinterpret_cast<double *>(wm_lds + wave_merge_vals_offset(stage)) + (size_t)w * stage;
+  const int64_t row0 = ((int64_t)blockIdx.x * kWavesPerBlock + w) * kWave;
+  if (row0 >= op.rows) return;   // whole wave past the end
+  const int64_t row = row0 + l;
+  const bool valid = row < op.rows;
+  const int64_t base = c_rp[row0];
+  const int64_t tot = c_rp[min(row0 + kWave, op.rows)] - base;
+  const int64_t o = valid ? c_rp[row] - base : 0;
+  const int64_t n = valid ? c_rp[row + 1] - c_rp[row] : 0;
   const bool staged = tot <= stage;
   if (staged && valid) {
     const int64_t got = merge_row<M, true>(op, row, scw + o, svw + o, n);
-    if (MODE == kNumeric && got != n)
-      atomicOr((unsigned long long *)&counters[kCtrError], (unsigned long long)kErrInconsistent);
-  }
-  if (MODE == kOnePass) {
-    base = lookback_resolve(status, wt, tot, counters + kCtrError, kErrLookback);
-    if (valid) {
-      c_rp[row] = base + o;
-      if (row == op.rows - 1) {
-        c_rp[op.rows] = base + tot;
-        counters[kCtrNnz] = base + tot;
-      }
-    }
+    if (got != n) atomicOr((unsigned long long *)&counters[kCtrError], (unsigned long long)kErrInconsistent);
   }
   const int64_t lim = max((int64_t)0, min(tot, c_capacity - base));
   if (lim < tot && l == 0) atomicOr((unsigned long long *)&counters[kCtrError], (unsigned long long)kErrCapacity);
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   if (staged) {
-    for (int64_t q = l; q < lim; q += kWave) {
-      put_c(c_col, c_val, base + q, scw[q], svw[q]);
-    }
+    for (int64_t q = l; q < lim; q += kWave) put_c(c_col, c_val, base + q, scw[q], svw[q]);
   } else if (valid) {
     // the wave's output does not fit the staging: rows write their own entries
     const int64_t rl = max((int64_t)0, min(n, lim - o));
     const int64_t got = merge_row<M, true>(op, row, c_col + base + o, c_val + base + o, rl);
-    if (MODE == kNumeric && got != n)
-      atomicOr((unsigned long long *)&counters[kCtrError], (unsigned long long)kErrInconsistent);
+    if (got != n) atomicOr((unsigned long long *)&counters[kCtrError], (unsigned long long)kErrInconsistent);
   }
 }
 
 template <int M, int MODE>
-static hipError_t launch_wave_merge_mm(const Operands &op, int64_t blocks, int stage, int64_t *counters,
-                                       uint64_t *status, int32_t *cnt_out, int64_t *c_rp, int32_t *c_col,
-                                       double *c_val, int64_t c_capacity, hipStream_t s) {
-  const size_t lds = MODE == kSymbolic ? 0 : wave_merge_lds(stage);
+static hipError_t launch_wave_merge_mm(const Operands &op, int stage, int64_t *counters, int32_t *cnt_out,
+                                       int64_t *partials, const int64_t *c_rp, int32_t *c_col, double *c_val,
+                                       int64_t c_capacity, hipStream_t s) {
+  const size_t lds = wave_merge_lds(MODE, stage);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wave_merge<M, MODE>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_wave_merge<M, MODE>), dim3((unsigned)blocks), dim3(kBlock), lds, s, op, counters, status,
-                     cnt_out, c_rp, c_col, c_val, c_capacity, stage);
-  return hipGetLastError();
+  const int64_t blocks = (op.rows + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL((k_wave_merge<M, MODE>), dim3((unsigned)blocks), dim3(kBlock), lds, s, op, counters, cnt_out,
+                     partials, c_rp, c_col, c_val, c_capacity, stage);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || MODE != kSymbolic) return e;
+  const int32_t dst[2] = {kCtrMults, kCtrEmpty};
+  return launch_sum_partials(partials, blocks, 2, 2, dst, nullptr, counters, s);
 }
 
 template <int M>
-static hipError_t launch_wave_merge_m(const Operands &op, int mode, int64_t blocks, int stage, int64_t *counters,
-                                      uint64_t *status, int32_t *cnt_out, int64_t *c_rp, int32_t *c_col,
-                                      double *c_val, int64_t c_capacity, hipStream_t s) {
+static hipError_t launch_wave_merge_m(const Operands &op, int mode, int stage, int64_t *counters, int32_t *cnt_out,
+                                      int64_t *partials, const int64_t *c_rp, int32_t *c_col, double *c_val,
+                                      int64_t c_capacity, hipStream_t s) {
   if (mode == kSymbolic)
-    return launch_wave_merge_mm<M, kSymbolic>(op, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val,
-                                              c_capacity, s);
+    return launch_wave_merge_mm<M, kSymbolic>(op, stage, counters, cnt_out, partials, c_rp, c_col, c_val, c_capacity,
+                                              s);
   if (mode == kNumeric)
-    return launch_wave_merge_mm<M, kNumeric>(op, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val,
-                                             c_capacity, s);
-  return launch_wave_merge_mm<M, kOnePass>(op, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val,
-                                           c_capacity, s);
+    return launch_wave_merge_mm<M, kNumeric>(op, stage, counters, cnt_out, partials, c_rp, c_col, c_val, c_capacity,
+                                             s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_wave_merge(const Operands &op, int mode, int merge_lists, int stage, int64_t *counters,
-                             uint64_t *status, int32_t *cnt_out, int64_t *c_rp, int32_t *c_col, double *c_val,
-                             int64_t c_capacity, hipStream_t s) {
+                             int32_t *cnt_out, int64_t *partials, const int64_t *c_rp, int32_t *c_col,
+                             double *c_val, int64_t c_capacity, hipStream_t s) {
   if (op.rows <= 0) return hipSuccess;
-  const int64_t blocks = (op.rows + kBlock - 1) / kBlock;
   switch (merge_lists) {
-    case 4: return launch_wave_merge_m<4>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
-    case 6: return launch_wave_merge_m<6>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
-    case 8: return launch_wave_merge_m<8>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
-    case 10: return launch_wave_merge_m<10>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
-    case 16: return launch_wave_merge_m<16>(op, mode, blocks, stage, counters, status, cnt_out, c_rp, c_col, c_val, c_capacity, s);
+    case 4: return launch_wave_merge_m<4>(op, mode, stage, counters, cnt_out, partials, c_rp, c_col, c_val, c_capacity, s);
+    case 6: return launch_wave_merge_m<6>(op, mode, stage, counters, cnt_out, partials, c_rp, c_col, c_val, c_capacity, s);
+    case 8: return launch_wave_merge_m<8>(op, mode, stage, counters, cnt_out, partials, c_rp, c_col, c_val, c_capacity, s);
+    case 10: return launch_wave_merge_m<10>(op, mode, stage, counters, cnt_out, partials, c_rp, c_col, c_val, c_capacity, s);
+    case 16: return launch_wave_merge_m<16>(op, mode, stage, counters, cnt_out, partials, c_rp, c_col, c_val, c_capacity, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-// Largest output of one merge wave (64 consecutive rows) from the row
-// pointers of C: sizes the numeric pass's staging.
-__global__ void __launch_bounds__(kBlock) k_wave_span(const int64_t *rp, int64_t rows, int64_t *partials) {
-  int64_t m = 0;
-  const int64_t waves = (rows + kWave - 1) / kWave;
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < waves; i += (int64_t)gridDim.x * kBlock)
-    m = max(m, rp[min((i + 1) * kWave, rows)] - rp[i * kWave]);
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) m = max(m, __shfl_xor(m, d, kWave));
-  __shared__ int64_t red[kWavesPerBlock];
-  if (lane_id() == 0) red[threadIdx.x / kWave] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t t = 0;
-    for (int j = 0; j < kWavesPerBlock; ++j) t = max(t, red[j]);
-    partials[blockIdx.x] = t;
-  }
-}
-
-hipError_t launch_wave_span(const int64_t *rp, int64_t rows, int64_t *counters, int64_t *partials, hipStream_t s) {
-  if (rows <= 0) return launch_fill_i64(counters + kCtrWaveSpan, 0, 1, s);
-  const int64_t waves = (rows + kWave - 1) / kWave;
-  const int64_t blocks = std::min<int64_t>(1024, (waves + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_wave_span, dim3((unsigned)blocks), dim3(kBlock), 0, s, rp, rows, partials);
-  const int32_t dst[1] = {kCtrWaveSpan};
-  const int32_t mx[1] = {1};
-  return launch_sum_partials(partials, blocks, 1, 1, dst, mx, counters, s);
 }
 
 size_t wave_tile_lds(int mode, int table_slots, int stage_slots) {
