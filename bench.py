@@ -177,25 +177,134 @@ def time_steps(torch, products, sizer, model, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall * 1e3 / steps, per
 
 
-def cpu_baseline(workloads, random_rows=1 << 19):
-    """The oracle (single-threaded C Gustavson) on a bounded sample: the whole
-    stencil square and the leading rows of the random product.  Reported in
-    GFLOP/s with the same flop convention."""
-    import oracle
-    flops = 0
-    t_tot = 0.0
-    parts = []
-    for name, A, B in workloads:
-        f1, ub, mx = oracle.features(A, B)
-        r1 = A.rows if A.rows <= (1 << 22) and not name.startswith("random") else min(A.rows, random_rows)
+def _best_of(fn, min_runs=5, min_seconds=2.0, max_seconds=6.0):
+    """The paper's protocol (Section III): repeat until more than two
+    seconds have passed and at least five runs were made, keep the best (a
+    cap bounds the time of slow samples); returns (best, median, runs)."""
+    times = []
+    t_start = time.perf_counter()
+    while True:
         t0 = time.perf_counter()
-        oracle.spgemm(A, B, 0, r1)
-        dt = time.perf_counter() - t0
-        flops += 2 * int(ub[:r1].sum())
-        t_tot += dt
-        parts.append("%s rows 0..%d (%.2f s)" % (name, r1, dt))
-    return {"value": round(flops / t_tot / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": "; ".join(parts) + "; single-threaded C oracle, one run each, on the host of the GPU"}
+        fn()
+        times.append(time.perf_counter() - t0)
+        el = time.perf_counter() - t_start
+        if (len(times) >= min_runs and el > min_seconds) or el > max_seconds:
+            break
+    times.sort()
+    return times[0], times[len(times) // 2], len(times)
+
+
+def cpu_baseline(workloads, random_rows=1 << 17):
+    """The oracle (single-threaded C Gustavson) on a bounded sample: the whole
+    stencil square and the leading rows of the random product, on one host
+    core with the paper's protocol; and the same oracle run row-parallel on
+    every core the box gives the job (disjoint row ranges on threads; the C
+    calls release the interpreter lock), on eight times as many random rows.
+    Reported in GFLOP/s with the same flop convention."""
+    import concurrent.futures as cf
+    import numpy as np
+    import oracle
+    cores = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+
+    one = {"flops": 0, "best": 0.0, "median": 0.0}
+    par = {"flops": 0, "best": 0.0}
+    parts = []
+    with cf.ThreadPoolExecutor(cores) as ex:
+        for name, A, B in workloads:
+            _, ub, _ = oracle.features(A, B)
+            stencil = not name.startswith("random")
+            r1 = A.rows if stencil else min(A.rows, random_rows)
+            best, med, runs = _best_of(lambda: oracle.spgemm(A, B, 0, r1))
+            one["flops"] += 2 * int(ub[:r1].sum())
+            one["best"] += best
+            one["median"] += med
+            rp = A.rows if stencil else min(A.rows, 8 * random_rows)
+            bounds = np.linspace(0, rp, 4 * cores + 1).astype(np.int64)
+
+            def all_cores():
+                list(ex.map(lambda k: oracle.spgemm(A, B, int(bounds[k]), int(bounds[k + 1])), range(4 * cores)))
+            pbest, _, pruns = _best_of(all_cores)
+            par["flops"] += 2 * int(ub[:rp].sum())
+            par["best"] += pbest
+            parts.append("%s rows 0..%d on one core (best of %d: %.3f s, median %.3f s) and rows 0..%d on %d "
+                         "threads (best of %d: %.3f s)" % (name, r1, runs, best, med, rp, cores, pruns, pbest))
+    return {"value": round(one["flops"] / one["best"] / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "median_value": round(one["flops"] / one["median"] / 1e9, 4),
+            "all_cores": {"value": round(par["flops"] / par["best"] / 1e9, 4), "unit": "GFLOP/s", "cores": cores},
+            "sample": "; ".join(parts) + "; single-threaded C oracle, each timing the best of at least five runs "
+                      "over more than two seconds (the paper's protocol, Section III)"}
+
+
+def measure_bmax(torch, nbytes=1 << 31, reps=10):
+    """STREAM-style copy on the device (the paper's b_max, Section III): the
+    best of `reps` device-to-device copies of `nbytes`, counting the bytes
+    read and written."""
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return 2 * nbytes / (best * 1e-3) / 1e9
+
+
+def time_product(torch, p, sizer, model, steps):
+    """Whole-product time of one workload alone (plan, passes, host round
+    trips), CUDA events around `steps` products."""
+    p.run(sizer, model)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        p.run(sizer, model)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def compute_only_ms(P, torch, p, steps):
+    """The pure computation kernel (every row accumulated, nothing stored;
+    Section IV-A) on a product whose rows all merge in registers: its kernel
+    time (HIP events of the library), or None for other products."""
+    plan = P.Plan(p.dA, p.dB, "exact", timing=True)
+    try:
+        ms = []
+        for _ in range(steps + 1):
+            plan.compute_only()
+            ms.append(plan.info["tile_ms"])
+        return sum(ms[1:]) / steps
+    except P.SpgemmError:
+        return None
+    finally:
+        plan.close()
+
+
+def misprediction(P, torch, p, model, margin=0.05, slack=2):
+    """How the learned sizes compare with the exact ones on this product:
+    rows whose prediction falls below nnz(C_i), and rows whose capacity
+    (the prediction with the default margin and slack, clamped to [longest
+    selected B row, multiplication count]) does; those are the rows a
+    learned one pass must place elsewhere or compute again."""
+    f1, f2, f3 = P.row_features(p.dA, p.dB)
+    plan = P.Plan(p.dA, p.dB, "exact")
+    rp, _ = plan.symbolic()
+    plan.close()
+    exact = (rp[1:] - rp[:-1]).to(torch.float64)
+    pred = model.predict(f1, f2, f3).to(torch.float64)
+    cap = torch.ceil(pred * (1.0 + margin)) + slack
+    cap = torch.minimum(torch.maximum(cap, f3.to(torch.float64)), f2.to(torch.float64))
+    n = max(int(exact.numel()), 1)
+    return {"rows_predicted_below_exact": round(float((pred < exact).sum()) / n, 6),
+            "rows_capacity_below_exact": round(float((cap < exact).sum()) / n, 6),
+            "capacity_over_nnz": round(float(cap.sum()) / max(float(exact.sum()), 1.0), 4)}
 
 
 def traffic_from_profile(launch_bytes_alg):
@@ -270,41 +379,119 @@ def stats_summary(stats_csv, out_txt, command, top=16):
 
 
 def run_batched(P, torch, args):
-    """Batched products vs a per-instance loop (scaled instance sizes)."""
-    import synth
-    insts = synth.batch_mix(args.batch_count, 7, lo=args.batch_lo, hi=args.batch_hi)
-    As, Bs = [], []
-    for it in insts:
-        dA = P.DeviceCSR.from_host(it.A)
-        As.append(dA)
-        Bs.append(dA if it.B is it.A else P.DeviceCSR.from_host(it.B))
-    # both sides do the whole product every step: the one-pass bound sizer
-    # (an exact-sized batch would replay only its numeric pass)
-    batch = P.Batch(As, Bs, args.batch_sizer)
-    batch.run()
-    for _ in range(args.warmup):
-        batch.run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        batch.run()
-    torch.cuda.synchronize()
-    bms = (time.perf_counter() - t0) * 1e3 / args.steps
+    """The batched launch against a per-instance loop, both doing the same
+    work per step: the numeric pass of every instance.  The batch replays its
+    captured launches (the value copies and the numeric pass of the whole
+    concatenation; with the exact sizer the counts of its first run are
+    kept, with the one-pass sizers the whole one pass is replayed).  The loop
+    calls spgemm_numeric on every instance's plan, built (and, exact sizer,
+    counted by its symbolic pass) before the timed region: one call and one
+    host round trip per instance.  The batch runs with the default tuning
+    and with the autotuner's choice for a 256-instance sample of the same
+    kind (seed disjoint from the batch's)."""
     import numpy as np
+    import synth
+    from paper_1303_1651_amd.autotune import autotune_batch
+    log("generating %d instances, N log-uniform in [%d, %d]" % (args.batch_count, args.batch_lo, args.batch_hi))
+    insts = []
+    for k0 in range(0, args.batch_count, 256):
+        part = synth.batch_mix(min(256, args.batch_count - k0), 7 + k0, lo=args.batch_lo, hi=args.batch_hi)
+        insts += part
+        log("  %d instances" % len(insts))
+
+    def upload(items):
+        As, Bs = [], []
+        for it in items:
+            dA = P.DeviceCSR.from_host(it.A)
+            As.append(dA)
+            Bs.append(dA if it.B is it.A else P.DeviceCSR.from_host(it.B))
+        return As, Bs
+
+    As, Bs = upload(insts)
     mults = 0
     for it in insts:
         # Section III count: sum over k of nnz(A column k) * nnz(B row k)
         acol = np.bincount(np.asarray(it.A.col), minlength=it.A.cols)
         mults += int(np.dot(acol.astype(np.int64), np.diff(np.asarray(it.B.row_ptr)).astype(np.int64)))
-    t0 = time.perf_counter()
+    sizer = args.batch_sizer
+
+    def time_batch(tuning):
+        b = P.Batch(As, Bs, sizer, tuning=tuning)
+        b.run()
+        for _ in range(args.warmup):
+            b.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            b.run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        nnz_c, graph = int(b.nnz.sum()), b.uses_graph()
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+        return ms, nnz_c, graph
+
+    log("batched launch, default tuning")
+    ms_default, nnz_c, graph = time_batch(None)
+    log("autotuning on a 256-instance sample")
+    sample = synth.batch_mix(256, 99991, lo=args.batch_lo, hi=args.batch_hi)
+    sA, sB = upload(sample)
+    tuned, cand = autotune_batch(sA, sB, sizer, reps=2, log=lambda m: log("  " + m))
+    del sA, sB
+    torch.cuda.empty_cache()
+    log("batched launch, tuned: %s" % tuned)
+    ms_tuned, _, _ = time_batch(tuned)
+
+    log("per-instance loop: plans")
+    dev = As[0].row_ptr.device
+    plans, rps, caps = [], [], []
+    scratch_max = 0
     for a, b in zip(As, Bs):
-        P.spgemm(a, b, args.batch_sizer)
+        pl = P.Plan(a, b, sizer, alloc_scratch=False)
+        scratch_max = max(scratch_max, int(pl.info["scratch_bytes"]))
+        plans.append(pl)
+    shared = torch.empty(max(scratch_max, 1), dtype=torch.uint8, device=dev) if scratch_max else None
+    for pl in plans:
+        pl.scratch = shared
+        if sizer == "exact":
+            rp, nnz = pl.symbolic()
+            rps.append(rp)
+            caps.append(nnz)
+        else:
+            rps.append(torch.empty(pl.A.rows + 1, dtype=torch.int64, device=dev))
+            caps.append(max(int(pl.info["c_capacity_hint"]), 1))
+    cmax = max(max(caps), 1)
+    col = torch.empty(cmax, dtype=torch.int32, device=dev)
+    val = torch.empty(cmax, dtype=torch.float64, device=dev)
+
+    def loop():
+        for pl, rp, cap in zip(plans, rps, caps):
+            code, _ = pl.numeric(rp, col, val, capacity=cap)
+            P.check(code, "spgemm_numeric")
+    loop()
     torch.cuda.synchronize()
-    lms = (time.perf_counter() - t0) * 1e3
+    log("per-instance loop: timed")
+    t0 = time.perf_counter()
+    loop_steps = max(1, min(args.steps, 3))
+    for _ in range(loop_steps):
+        loop()
+    torch.cuda.synchronize()
+    lms = (time.perf_counter() - t0) * 1e3 / loop_steps
+    for pl in plans:
+        pl.close()
+    best = min(ms_default, ms_tuned)
     return {"instances": len(insts), "rows": int(sum(it.A.rows for it in insts)), "multiplications": mults,
-            "nnz_c": int(batch.nnz.sum()), "batched_ms": round(bms, 3), "loop_ms": round(lms, 3),
-            "batched_gflops": round(2 * mults / (bms * 1e-3) / 1e9, 3), "loop_gflops": round(2 * mults / (lms * 1e-3) / 1e9, 3),
-            "graph_replay": batch.uses_graph()}
+            "nnz_c": nnz_c, "sizer": sizer,
+            "batched_ms": round(best, 3), "batched_ms_default_tuning": round(ms_default, 3),
+            "batched_ms_tuned": round(ms_tuned, 3), "tuning": tuned, "tuning_candidates": len(cand),
+            "loop_ms": round(lms, 3), "loop_steps": loop_steps, "speedup_over_loop": round(lms / best, 2),
+            "batched_gflops": round(2 * mults / (best * 1e-3) / 1e9, 3),
+            "loop_gflops": round(2 * mults / (lms * 1e-3) / 1e9, 3), "graph_replay": graph,
+            "work_per_step": "both sides: the numeric pass of every instance (plans, and the exact sizer's "
+                             "counts, made before the timed region)"}
 
 
 def main():
@@ -319,7 +506,7 @@ def main():
                     choices=["roofline", "stencil", "random", "zipf", "st9", "st27", "batched"])
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-lo", type=int, default=256)
-    ap.add_argument("--batch-hi", type=int, default=4096)
+    ap.add_argument("--batch-hi", type=int, default=65536)
     ap.add_argument("--batch-sizer", default="exact", choices=["learned", "upper_bound", "exact"])
     ap.add_argument("--calibrate", action="store_true", help="also run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
@@ -352,7 +539,9 @@ def main():
                           "ms_per_step": res["batched_ms"], "higher_is_better": True, "scaling": "weak",
                           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
                           "config": {"workload": "batched: %d products, N log-uniform [%d, %d], half 5-point stencils, "
-                                                 "half random 4-32/row" % (args.batch_count, args.batch_lo, args.batch_hi)},
+                                                 "half random 4-32/row; numeric pass of every instance per step, "
+                                                 "batched replay vs per-instance loop" % (
+                                                     args.batch_count, args.batch_lo, args.batch_hi)},
                           "batched": res}), flush=True)
         return
 
@@ -430,6 +619,34 @@ def main():
             del b_csc
         details["step_ms_exact_csc_operand"] = round(details["step_ms_exact"] + conv, 4)
 
+    whole = {}
+    if not args.no_compare:
+        log("whole-product times, compute-only kernel, learned sizes against exact ones")
+        for p in products:
+            d = details[p.name]
+            mb = d["model_bytes"]
+            w = {"model_bytes": mb}
+            for sz in ("exact", "upper_bound", "learned"):
+                ms_p = time_product(torch, p, sz, model, args.steps)
+                w["product_ms_" + sz] = round(ms_p, 4)
+                w["GBps_" + sz] = round(mb / (ms_p * 1e-3) / 1e9, 1)
+            co = compute_only_ms(P, torch, p, args.steps)
+            if co is not None:
+                # Section IV-B measures storing as what the complete kernel
+                # adds to the pure computation kernel
+                d["compute_only_ms"] = round(co, 4)
+                d["compute_only_over_numeric_pass"] = round(co / d["numeric_pass_ms"], 3)
+                d["compute_only_over_product"] = round(co / w["product_ms_exact"], 3)
+            d["learned_sizes"] = misprediction(P, torch, p, model)
+            whole[p.name] = w
+    log("device copy bandwidth (b_max)")
+    bmax = measure_bmax(torch)
+    for w in whole.values():
+        for sz in ("exact", "upper_bound", "learned"):
+            gbps = w["GBps_" + sz]
+            w["frac_8TBps_" + sz] = round(gbps / HBM_PEAK_GBS, 4)
+            w["frac_bmax_" + sz] = round(gbps / bmax, 4)
+
     name, dms, dbytes, dinfo = dominant
     achieved = dbytes / (dms * 1e-3) / 1e9
     traffic = traffic_from_profile(dbytes) if name.startswith("random16") and args.sizer == "exact" else None
@@ -457,7 +674,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "numeric pass of %s (%s sizer)" % (name, args.sizer),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "algorithmic_bytes_per_launch": dbytes, "launch_ms": round(dms, 4)},
+                     "algorithmic_bytes_per_launch": dbytes, "launch_ms": round(dms, 4),
+                     "b_max_measured": round(bmax, 1), "frac_of_b_max": round(achieved / bmax, 4)},
+        "whole_product_roofline": {"note": "model bytes |A| + |B| + |C| over the whole product's time (plan, "
+                                           "passes and host round trips), against 8 TB/s and against b_max, the "
+                                           "device copy bandwidth measured in this run (the paper's b_max)",
+                                   **whole},
         "wall_ms_per_step": round(wall_ms, 3),
         "workloads": details,
     }

@@ -217,6 +217,21 @@ spgemm_status spgemm_numeric_static(spgemm_plan *plan, const double *a_val, cons
                                     int64_t c_capacity, int64_t *c_nnz, void *stream);
 size_t spgemm_numeric_static_limit(void);
 
+/* The pure computation kernel (Section IV-A), as a diagnostic beside the
+ * complete product (Section IV-B measures storing as the difference): every
+ * row of C is accumulated exactly as spgemm_numeric does (same order, same
+ * rounding), but nothing of C is stored.  For each row r only its number of
+ * entries (row_nnz[r], device int32, rows) and the largest magnitude of its
+ * values (row_maxabs[r], device FP64, rows; 0 for an empty row) are written,
+ * so the work cannot be skipped and can be checked.  Any sizer's plan;
+ * products whose rows all take the register merge only (every row of A with
+ * at most 16 entries and short outputs: the paper's five-point, nine-point
+ * and random five-per-row test cases), SPGEMM_E_INVALID otherwise.  a_val
+ * and b_val may be NULL (the descriptors' values).  Synchronises `stream`;
+ * with SPGEMM_OPT_TIMING the kernel's time is in spgemm_info.tile_ms. */
+spgemm_status spgemm_compute_only(spgemm_plan *plan, const double *a_val, const double *b_val,
+                                  int32_t *row_nnz, double *row_maxabs, void *stream);
+
 spgemm_status spgemm_plan_info(const spgemm_plan *plan, spgemm_info *info);
 int spgemm_plan_last_hip_error(const spgemm_plan *plan);
 void spgemm_plan_destroy(spgemm_plan *plan);

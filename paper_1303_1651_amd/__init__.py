@@ -239,7 +239,8 @@ class Plan:
     """One product C = A * B: plan, then (symbolic) and numeric passes."""
 
     def __init__(self, A: DeviceCSR, B: DeviceCSR, sizer="exact", model: Model | None = None,
-                 fast=False, validate=False, tuning: dict | None = None, stream=None, timing=False):
+                 fast=False, validate=False, tuning: dict | None = None, stream=None, timing=False,
+                 alloc_scratch=True):
         self.A, self.B = A, B
         self.device = A.row_ptr.device
         self.stream = stream
@@ -262,7 +263,10 @@ class Plan:
                                        ctypes.byref(self.handle), ctypes.byref(info))
         check(code, "spgemm_plan_create")
         self.info = info.as_dict()
-        self.scratch = _bytes(self.info["scratch_bytes"], self.device) if self.info["scratch_bytes"] else None
+        # alloc_scratch=False: the caller sets .scratch (say, one buffer that
+        # plans used one after another share)
+        self.scratch = (_bytes(self.info["scratch_bytes"], self.device)
+                        if alloc_scratch and self.info["scratch_bytes"] else None)
 
     def _scratch(self):
         return (self.scratch.data_ptr(), self.scratch.numel()) if self.scratch is not None else (None, 0)
@@ -294,6 +298,18 @@ class Plan:
                                    _stream_ptr(self.stream))
         self.refresh_info()
         return code, int(nnz.value)
+
+    def compute_only(self):
+        """Accumulates every row of C without storing it (the pure
+        computation kernel of Section IV-A); returns each row's entry count
+        (int32) and largest |value| (float64) as device tensors."""
+        n = self.A.rows
+        cnt = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        mx = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+        check(_lib.spgemm_compute_only(self.handle, None, None, cnt.data_ptr(), mx.data_ptr(),
+                                       _stream_ptr(self.stream)), "spgemm_compute_only")
+        self.refresh_info()
+        return cnt[:n], mx[:n]
 
     def numeric_static(self, c_row_ptr, c_col, c_val, capacity=None):
         """The numeric pass with the library's static scratch (no allocation

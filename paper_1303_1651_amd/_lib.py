@@ -90,6 +90,7 @@ spgemm_symbolic = _sig("spgemm_symbolic", ctypes.c_int, [P, P, SZ, P, I64_P, P])
 spgemm_numeric = _sig("spgemm_numeric", ctypes.c_int, [P, P, SZ, P, P, P, P, P, I64, I64_P, P])
 spgemm_numeric_static = _sig("spgemm_numeric_static", ctypes.c_int, [P, P, P, P, P, P, I64, I64_P, P])
 spgemm_numeric_static_limit = _sig("spgemm_numeric_static_limit", SZ, [])
+spgemm_compute_only = _sig("spgemm_compute_only", ctypes.c_int, [P, P, P, P, P, P])
 spgemm_plan_info = _sig("spgemm_plan_info", ctypes.c_int, [P, INFO_P])
 spgemm_plan_last_hip_error = _sig("spgemm_plan_last_hip_error", ctypes.c_int, [P])
 spgemm_plan_destroy = _sig("spgemm_plan_destroy", None, [P])
@@ -116,7 +117,7 @@ spgemm_model_predict = _sig("spgemm_model_predict", ctypes.c_int, [P, P, P, P, I
 
 EXPORTED = [
     "spgemm_status_string", "spgemm_plan_workspace_size", "spgemm_plan_create", "spgemm_symbolic",
-    "spgemm_numeric", "spgemm_numeric_static", "spgemm_numeric_static_limit", "spgemm_plan_info", "spgemm_plan_last_hip_error", "spgemm_plan_destroy",
+    "spgemm_numeric", "spgemm_numeric_static", "spgemm_numeric_static_limit", "spgemm_compute_only", "spgemm_plan_info", "spgemm_plan_last_hip_error", "spgemm_plan_destroy",
     "spgemm_model_create", "spgemm_model_get", "spgemm_model_save", "spgemm_model_load",
     "spgemm_model_destroy", "spgemm_model_device_bytes", "spgemm_model_upload", "spgemm_row_features",
     "spgemm_model_stats_scratch", "spgemm_model_feature_stats", "spgemm_model_grad_scratch",

@@ -15,7 +15,7 @@ import os
 
 import torch
 
-from . import DeviceCSR, Plan, check
+from . import Batch, DeviceCSR, Plan, check
 
 DEFAULT_GRID = {
     "table_slots": [512, 1024, 2048],
@@ -87,3 +87,45 @@ def autotune(A: DeviceCSR, B: DeviceCSR, sizer: str = "exact", model=None, grid:
         stored[key] = {"tuning": best, "ms": best_ms, "candidates": len(results)}
         json.dump(stored, open(cache, "w"), indent=1, sort_keys=True)
     return best
+
+
+BATCH_GRID = {
+    "table_slots": [512, 1024, 2048],
+    "stage_slots": [512, 1024],
+    "merge_max_nnz": [32, 64],
+    "dense_ratio": [1.0, 2.0, 4.0],
+}
+
+
+def autotune_batch(As, Bs, sizer: str = "exact", model=None, grid: dict | None = None, reps: int = 3,
+                   log=None) -> tuple[dict, list]:
+    """Tuning block for a batch of products: every candidate of the grid
+    builds the batch (its first run captures the launches) and its graph
+    replays are timed (best of `reps`); returns the fastest candidate and
+    every (ms, candidate) pair.  Pass a sample of a large batch: the choice
+    carries over to batches of the same kind."""
+    grid = grid or BATCH_GRID
+    names = list(grid)
+    results = []
+    for values in itertools.product(*[grid[n] for n in names]):
+        t = dict(zip(names, values))
+        if 12 * (t.get("table_slots", 1024) + t.get("stage_slots", 1024)) > 147456:
+            continue
+        b = Batch(As, Bs, sizer, model=model, tuning=t)
+        b.run()
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        b.close()
+        results.append((best, t))
+        if log:
+            log("%8.3f ms  %s" % (best, t))
+    results.sort(key=lambda r: r[0])
+    return results[0][1], results

@@ -900,6 +900,27 @@ spgemm_status spgemm_numeric(spgemm_plan *p, void *scratch, size_t scratch_bytes
                       nullptr);
 }
 
+spgemm_status spgemm_compute_only(spgemm_plan *p, const double *a_val, const double *b_val, int32_t *row_nnz,
+                                  double *row_maxabs, void *stream) {
+  if (!p || (p->A.rows > 0 && (!row_nnz || !row_maxabs))) return SPGEMM_E_NULL;
+  const double *av = a_val ? a_val : p->A.val;
+  const double *bv = b_val ? b_val : p->B.val;
+  if ((p->A.nnz > 0 && !av) || (p->B.nnz > 0 && !bv)) return SPGEMM_E_NULL;
+  if (!p->merge_only && p->A.rows > 0) return SPGEMM_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  timing_begin(p, s, &e);
+  HIPCK(p, e);
+  HIPCK(p, launch_wave_merge(operands_of(p, av, bv), kComputeOnly, p->merge_m, 0, ctr(p), row_nnz, nullptr, nullptr,
+                             nullptr, row_maxabs, 0, s));
+  timing_end(p, s, &e);
+  HIPCK(p, e);
+  int64_t *h;
+  spgemm_status st = read_counters(p, s, &h);
+  if (st != SPGEMM_OK) return st;
+  return device_errors(p, h);
+}
+
 spgemm_status spgemm_plan_info(const spgemm_plan *p, spgemm_info *info) {
   if (!p || !info) return SPGEMM_E_NULL;
   *info = p->info;

@@ -26,7 +26,9 @@ __host__ __device__ inline bool info_esc(uint32_t w) { return (w >> 3) & 1u; }
 __host__ __device__ inline uint32_t info_slots(uint32_t w) { return w >> 4; }
 
 // Pass kinds of the tile kernel.
-enum Mode : int { kSymbolic = 0, kNumeric = 1, kOnePass = 2 };
+// kComputeOnly: the numeric accumulation without storing C (row-per-thread
+// merge kernels only).
+enum Mode : int { kSymbolic = 0, kNumeric = 1, kOnePass = 2, kComputeOnly = 3 };
 
 // counters[] layout (int64, device)
 enum Counter : int {
@@ -281,7 +283,9 @@ hipError_t launch_sum_partials(const int64_t *partials, int64_t nblocks, int n, 
 // tier (merge_lists 4, 6, 8, 10 or 16).  kSymbolic: counts into cnt_out,
 // multiplication count and empty rows into counters (through partials).
 // kNumeric: C from the exact row_ptr c_rp, `stage` entries of LDS staging
-// per wave.
+// per wave.  kComputeOnly: every row accumulated, nothing of C stored; the
+// row's entry count into cnt_out and its largest |value| into c_val (one
+// per row).
 hipError_t launch_wave_merge(const Operands &op, int mode, int merge_lists, int stage, int64_t *counters,
                              int32_t *cnt_out, int64_t *partials, const int64_t *c_rp, int32_t *c_col,
                              double *c_val, int64_t c_capacity, hipStream_t s);

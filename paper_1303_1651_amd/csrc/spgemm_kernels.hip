@@ -757,7 +757,7 @@ __device__ __forceinline__ RowHash make_hash(int32_t lo, int32_t hi, int64_t slo
 // the row-major kernel.  Writes min(count, lim) entries; returns the count.
 template <int M, bool VALUES, bool DBUF = true>
 __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, double *out_val,
-                             int64_t lim, int64_t *ub_out = nullptr) {
+                             int64_t lim, int64_t *ub_out = nullptr, double *maxabs_out = nullptr) {
   const int64_t as = op.a_rp[row];
   const int m = (int)(op.a_rp[row + 1] - as);
   // per list: head (h, v), with DBUF the entry after it (h2, v2), the next
@@ -826,6 +826,7 @@ __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, 
       out_col[n] = mn;
       if (VALUES) out_val[n] = acc;
     }
+    if (VALUES && maxabs_out) *maxabs_out = fmax(*maxabs_out, fabs(acc));
     ++n;
   }
   return n;
@@ -2363,7 +2364,7 @@ __host__ __device__ inline size_t wave_merge_vals_offset(int stage) {
   return (((size_t)kWavesPerBlock * stage * 4) + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t wave_merge_lds(int mode, int stage) {
-  if (mode == kSymbolic) return 0;
+  if (mode != kNumeric) return 0;
   return wave_merge_vals_offset(stage) + (size_t)kWavesPerBlock * stage * 8;
 }
 
@@ -2397,6 +2398,18 @@ k_wave_merge(Operands op, int64_t *counters, int32_t *cnt_out, int64_t *partials
       }
       partials[2 * blockIdx.x] = a;
       partials[2 * blockIdx.x + 1] = b;
+    }
+    return;
+  }
+  if (MODE == kComputeOnly) {
+    // every entry accumulated as in the numeric pass, none stored: the
+    // row's count and largest magnitude are all that leave the chip
+    const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (row < op.rows) {
+      double mx = 0.0;
+      const int64_t n = merge_row<M, true>(op, row, nullptr, nullptr, 0, nullptr, &mx);
+      cnt_out[row] = (int32_t)n;
+      c_val[row] = mx;
     }
     return;
   }
@@ -2458,6 +2471,9 @@ static hipError_t launch_wave_merge_m(const Operands &op, int mode, int stage, i
   if (mode == kNumeric)
     return launch_wave_merge_mm<M, kNumeric>(op, stage, counters, cnt_out, partials, c_rp, c_col, c_val, c_capacity,
                                              s);
+  if (mode == kComputeOnly)
+    return launch_wave_merge_mm<M, kComputeOnly>(op, 0, counters, cnt_out, partials, c_rp, c_col, c_val, c_capacity,
+                                                 s);
   return hipErrorInvalidValue;
 }
 

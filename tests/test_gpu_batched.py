@@ -112,3 +112,18 @@ def test_batch_matches_per_instance_products():
         one = P.spgemm(As[i], Bs[i], "exact")
         assert_bit_exact(batch.product(i), want)
         assert_bit_exact((one.row_ptr.cpu().numpy(), one.col.cpu().numpy(), one.val.cpu().numpy()), want)
+
+
+def test_batch_autotuner_picks_a_valid_tuning_and_stays_exact():
+    import paper_1303_1651_amd as P
+    from paper_1303_1651_amd.autotune import autotune_batch
+    insts = _batch(24, 41, lo=64, hi=2048)
+    wants = [oracle.spgemm(it.A, it.B) for it in insts]
+    As, Bs = _dev(insts)
+    grid = {"table_slots": [512, 1024], "dense_ratio": [1.0, 2.0]}
+    best, cands = autotune_batch(As, Bs, "exact", grid=grid, reps=1)
+    assert len(cands) == 4 and best in [t for _, t in cands]
+    batch = P.Batch(As, Bs, "exact", tuning=best)
+    batch.run()
+    batch.run()
+    _check_all(batch, insts, wants)
