@@ -124,9 +124,9 @@ class Product:
         self.name, self.A, self.B, self.dA, self.dB = name, A, B, dA, dB
         self.out = {}
 
-    def run(self, sizer, model):
+    def run(self, sizer, model, tuning=None):
         P, torch = self.P, self.torch
-        plan = P.Plan(self.dA, self.dB, sizer, model, timing=True)
+        plan = P.Plan(self.dA, self.dB, sizer, model, timing=True, tuning=tuning)
         dev = self.dA.row_ptr.device
         sym_ms = 0.0
         if sizer == "exact":
@@ -256,18 +256,74 @@ def measure_bmax(torch, nbytes=1 << 31, reps=10):
     return 2 * nbytes / (best * 1e-3) / 1e9
 
 
-def time_product(torch, p, sizer, model, steps):
+def time_product(torch, p, sizer, model, steps, tuning=None, numeric=False):
     """Whole-product time of one workload alone (plan, passes, host round
-    trips), CUDA events around `steps` products."""
-    p.run(sizer, model)
+    trips), CUDA events around `steps` products; with numeric=True also the
+    numeric pass's kernel time (the library's HIP events)."""
+    p.run(sizer, model, tuning)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    num = []
     e0.record()
     for _ in range(steps):
-        p.run(sizer, model)
+        num.append(p.run(sizer, model, tuning)[1]["numeric_ms"])
     e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps
+    ms = e0.elapsed_time(e1) / steps
+    return (ms, sum(num) / len(num)) if numeric else ms
+
+
+# The storing-strategy study of Section IV-B: random matrices of 0.1 % fill,
+# the dense window (MinMax) against the sorted table (Sort) as N grows.
+FILL_NS = [4096, 8192, 16384, 24576, 32768, 38912, 49152, 65536, 98304, 131072]
+
+
+def run_fill(P, torch, args):
+    """Every product of the sweep three ways on the plain two-pass path: the
+    library's default choice, every row in the workgroup tier with a dense
+    window of its column region (MinMax), and every row there with a hashed
+    table whose runs are sorted on the way out (Sort).  Reports the numeric
+    pass and the whole product of each, and where the dense window starts to
+    win (as N and as the ratio of a row's column region to its entries, the
+    quantity the dense-window rule compares)."""
+    import synth
+    forced = {"dense_window": {"merge_max_nnz": -1, "table_slots": -1, "dense_ratio": 1e9},
+              "sorted_table": {"merge_max_nnz": -1, "table_slots": -1, "dense_ratio": 1e-9}}
+    out = []
+    for n in FILL_NS:
+        if n > args.fill_max:
+            break
+        A = synth.random_fill(n, 0.001, 11)
+        B = synth.random_fill(n, 0.001, 12)
+        dA, dB = P.DeviceCSR.from_host(A), P.DeviceCSR.from_host(B)
+        prod = Product(P, torch, "fill%d" % n, A, B, dA, dB)
+        got, info = prod.run("exact", None)
+        row = {"n": n, "row_entries": int(A.row_ptr[1]), "nnz_c": got, "multiplications": info["multiplications"],
+               "region_over_entries": round(n / max(got / n, 1e-9), 2)}
+        for label, tuning in (("default", None), ("dense_window", forced["dense_window"]),
+                              ("sorted_table", forced["sorted_table"])):
+            ms, num = time_product(torch, prod, "exact", None, args.steps, tuning, numeric=True)
+            row["product_ms_" + label] = round(ms, 4)
+            row["numeric_ms_" + label] = round(num, 4)
+            row["gflops_" + label] = round(2 * info["multiplications"] / (ms * 1e-3) / 1e9, 3)
+        log("fill n=%d: numeric dense %.3f ms, sorted %.3f ms, default %.3f ms" % (
+            n, row["numeric_ms_dense_window"], row["numeric_ms_sorted_table"], row["numeric_ms_default"]))
+        out.append(row)
+        del prod, dA, dB
+        torch.cuda.empty_cache()
+    # break-even: first N from which the dense window's numeric pass is faster
+    cross = None
+    for a, b in zip(out, out[1:]):
+        da = a["numeric_ms_dense_window"] - a["numeric_ms_sorted_table"]
+        db = b["numeric_ms_dense_window"] - b["numeric_ms_sorted_table"]
+        if da > 0 >= db or da < 0 <= db:
+            t = da / (da - db)
+            cross = {"n": round(a["n"] + t * (b["n"] - a["n"])),
+                     "region_over_entries": round(a["region_over_entries"] + t * (b["region_over_entries"] -
+                                                                                  a["region_over_entries"]), 2),
+                     "dense_wins_above": db <= 0}
+            break
+    return out, cross
 
 
 def compute_only_ms(P, torch, p, steps):
@@ -503,7 +559,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other sizers")
     ap.add_argument("--workload", default="roofline",
-                    choices=["roofline", "stencil", "random", "zipf", "st9", "st27", "batched"])
+                    choices=["roofline", "stencil", "random", "zipf", "st9", "st27", "batched", "fill"])
+    ap.add_argument("--fill-max", type=int, default=131072, help="largest N of the 0.1%%-fill sweep")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-lo", type=int, default=256)
     ap.add_argument("--batch-hi", type=int, default=65536)
@@ -531,6 +588,19 @@ def main():
     import paper_1303_1651_amd as P
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+
+    if args.workload == "fill":
+        rows, cross = run_fill(P, torch, args)
+        ref = next((r for r in rows if r["n"] == 38912), rows[-1])
+        print(json.dumps({"metric": "SpGEMM GFLOP/s on 0.1%-fill random products, dense window vs sorted table",
+                          "value": ref["gflops_default"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": 1, "ms_per_step": ref["product_ms_default"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "random N x N, ceil(0.001 N) distinct columns per row, U(-1, 1), "
+                                                 "C = A * B, N swept %d..%d; value at N = %d" % (
+                                                     rows[0]["n"], rows[-1]["n"], ref["n"])},
+                          "sweep": rows, "break_even": cross}), flush=True)
+        return
 
     if args.workload == "batched":
         res = run_batched(P, torch, args)

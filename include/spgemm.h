@@ -64,7 +64,9 @@ typedef enum spgemm_status {
     SPGEMM_E_STATE = 8,           /* calls out of order (e.g. numeric before plan)   */
     SPGEMM_E_HIP = 9,             /* HIP runtime error                               */
     SPGEMM_E_INVALID = 10,        /* bad option value                                */
-    SPGEMM_E_IO = 11              /* model file could not be read or written         */
+    SPGEMM_E_IO = 11,             /* model file could not be read or written         */
+    SPGEMM_STATUS_INT_RANGE = 0x7fffffff  /* not a status: makes every int a value of the
+                                             type, so that status_string may take any */
 } spgemm_status;
 
 /* A CSR matrix; pointers are device pointers.  val may be NULL where only

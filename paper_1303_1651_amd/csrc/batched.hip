@@ -304,12 +304,6 @@ spgemm_status spgemm_batched_plan(int64_t count, const spgemm_csr *A, const spge
   b->plan_bytes = plan_workspace_bytes(R, K);
   b->o_plan = take(b->plan_bytes);
   b->total = o;
-  void *pin = nullptr;
-  if (hipHostMalloc(&pin, sizeof(int64_t) * (2 * count + 1 + kNumCounters), hipHostMallocDefault) != hipSuccess) {
-    delete b;
-    return SPGEMM_E_HIP;
-  }
-  b->pinned = static_cast<int64_t *>(pin);
   *workspace_bytes = b->total;
   *out = b;
   return SPGEMM_OK;
@@ -320,6 +314,13 @@ spgemm_status spgemm_batched_reserve(spgemm_batch *b, void *workspace, size_t wo
   if (!b || !workspace || !c_capacity || !scratch_bytes) return SPGEMM_E_NULL;
   if (workspace_bytes < b->total || !aligned256(workspace)) return SPGEMM_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
+  if (!b->pinned) {
+    // host buffer the runs read the instances' sizes and the counters into
+    void *pin = nullptr;
+    if (hipHostMalloc(&pin, sizeof(int64_t) * (2 * b->count + 1 + kNumCounters), hipHostMallocDefault) != hipSuccess)
+      return SPGEMM_E_HIP;
+    b->pinned = static_cast<int64_t *>(pin);
+  }
   drop_graph(b);
   if (b->plan) {
     spgemm_plan_destroy(b->plan);

@@ -415,6 +415,7 @@ static spgemm_status run_big(spgemm_plan *p, int mode, bool overflow_list, void 
   bp.scratch = static_cast<char *>(scratch) + off;
   bp.scratch_slots = p->scratch_slots;
   bp.fast = (p->opts.flags & SPGEMM_OPT_FAST) ? 1 : 0;
+  bp.dense_ratio = p->tune.dense_ratio;
   // the list's huge rows are split into column ranges (the rows listed for
   // the exact path after a one pass are not)
   bp.split = overflow_list ? 0 : 1;
@@ -526,6 +527,7 @@ const char *spgemm_status_string(spgemm_status s) {
     case SPGEMM_E_HIP: return "HIP runtime error";
     case SPGEMM_E_INVALID: return "invalid option";
     case SPGEMM_E_IO: return "model file error";
+    default: break;
   }
   return "unknown status";
 }

@@ -183,6 +183,7 @@ struct BigParams {
   char *scratch;            // per-workgroup device tables
   int64_t scratch_slots;    // slots per workgroup
   int fast;                 // reordered accumulation allowed
+  float dense_ratio;        // dense window when the column region <= ratio * count
   int split;                // the first kMaxSplitRows rows of the huge front of
                             // the list take kSplitParts tickets each; those of
                             // kSplitWork products or more are computed as

@@ -348,12 +348,13 @@ hipError_t launch_row_max(const Operands &op, int64_t *counters, int64_t *partia
 // ------------------------------------------------------------ sizing/tiers
 // Device table of a workgroup-tier row: capacity c, load <= 1/2, and c
 // slots of probe room so that linear probing can never run off the end; a
-// dense window when the column region is at most twice the capacity (the
-// paper's "Combined" rule of Section IV-B: MinMax when the region is
-// smaller than twice the row's entries, Sort otherwise).
-__device__ __forceinline__ int64_t global_table_alloc(int64_t span, int64_t c, bool *dense,
+// dense window when the column region is at most `ratio` times the capacity
+// (the paper's "Combined" rule of Section IV-B: MinMax when the region is
+// smaller than twice the row's entries, Sort otherwise; the ratio is a
+// tuning parameter, 2 by default).
+__device__ __forceinline__ int64_t global_table_alloc(int64_t span, int64_t c, float ratio, bool *dense,
                                                        int64_t *slots) {
-  if (span <= 2 * c) {
+  if ((double)span <= (double)ratio * (double)c) {
     *dense = true;
     *slots = span;
     return span;
@@ -364,8 +365,12 @@ __device__ __forceinline__ int64_t global_table_alloc(int64_t span, int64_t c, b
 }
 
 // Slots global_table_alloc takes for any capacity up to c (a smaller exact
-// count may trade a dense window for a hashed table).
-__device__ __forceinline__ int64_t global_table_bound(int64_t c) { return 3 * c + 16; }
+// count may trade a dense window for a hashed table); a dense window is at
+// most `cols` slots.
+__device__ __forceinline__ int64_t global_table_bound(int64_t c, float ratio, int64_t cols) {
+  const double d = min((double)ratio * (double)c, (double)cols);
+  return max(3 * c + 16, (int64_t)ceil(d));
+}
 
 constexpr int64_t kSortMax = 1024;   // keys a wave sorts in registers (64 lanes x 16)
 constexpr int64_t kEscMax = 512;    // products of an expand-sort row (64 lanes x 8)
@@ -491,17 +496,18 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
         // to the workgroup tier gets its device table counted already
         if (sym && (table_pow2(2 * ub) > sp.value_table_max || ub > kSortMax) &&
             !((double)span <= (double)sp.dense_ratio * (double)mx && span <= sp.value_table_max))
-          scratch = global_table_bound(ub);
+          scratch = global_table_bound(ub, sp.dense_ratio, op.b_cols);
       } else {
         tier = kTierGlobal;
         info = pack_info(kTierGlobal, false, 0);
         big = true;
-        scratch = global_table_bound(sp.mode == kNumeric ? c : ub);
+        scratch = global_table_bound(sp.mode == kNumeric ? c : ub, sp.dense_ratio, op.b_cols);
       }
     }
     // learned one pass: any row may outgrow its capacity and be computed by
     // a workgroup with a device table sized by its exact count (<= bound)
-    if (sp.mode == kOnePass && sp.sizer == 2 && tier != kTierEmpty) scratch = max(scratch, global_table_bound(ub));
+    if (sp.mode == kOnePass && sp.sizer == 2 && tier != kTierEmpty)
+      scratch = max(scratch, global_table_bound(ub, sp.dense_ratio, op.b_cols));
     pa.info[i] = info;
     pa.cap[i] = (int32_t)c;
     pa.cost[i] = cost;
@@ -2277,7 +2283,7 @@ __global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
     bool dense = false;
     int64_t slots = 0, alloc = 0;
     if (work) {
-      alloc = global_table_alloc((int64_t)hi - lo + 1, c, &dense, &slots);
+      alloc = global_table_alloc((int64_t)hi - lo + 1, c, p.dense_ratio, &dense, &slots);
       if (alloc > p.scratch_slots) {
         if (threadIdx.x == 0) atomicOr((unsigned long long *)err, (unsigned long long)kErrScratch);
         work = false;

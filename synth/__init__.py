@@ -176,6 +176,14 @@ def random_fixed(n: int, k: int, seed: int, cols: int | None = None) -> CSR:
     return random_rows(n, cols, np.full(n, k, dtype=np.int64), seed)
 
 
+def random_fill(n: int, fill: float, seed: int) -> CSR:
+    """n x n matrix with ceil(fill * n) distinct uniform-random columns per
+    row, values U(-1, 1): the random test case at a fixed fill (0.1 % in the
+    storing-strategy study of Section IV-B, whose product rows then hold
+    about (0.001 n)^2 entries spread over all n columns)."""
+    return random_fixed(n, max(1, int(math.ceil(fill * n - 1e-9))), seed)
+
+
 def random_uniform_lengths(n: int, lo: int, hi: int, seed: int) -> CSR:
     """Square n x n matrix, row lengths uniform in {lo..hi} (capped at n)."""
     bits = splitmix64(_sub_seed(seed, 3), np.arange(n, dtype=np.uint64))

@@ -392,3 +392,20 @@ def test_autotuner_picks_a_valid_tuning(tmp_path):
     # cached on the second call, and the tuned product is still exact
     assert autotune(dA, dA, "exact", grid=grid, reps=1, cache=cache) == best
     assert_bit_exact(gpu_product(A, A, "exact", tuning=best), oracle.spgemm(A, A))
+
+
+@pytest.mark.parametrize("n", [8192, 40960])
+def test_fill01_random_dense_window_and_sorted_table(n):
+    # the storing-strategy study's random matrices (0.1 % fill, Section IV-B):
+    # product rows of about (0.001 n)^2 entries over all n columns; the
+    # workgroup tier with a dense window (MinMax) for every row, with a
+    # hashed, sorted table (Sort) for every row, and the default choice
+    A = synth.random_fill(n, 0.001, 5)
+    B = synth.random_fill(n, 0.001, 6)
+    want = oracle.spgemm(A, B)
+    dense = {"merge_max_nnz": -1, "table_slots": -1, "dense_ratio": 1e9}
+    hashed = {"merge_max_nnz": -1, "table_slots": -1, "dense_ratio": 1e-9}
+    for sizer in SIZERS:
+        for tuning in (None, dense, hashed):
+            got = gpu_product(A, B, sizer, tuning=tuning)
+            assert_bit_exact(got, want)

@@ -392,3 +392,16 @@ def test_generators_match_paper_workload_shapes():
         c, _ = R.row(i)
         assert np.all(np.diff(c) > 0)
     assert np.all((R.val > -1) & (R.val < 1))
+
+
+def test_fill_generator_rows():
+    # 0.1 % fill: ceil(0.001 n) distinct columns per row, sorted, in range
+    for n, k in ((5000, 5), (38912, 39), (1000, 1)):
+        A = synth.random_fill(n, 0.001, 3)
+        assert A.rows == n and A.cols == n
+        lens = np.diff(A.row_ptr)
+        assert np.all(lens == k)
+        for i in range(0, n, max(1, n // 50)):
+            c = A.col[A.row_ptr[i]:A.row_ptr[i + 1]]
+            assert np.all(np.diff(c) > 0) and c.min() >= 0 and c.max() < n
+        assert np.all(np.abs(A.val) < 1.0)
