@@ -10,7 +10,10 @@
 // transpose; move every entry of M to its place, into scratch; then each row
 // of the transpose is written in increasing column order, every entry at the
 // number of smaller columns in its row (the columns of a row are distinct
-// for a canonical M).
+// for a canonical M): counted by shuffles for short rows, by a sort in LDS
+// for rows of up to kTrSortMax entries, and for longer ones from sorted
+// chunks (the entry's place in its chunk plus a binary search in each
+// other chunk).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -111,19 +114,23 @@ __global__ void __launch_bounds__(kBlock) k_tr_order(const int64_t *t_rp, int64_
 
 // The listed rows of the transpose (longer than kTrLong), one workgroup each: up to
 // kTrSortMax entries sorted as (column, source index) pairs by a bitonic
-// network in LDS (columns distinct, so the order is unique); longer rows by
-// counting the smaller columns of every entry over the whole row.
+// network in LDS (columns distinct, so the order is unique) and written out;
+// a longer row is cut into chunks of kTrSortMax entries, each chunk sorted
+// the same way and put back in place in the scratch (columns and values),
+// for k_tr_rank_long.
 __global__ void __launch_bounds__(kBlock) k_tr_order_long(const int64_t *t_rp, const int64_t *longs,
-                                                          const int64_t *nlong, const int32_t *tmp_col,
-                                                          const double *tmp_val, int32_t *t_col, double *t_val) {
+                                                          const int64_t *nlong, int32_t *tmp_col, double *tmp_val,
+                                                          int32_t *t_col, double *t_val) {
   __shared__ int32_t sk[kTrSortMax];
   __shared__ int32_t si[kTrSortMax];
   const int t = threadIdx.x;
   const int64_t nl = *nlong;
   for (int64_t li = blockIdx.x; li < nl; li += gridDim.x) {
     const int64_t q = longs[li];
-    const int64_t s = t_rp[q], len = t_rp[q + 1] - s;
-    if (len <= kTrSortMax) {
+    const int64_t s0 = t_rp[q], len0 = t_rp[q + 1] - s0;
+    for (int64_t c0 = 0; c0 < len0; c0 += kTrSortMax) {
+      // the whole row (len0 <= kTrSortMax), or one chunk of a longer row
+      const int64_t s = s0 + c0, len = min((int64_t)kTrSortMax, len0 - c0);
       int n = 1;
       while (n < len) n <<= 1;
       for (int i = t; i < n; i += kBlock) {
@@ -150,19 +157,65 @@ __global__ void __launch_bounds__(kBlock) k_tr_order_long(const int64_t *t_rp, c
           __syncthreads();
         }
       }
-      for (int i = t; i < len; i += kBlock) {
-        t_col[s + i] = sk[i];
-        if (t_val) t_val[s + i] = tmp_val[s + si[i]];
+      if (len0 <= kTrSortMax) {
+        for (int i = t; i < len; i += kBlock) {
+          t_col[s + i] = sk[i];
+          if (t_val) t_val[s + i] = tmp_val[s + si[i]];
+        }
+      } else {
+        // the chunk sorted in place: every value read before any is written
+        constexpr int kPer = kTrSortMax / kBlock;
+        double v[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int i = t + u * kBlock;
+          v[u] = (tmp_val && i < len) ? tmp_val[s + si[i]] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int i = t + u * kBlock;
+          if (i < len) {
+            tmp_col[s + i] = sk[i];
+            if (tmp_val) tmp_val[s + i] = v[u];
+          }
+        }
       }
       __syncthreads();
-    } else {
-      for (int64_t i = t; i < len; i += kBlock) {
-        const int32_t key = tmp_col[s + i];
-        int64_t rank = 0;
-        for (int64_t j = 0; j < len; ++j) rank += tmp_col[s + j] < key ? 1 : 0;
-        t_col[s + rank] = key;
-        if (t_val) t_val[s + rank] = tmp_val[s + i];
+    }
+  }
+}
+
+// Rows of the transpose longer than kTrSortMax, their chunks sorted: every
+// entry's place in the row is its place in its chunk plus, for every other
+// chunk, the number of its columns below the entry's (a binary search; the
+// columns of a row are distinct).  All workgroups share each row's entries.
+__global__ void __launch_bounds__(kBlock) k_tr_rank_long(const int64_t *t_rp, const int64_t *longs,
+                                                         const int64_t *nlong, const int32_t *tmp_col,
+                                                         const double *tmp_val, int32_t *t_col, double *t_val) {
+  const int64_t nl = *nlong;
+  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x, nt = (int64_t)gridDim.x * kBlock;
+  for (int64_t li = 0; li < nl; ++li) {
+    const int64_t q = longs[li];
+    const int64_t s = t_rp[q], len = t_rp[q + 1] - s;
+    if (len <= kTrSortMax) continue;
+    const int64_t nch = (len + kTrSortMax - 1) / kTrSortMax;
+    for (int64_t i = tid; i < len; i += nt) {
+      const int32_t key = tmp_col[s + i];
+      const int64_t mine = i / kTrSortMax;
+      int64_t rank = i - mine * kTrSortMax;
+      for (int64_t d = 0; d < nch; ++d) {
+        if (d == mine) continue;
+        int64_t lo = d * kTrSortMax, hi = min(len, lo + kTrSortMax);
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (tmp_col[s + mid] < key) lo = mid + 1;
+          else hi = mid;
+        }
+        rank += lo - d * kTrSortMax;
       }
+      t_col[s + rank] = key;
+      if (t_val) t_val[s + rank] = tmp_val[s + i];
     }
   }
 }
@@ -264,6 +317,11 @@ spgemm_status spgemm_transpose(const spgemm_csr *M, int64_t *t_row_ptr, int32_t 
     hipLaunchKernelGGL(k_tr_order_long, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(nnz / (kTrLong + 1) + 1, 1024))),
                        dim3(kBlock), 0, s, (const int64_t *)t_row_ptr, (const int64_t *)longs, (const int64_t *)(ctr + 3),
                        tmp_col, tmp_val, t_col, t_val);
+    // rows longer than one LDS sort: only when M has that many entries
+    if (nnz > kTrSortMax)
+      hipLaunchKernelGGL(k_tr_rank_long, dim3((unsigned)grid_for(nnz, kBlock)), dim3(kBlock), 0, s,
+                         (const int64_t *)t_row_ptr, (const int64_t *)longs, (const int64_t *)(ctr + 3), tmp_col,
+                         tmp_val, t_col, t_val);
   }
   if (hipGetLastError() != hipSuccess) return SPGEMM_E_HIP;
   if (hipMemcpyAsync(&herr, ctr, sizeof(herr), hipMemcpyDeviceToHost, s) != hipSuccess ||

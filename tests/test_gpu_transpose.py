@@ -31,6 +31,21 @@ def _by_columns(M):
     return synth.CSR(T.rows, T.cols, T.row_ptr, T.col, T.val)
 
 
+def _long_columns(n_rows, n_cols, seed):
+    # random rows, one column in every row, another in every third row: rows
+    # of the transpose of n_rows and n_rows / 3 entries (sorted in chunks)
+    M = synth.random_uniform_lengths(n_rows, 0, 6, seed)
+    rows = []
+    for i in range(n_rows):
+        c = M.col[M.row_ptr[i]:M.row_ptr[i + 1]].astype(np.int64) % n_cols
+        extra = [5] + ([n_cols - 2] if i % 3 == 0 else [])
+        rows.append(np.unique(np.append(c, extra)))
+    ptr = np.zeros(n_rows + 1, np.int64)
+    ptr[1:] = np.cumsum([r.size for r in rows])
+    col = np.concatenate(rows).astype(np.int32)
+    return synth.CSR(n_rows, n_cols, ptr, col, np.random.default_rng(seed).uniform(-1, 1, col.size))
+
+
 CASES = {
     # rows of the transpose of up to a few thousand entries (sorted in LDS)
     "zipf_by_columns": lambda: _by_columns(synth.zipf_matrix(20000, 5)),
@@ -39,6 +54,8 @@ CASES = {
     "zipf": lambda: synth.zipf_matrix(20000, 5),
     "dense_column": lambda: _dense_column(5000, 900, 17, 8),
     "one_row": lambda: synth.random_sparse(1, 5000, 0.3, 9),
+    # rows of the transpose of 120,000 and 40,000 entries
+    "long_columns": lambda: _long_columns(120000, 2000, 12),
     "empty": lambda: synth.random_sparse(30, 20, 0.0, 1),
     "no_rows": lambda: synth.CSR(0, 7, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0)),
     "no_cols": lambda: synth.CSR(5, 0, np.zeros(6, np.int64), np.zeros(0, np.int32), np.zeros(0)),
