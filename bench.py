@@ -275,7 +275,7 @@ def time_product(torch, p, sizer, model, steps, tuning=None, numeric=False):
 
 # The storing-strategy study of Section IV-B: random matrices of 0.1 % fill,
 # the dense window (MinMax) against the sorted table (Sort) as N grows.
-FILL_NS = [4096, 8192, 16384, 24576, 32768, 38912, 49152, 65536, 98304, 131072]
+FILL_NS = [4096, 8192, 16384, 24576, 32768, 38912, 49152, 65536, 98304, 131072, 163840, 196608]
 
 
 def run_fill(P, torch, args):
@@ -560,7 +560,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other sizers")
     ap.add_argument("--workload", default="roofline",
                     choices=["roofline", "stencil", "random", "zipf", "st9", "st27", "batched", "fill"])
-    ap.add_argument("--fill-max", type=int, default=131072, help="largest N of the 0.1%%-fill sweep")
+    ap.add_argument("--fill-max", type=int, default=196608, help="largest N of the 0.1%%-fill sweep")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-lo", type=int, default=256)
     ap.add_argument("--batch-hi", type=int, default=65536)
@@ -569,6 +569,7 @@ def main():
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
                     help="write the traffic summary from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--pmc-command", default="")
+    ap.add_argument("--pmc-kernel", default="k_wt<1,", help="kernel name substring of the counter summary")
     ap.add_argument("--stats-summary", nargs=2, metavar=("KERNEL_STATS_CSV", "OUT_TXT"),
                     help="write a text summary of a rocprofv3 --stats run and exit (command: --pmc-command)")
     args = ap.parse_args()
@@ -576,7 +577,7 @@ def main():
         stats_summary(args.stats_summary[0], args.stats_summary[1], args.pmc_command)
         return
     if args.pmc_summary:
-        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], "k_wt<1,", 1 << 30, args.pmc_summary[2],
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_kernel, 1 << 30, args.pmc_summary[2],
                     args.pmc_command)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
