@@ -92,6 +92,12 @@ __device__ __forceinline__ int32_t wave_max32(int32_t v) {
   return v;
 }
 
+__device__ __forceinline__ int32_t wave_min32(int32_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v = min(v, __shfl_xor(v, d, kWave));
+  return v;
+}
+
 // Block-wide exclusive scan of one int64 per thread.  `wtot` is LDS scratch
 // of kWavesPerBlock + 1 entries; returns the exclusive prefix and the total.
 __device__ __forceinline__ int64_t block_exclusive_sum(int64_t v, int64_t *wtot, int64_t *total) {

@@ -165,20 +165,21 @@ __global__ void __launch_bounds__(kBlock) k_mlp_predict(const float *__restrict_
   for (int j = 0; j < kPredRowsPerThread; ++j) {
     const int64_t r = base + j * kBlock + threadIdx.x;
     mine[j] = kNoKey;
-    if (r < n) {
-      if (FEAT) {
-        int64_t m, ub;
-        int32_t mx, lo, hi;
-        row_features<false>(op, r, m, ub, mx, lo, hi);
+    if (FEAT) {
+      // every lane takes part: long rows are walked by the whole wave
+      int64_t m, ub;
+      int32_t mx, lo, hi;
+      wave_row_features<false>(op, r, r < n, m, ub, mx, lo, hi);
+      if (r < n) {
         const int64_t u = min(ub, (int64_t)op.b_cols);
         mine[j] = triple_key((int32_t)min(m, (int64_t)0x7fffffff), (int32_t)u, mx);
         if (mine[j] == kNoKey) unpacked += u;
         mults += ub;
         max_a = max(max_a, m);
         empty += ub == 0 ? 1 : 0;
-      } else {
-        mine[j] = triple_key(f1a[r], f2a[r], f3a[r]);
       }
+    } else if (r < n) {
+      mine[j] = triple_key(f1a[r], f2a[r], f3a[r]);
     }
   }
 #pragma unroll

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "device_common.h"
+
 namespace spg {
 
 // Per-row tier.  EMPTY rows produce nothing; MERGE rows are merged in
@@ -240,6 +242,86 @@ __device__ __forceinline__ void row_features(const Operands &op, int64_t i, int6
         ub += len;
         mx = max(mx, len);
       }
+    }
+  }
+}
+
+// The same features for the rows held by the lanes of a wave (row i where
+// `live`; every lane of the wave calls it).  A row of at most kFeatLong
+// entries is walked by its own lane; longer rows (power-law rows reach
+// thousands of entries) are walked by the whole wave, one after another,
+// each lane taking every 64th entry, so that no lane walks a long row while
+// the other 63 wait.  Integer sums, minima and maxima: the result does not
+// depend on who walks the row.
+constexpr int64_t kFeatLong = 32;
+template <bool SPAN>
+__device__ __forceinline__ void wave_row_features(const Operands &op, int64_t i, bool live, int64_t &m, int64_t &ub,
+                                                  int32_t &mx, int32_t &lo, int32_t &hi,
+                                                  const int32_t *brow = nullptr) {
+  m = 0;
+  ub = 0;
+  mx = 0;
+  lo = 0x7fffffff;
+  hi = -1;
+  int64_t s = 0, e = 0;
+  if (live) {
+    s = op.a_rp[i];
+    e = op.a_rp[i + 1];
+  }
+  const bool longrow = live && e - s > kFeatLong;
+  if (live && !longrow) row_features<SPAN>(op, i, m, ub, mx, lo, hi, brow);
+  uint64_t pend = ballot(longrow);
+  const int lane = lane_id();
+  while (pend) {
+    const int r = __ffsll((unsigned long long)pend) - 1;
+    pend &= pend - 1;
+    const int64_t rs = __shfl(s, r, kWave), re = __shfl(e, r, kWave);
+    int64_t u = 0;
+    int32_t x = 0, l = 0x7fffffff, h = -1;
+    // four entries per lane at a time: their gathers are in flight together
+    for (int64_t q0 = rs + lane; q0 < re; q0 += 4 * kWave) {
+      int32_t k[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) k[q] = q0 + q * kWave < re ? op.a_col[q0 + q * kWave] : -1;
+      if (SPAN) {
+        int4 rr[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          rr[q] = k[q] >= 0 ? reinterpret_cast<const int4 *>(brow)[k[q]] : make_int4(0, 0x7fffffff, -1, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          u += rr[q].x;
+          x = max(x, rr[q].x);
+          l = min(l, rr[q].y);
+          h = max(h, rr[q].z);
+        }
+      } else {
+        int64_t bs[4], be[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          bs[q] = k[q] >= 0 ? op.b_rp[k[q]] : 0;
+          be[q] = k[q] >= 0 ? op.b_rp[k[q] + 1] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int32_t len = (int32_t)(be[q] - bs[q]);
+          u += len;
+          x = max(x, len);
+        }
+      }
+    }
+    u = wave_sum(u);
+    x = wave_max32(x);
+    if (SPAN) {
+      l = wave_min32(l);
+      h = wave_max32(h);
+    }
+    if (lane == r) {
+      m = re - rs;
+      ub = u;
+      mx = x;
+      lo = l;
+      hi = h;
     }
   }
 }

@@ -138,9 +138,9 @@ __global__ void __launch_bounds__(kBlock) k_features(Operands op, Features f, in
   if (i == 0 && (op.a_rp[op.rows] != op.a_nnz || op.b_rp[op.b_rows] != op.b_nnz))
     atomicOr((unsigned long long *)err, (unsigned long long)kErrDescriptor);
   int64_t ub = 0, m = 0, empty = 0;
+  int32_t mx, lo, hi;
+  wave_row_features<MODE == 2>(op, i, i < op.rows, m, ub, mx, lo, hi, f.brow);
   if (i < op.rows) {
-    int32_t mx, lo, hi;
-    row_features<MODE == 2>(op, i, m, ub, mx, lo, hi, f.brow);
     if (MODE == 2) {
       f.nnz_a[i] = (int32_t)m;
       f.ub[i] = (int32_t)min(ub, (int64_t)op.b_cols);
@@ -881,7 +881,6 @@ __device__ __forceinline__ void wg_sync_global() {
 }
 
 // Write the sorted row held by an LDS table (G lanes).
-constexpr int kDupSlots = 1024;   // LDS set of a batch's table slots (ordered values)
 struct WgScratch {
   int64_t pref[kBlock + 1];
   int64_t bs[kBlock];
@@ -889,98 +888,17 @@ struct WgScratch {
   int64_t wtot[kWavesPerBlock + 1];
   int32_t cnt, dmax;
   int64_t run;
-  int32_t dset[kDupSlots];
   int32_t first;   // extraction: the end of a chunk
 };
 
-// Products of the row (those of columns in [c0, c1); c1 < 0: all)
-// enumerated flat over the workgroup, 256 A entries at a time;
-// fn(b_position, a_value) is called once per product.
-template <typename Fn>
-__device__ void wg_for_products(const Operands &op, int64_t row, int32_t c0, int32_t c1, WgScratch &ws, Fn fn) {
-  const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
-  for (int64_t eb = as; eb < ae; eb += kBlock) {
-    const int64_t e = eb + threadIdx.x;
-    int64_t bs = 0, bl = 0;
-    double av = 0.0;
-    if (e < ae) {
-      av = op.a_val ? op.a_val[e] : 0.0;
-      int32_t l;
-      b_row_part(op, e, c0, c1, bs, l);
-      bl = l;
-    }
-    int64_t tot;
-    int64_t ex = block_exclusive_sum(bl, ws.wtot, &tot);
-    ws.pref[threadIdx.x] = ex;
-    ws.bs[threadIdx.x] = bs;
-    ws.av[threadIdx.x] = av;
-    __syncthreads();
-    for (int64_t q = threadIdx.x; q < tot; q += kBlock) {
-      int lo = 0, hi = kBlock - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (ws.pref[mid] <= q) lo = mid;
-        else hi = mid - 1;
-      }
-      fn(ws.bs[lo] + (q - ws.pref[lo]), ws.av[lo]);
-    }
-    __syncthreads();
-  }
-}
-
-__device__ __forceinline__ int32_t global_probe_insert(int32_t *keys, int64_t alloc, const RowHash &hs,
-                                                      int32_t j, bool *is_new, int32_t *disp) {
-  int32_t h = hs.home(j);
-  int64_t s = h;
-  *is_new = false;
-  while (s < alloc) {
-    int32_t old = gcas(&keys[s], kEmpty, j);
-    if (old == kEmpty) {
-      *is_new = true;
-      break;
-    }
-    if (old == j) break;
-    ++s;
-  }
-  *disp = (int32_t)(s - h);
-  return (int32_t)s;
-}
-
-// Slot holding key j (inserted earlier), or -1 if it is missing.
-__device__ __forceinline__ int64_t global_find(const int32_t *keys, int64_t alloc, const RowHash &hs, int32_t j) {
-  for (int64_t s = hs.home(j); s < alloc; ++s)
-    if (gload(keys + s) == j) return s;
-  return -1;
-}
-
-// Builds the row's key set in the table and returns its size.  The table
-// has room for every product (c >= the row's multiplication count or its
-// exact size), so no probe leaves it; a key that would is reported through
-// *err (kErrInconsistent) rather than dropped silently.
-__device__ int32_t wg_global_keys(const Operands &op, int64_t row, int32_t c0, int32_t c1, int32_t *keys,
-                                  int64_t alloc, const RowHash &hs, WgScratch &ws, double *vals_or_null,
-                                  int64_t *err) {
-  for (int64_t s = threadIdx.x; s < alloc; s += kBlock) {
-    gstore(keys + s, kEmpty);
-    if (vals_or_null) gstored(vals_or_null + s, 0.0);
-  }
-  if (threadIdx.x == 0) {
-    ws.cnt = 0;
-    ws.dmax = 0;
-  }
-  wg_sync_global();
-  wg_for_products(op, row, c0, c1, ws, [&](int64_t bpos, double) {
-    int32_t j = op.b_col[bpos];
-    bool nw;
-    int32_t disp;
-    int32_t s = global_probe_insert(keys, alloc, hs, j, &nw, &disp);
-    if (s >= alloc) atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
-    if (nw) atomicAdd(&ws.cnt, 1);
-    if (disp > 0) atomicMax(&ws.dmax, disp);
-  });
-  wg_sync_global();
-  return ws.cnt;
-}
+// Extraction staging of the workgroup tier (see wg_extract_chunked); free
+// while the table is built, when it holds the LDS sets of the ordered
+// accumulation.
+constexpr int kExtChunk = 2048, kExtPad = 256;
+struct ExtLds {
+  int32_t k[kExtChunk + kExtPad];
+  double v[kExtChunk + kExtPad];
+};
 
 // Waits until this wave's outstanding memory operations have completed (no
 // cache write-back or invalidation): the device-table updates of one
@@ -1016,120 +934,298 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Values of the row into the table built by wg_global_keys.  Ordered: the
-// products are taken in A's stored order, 256 at a time over the workgroup
-// (entries of A 256 at a time, their B rows enumerated flat), so within a
-// chunk the thread index follows A's order.  Products of one chunk that
-// share no slot (checked through an LDS set) update their slots at once; a
-// chunk where a slot repeats updates in rounds, in each of which the
-// lowest-indexed pending product of every slot applies (an LDS minimum per
-// slot in `cellmin`, kDupSlots words that hold INT32_MAX between uses): as
-// many rounds as the chunk's largest repeat count.  The stores of a round
-// complete before the next round or chunk reads, so every slot is
-// accumulated in A's column order.  Fast: every product at once with atomic
-// adds.
-__device__ void wg_global_values(const Operands &op, int64_t row, int32_t c0, int32_t c1, const int32_t *keys,
-                                 double *vals, int64_t alloc, const RowHash &hs, WgScratch &ws, int32_t *cellmin,
-                                 bool fast) {
-  if (fast) {
-    wg_for_products(op, row, c0, c1, ws, [&](int64_t bpos, double av) {
-      int32_t j = op.b_col[bpos];
-      int64_t s = global_find(keys, alloc, hs, j);
-      double p;
-      {
-#pragma clang fp contract(off)
-        p = av * op.b_val[bpos];
+// Workgroup-tier passes take the row's products in steps of kWgChunk, in
+// A's stored order (entries of A 256 at a time, their B rows enumerated
+// flat): thread t holds products q0 + u * kBlock + t for u < kWgProducts, so
+// that the gathers and table probes of its kWgProducts products are in
+// flight together.
+constexpr int kWgProducts = 4;
+constexpr int kWgChunk = kBlock * kWgProducts;
+constexpr int kDupBits = 11;
+constexpr int kDupSlots = 1 << kDupBits;   // LDS set of one step's columns (2 x kWgChunk)
+static_assert(kDupSlots == 2 * kWgChunk, "set size");
+static_assert(sizeof(ExtLds::v) / 4 >= kDupSlots, "LDS set");
+
+// Stages the next (at most) 256 entries of A from eb: the exclusive sums of
+// their B rows' lengths (those of columns in [c0, c1); c1 < 0: all), the B
+// row starts and the A values.  Returns the batch's product count.  The
+// caller synchronises before restaging.
+__device__ __forceinline__ int64_t wg_stage_entries(const Operands &op, int64_t eb, int64_t ae, int32_t c0,
+                                                    int32_t c1, WgScratch &ws, bool values) {
+  const int64_t e = eb + threadIdx.x;
+  int64_t bs = 0, bl = 0;
+  double av = 0.0;
+  if (e < ae) {
+    av = values && op.a_val ? op.a_val[e] : 0.0;
+    int32_t l;
+    b_row_part(op, e, c0, c1, bs, l);
+    bl = l;
+  }
+  int64_t tot;
+  const int64_t ex = block_exclusive_sum(bl, ws.wtot, &tot);
+  ws.pref[threadIdx.x] = ex;
+  ws.bs[threadIdx.x] = bs;
+  ws.av[threadIdx.x] = av;
+  __syncthreads();
+  return tot;
+}
+
+// This thread's products of the step at q0 of a staged batch of tot
+// products: B positions and A values (live[u] false past the batch).
+__device__ __forceinline__ void wg_step_products(const WgScratch &ws, int64_t q0, int64_t tot, int64_t *bpos,
+                                                 double *av, bool *live) {
+#pragma unroll
+  for (int u = 0; u < kWgProducts; ++u) {
+    const int64_t q = q0 + u * kBlock + threadIdx.x;
+    live[u] = q < tot;
+    bpos[u] = 0;
+    av[u] = 0.0;
+    if (live[u]) {
+      int lo = 0, hi = kBlock - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ws.pref[mid] <= q) lo = mid;
+        else hi = mid - 1;
       }
-      if (s >= 0) atomicAdd(&vals[s], p);
-    });
-    wg_sync_global();
-    return;
+      bpos[u] = ws.bs[lo] + (q - ws.pref[lo]);
+      av[u] = ws.av[lo];
+    }
   }
-  const int t = threadIdx.x;
-  for (int q = t; q < kDupSlots; q += kBlock) {
-    ws.dset[q] = -1;
-    cellmin[q] = 0x7fffffff;
+}
+
+// Inserts the keys j[u] (where go[u]) into the device table: slot[u] is the
+// key's slot, fresh[u] whether this call claimed it.  The first probes of
+// the thread's keys are issued together; a key displaced further probes on
+// one slot at a time.  The table has room for every product, so no probe
+// leaves it; one that would sets *full (reported, never dropped silently).
+__device__ __forceinline__ void global_insert_n(int32_t *keys, int64_t alloc, const RowHash &hs, const int32_t *j,
+                                                const bool *go, int64_t *slot, bool *fresh, int32_t &dmax,
+                                                bool &full) {
+  int32_t old[kWgProducts];
+#pragma unroll
+  for (int u = 0; u < kWgProducts; ++u) {
+    slot[u] = go[u] ? hs.home(j[u]) : 0;
+    old[u] = go[u] ? gcas(&keys[slot[u]], kEmpty, j[u]) : kEmpty;
   }
+#pragma unroll
+  for (int u = 0; u < kWgProducts; ++u) {
+    fresh[u] = false;
+    if (!go[u]) continue;
+    if (old[u] == kEmpty) {
+      fresh[u] = true;
+      continue;
+    }
+    if (old[u] == j[u]) continue;
+    const int64_t h = slot[u];
+    int64_t sl = h + 1;
+    while (sl < alloc) {
+      const int32_t o = gcas(&keys[sl], kEmpty, j[u]);
+      if (o == kEmpty) {
+        fresh[u] = true;
+        break;
+      }
+      if (o == j[u]) break;
+      ++sl;
+    }
+    if (sl >= alloc) {
+      full = true;
+      sl = h;   // never used: the row is reported
+    }
+    slot[u] = sl;
+    dmax = max(dmax, (int32_t)(sl - h));
+  }
+}
+
+// Publishes a pass's distinct-key count and largest displacement to ws.
+__device__ __forceinline__ void wg_publish_keys(WgScratch &ws, int32_t nnew, int32_t dmax, bool full, int64_t *err) {
+  const int32_t wn = (int32_t)wave_sum((int64_t)nnew), wd = wave_max32(dmax);
+  const bool wf = ballot(full) != 0;
+  if (lane_id() == 0) {
+    if (wn) atomicAdd(&ws.cnt, wn);
+    if (wd) atomicMax(&ws.dmax, wd);
+    if (wf) atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
+  }
+}
+
+// Counting pass of a workgroup-tier row (or of the column range [c0, c1) of
+// a split one): builds its key set in the table and returns its size.
+__device__ int32_t wg_global_keys(const Operands &op, int64_t row, int32_t c0, int32_t c1, int32_t *keys,
+                                  int64_t alloc, const RowHash &hs, WgScratch &ws, int64_t *err) {
+  for (int64_t s = threadIdx.x; s < alloc; s += kBlock) gstore(keys + s, kEmpty);
+  if (threadIdx.x == 0) {
+    ws.cnt = 0;
+    ws.dmax = 0;
+  }
+  wg_sync_global();
+  int32_t nnew = 0, dmax = 0;
+  bool full = false;
   const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
   for (int64_t eb = as; eb < ae; eb += kBlock) {
-    const int64_t e = eb + t;
-    int64_t bs = 0, bl = 0;
-    double av = 0.0;
-    if (e < ae) {
-      av = op.a_val[e];
-      int32_t l;
-      b_row_part(op, e, c0, c1, bs, l);
-      bl = l;
+    const int64_t tot = wg_stage_entries(op, eb, ae, c0, c1, ws, false);
+    for (int64_t q0 = 0; q0 < tot; q0 += kWgChunk) {
+      int64_t bpos[kWgProducts], slot[kWgProducts];
+      double av[kWgProducts];
+      bool live[kWgProducts], fresh[kWgProducts];
+      int32_t j[kWgProducts];
+      wg_step_products(ws, q0, tot, bpos, av, live);
+#pragma unroll
+      for (int u = 0; u < kWgProducts; ++u) j[u] = live[u] ? op.b_col[bpos[u]] : 0;
+      global_insert_n(keys, alloc, hs, j, live, slot, fresh, dmax, full);
+#pragma unroll
+      for (int u = 0; u < kWgProducts; ++u) nnew += fresh[u] ? 1 : 0;
     }
-    int64_t tot;
-    const int64_t ex = block_exclusive_sum(bl, ws.wtot, &tot);
-    ws.pref[t] = ex;
-    ws.bs[t] = bs;
-    ws.av[t] = av;
     __syncthreads();
-    for (int64_t q0 = 0; q0 < tot; q0 += kBlock) {
-      const int64_t q = q0 + t;
-      int64_t sl = -1;
-      double a = 0.0, b = 0.0;
-      if (q < tot) {
-        int lo = 0, hi = kBlock - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (ws.pref[mid] <= q) lo = mid;
-          else hi = mid - 1;
-        }
-        const int64_t bpos = ws.bs[lo] + (q - ws.pref[lo]);
-        a = ws.av[lo];
-        b = op.b_val[bpos];
-        sl = global_find(keys, alloc, hs, op.b_col[bpos]);
+  }
+  wg_publish_keys(ws, nnew, dmax, full, err);
+  wg_sync_global();
+  return ws.cnt;
+}
+
+// Numeric pass of a workgroup-tier row (or of a column range): keys and
+// values in one sweep over the products, in A's order.  A step whose
+// columns are distinct (checked through an LDS set of its columns) inserts
+// its keys and updates their slots at once: a slot claimed by the step
+// starts at +0.0 + a*b, one claimed earlier adds a*b to what the earlier
+// steps left (their stores have completed before this step reads).  A step
+// where a column repeats applies in rounds, in each of which the
+// lowest-indexed pending product of every column inserts and updates (an
+// LDS minimum per column, kept in the column's cell of the set, INT32_MAX
+// between rounds): as many rounds as the step's largest repeat count.  So every entry of C sums its
+// products in A's column order, as the row-major kernel does (Section
+// IV-A).  Fast: every product at once, atomic adds into slots cleared to
+// +0.0 (the summation order is then not fixed).  Returns the row's size.
+__device__ int32_t wg_global_accumulate(const Operands &op, int64_t row, int32_t c0, int32_t c1, int32_t *keys,
+                                        double *vals, int64_t alloc, const RowHash &hs, WgScratch &ws, ExtLds &xl,
+                                        bool fast, int64_t *err) {
+  const int t = threadIdx.x;
+  int32_t *dset = reinterpret_cast<int32_t *>(xl.v);
+  for (int64_t s = t; s < alloc; s += kBlock) {
+    gstore(keys + s, kEmpty);
+    if (fast) gstored(vals + s, 0.0);
+  }
+  for (int q = t; q < kDupSlots; q += kBlock) dset[q] = kEmpty;
+  if (t == 0) {
+    ws.cnt = 0;
+    ws.dmax = 0;
+  }
+  wg_sync_global();
+  int32_t nnew = 0, dmax = 0;
+  bool full = false;
+  const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
+  for (int64_t eb = as; eb < ae; eb += kBlock) {
+    const int64_t tot = wg_stage_entries(op, eb, ae, c0, c1, ws, true);
+    for (int64_t q0 = 0; q0 < tot; q0 += kWgChunk) {
+      int64_t bpos[kWgProducts], slot[kWgProducts];
+      double a[kWgProducts], b[kWgProducts];
+      bool live[kWgProducts], fresh[kWgProducts];
+      int32_t j[kWgProducts];
+      wg_step_products(ws, q0, tot, bpos, a, live);
+#pragma unroll
+      for (int u = 0; u < kWgProducts; ++u) {
+        j[u] = live[u] ? op.b_col[bpos[u]] : 0;
+        b[u] = live[u] ? op.b_val[bpos[u]] : 0.0;
       }
-      // does a slot repeat within the chunk?
+      if (fast) {
+        global_insert_n(keys, alloc, hs, j, live, slot, fresh, dmax, full);
+#pragma unroll
+        for (int u = 0; u < kWgProducts; ++u) {
+          nnew += fresh[u] ? 1 : 0;
+          if (live[u] && !full) {
+            double p;
+            {
+#pragma clang fp contract(off)
+              p = a[u] * b[u];
+            }
+            atomicAdd(&vals[slot[u]], p);
+          }
+        }
+        continue;
+      }
+      // does a column repeat within the step?
+      int32_t cell[kWgProducts], at[kWgProducts];
       bool dup = false;
-      int32_t at = -1, cell = 0;
-      if (sl >= 0) {
-        uint32_t h = ((uint32_t)sl * 0x9E3779B1u) >> (32 - 10);
+#pragma unroll
+      for (int u = 0; u < kWgProducts; ++u) {
+        at[u] = -1;
+        cell[u] = 0;
+        if (!live[u]) continue;
+        uint32_t h = ((uint32_t)j[u] * 0x9E3779B1u) >> (32 - kDupBits);
         while (true) {
-          const int32_t old = atomicCAS(&ws.dset[h], -1, (int32_t)sl);
-          if (old == -1) {
-            at = (int32_t)h;
+          const int32_t o = atomicCAS(&dset[h], kEmpty, j[u]);
+          if (o == kEmpty) {
+            at[u] = (int32_t)h;
             break;
           }
-          if (old == (int32_t)sl) {
+          if (o == j[u]) {
             dup = true;
             break;
           }
           h = (h + 1) & (kDupSlots - 1);
         }
-        cell = (int32_t)h;
+        cell[u] = (int32_t)h;
       }
       const bool ordered = __syncthreads_or(dup ? 1 : 0) != 0;
-      if (at >= 0) ws.dset[at] = -1;
-      if (!ordered) {
-        if (sl >= 0) gstored(vals + sl, mul_add_rn(gloadd(vals + sl), a, b));
+      // the set's cells of this step's columns: free again, or (ordered)
+      // the columns' round minima
+#pragma unroll
+      for (int u = 0; u < kWgProducts; ++u)
+        if (at[u] >= 0) dset[at[u]] = ordered ? 0x7fffffff : kEmpty;
+      bool pend[kWgProducts];
+#pragma unroll
+      for (int u = 0; u < kWgProducts; ++u) pend[u] = live[u];
+      while (true) {
+        bool go[kWgProducts];
+        if (ordered) {
+          // the first pending product of every column applies
+          bool any = false;
+#pragma unroll
+          for (int u = 0; u < kWgProducts; ++u) any |= pend[u];
+          if (!__syncthreads_or(any ? 1 : 0)) break;
+#pragma unroll
+          for (int u = 0; u < kWgProducts; ++u)
+            if (pend[u]) atomicMin(&dset[cell[u]], u * kBlock + t);
+          __syncthreads();
+#pragma unroll
+          for (int u = 0; u < kWgProducts; ++u) go[u] = pend[u] && dset[cell[u]] == u * kBlock + t;
+        } else {
+#pragma unroll
+          for (int u = 0; u < kWgProducts; ++u) go[u] = pend[u];
+        }
+        global_insert_n(keys, alloc, hs, j, go, slot, fresh, dmax, full);
+        double old[kWgProducts];
+#pragma unroll
+        for (int u = 0; u < kWgProducts; ++u) old[u] = (go[u] && !fresh[u] && !full) ? gloadd(vals + slot[u]) : 0.0;
+#pragma unroll
+        for (int u = 0; u < kWgProducts; ++u) {
+          if (!go[u] || full) continue;
+          nnew += fresh[u] ? 1 : 0;
+          gstored(vals + slot[u], fresh[u] ? first_add_rn(a[u], b[u]) : mul_add_rn(old[u], a[u], b[u]));
+        }
         wave_mem_wait();
         __syncthreads();
-      } else {
-        // rounds: the first pending product of every slot applies
-        bool pending = sl >= 0;
-        while (__syncthreads_or(pending ? 1 : 0)) {
-          if (pending) atomicMin(&cellmin[cell], t);
-          __syncthreads();
-          const bool go = pending && cellmin[cell] == t;
-          if (go) gstored(vals + sl, mul_add_rn(gloadd(vals + sl), a, b));
-          wave_mem_wait();
-          __syncthreads();
-          if (go) {
-            cellmin[cell] = 0x7fffffff;
-            pending = false;
+        if (!ordered) break;
+#pragma unroll
+        for (int u = 0; u < kWgProducts; ++u)
+          if (go[u]) {
+            dset[cell[u]] = 0x7fffffff;
+            pend[u] = false;
           }
-        }
+      }
+      if (ordered) {
+        // the last round's barrier has passed: free the cells before the
+        // next step inserts (uniform branch)
+#pragma unroll
+        for (int u = 0; u < kWgProducts; ++u)
+          if (at[u] >= 0) dset[at[u]] = kEmpty;
+        __syncthreads();
       }
     }
     __syncthreads();
   }
+  wg_publish_keys(ws, nnew, dmax, full, err);
   wg_sync_global();
+  return ws.cnt;
 }
-
 
 // Run sorting (see lds_sort_runs) on a device table, one thread per run.
 __device__ void wg_sort_runs(int32_t *keys, double *vals, int64_t alloc) {
@@ -1160,11 +1256,6 @@ __device__ void wg_sort_runs(int32_t *keys, double *vals, int64_t alloc) {
 // sorted in LDS (one thread per run), and its occupied slots are compacted
 // to the output.  Returns false, having written nothing final, when a run is
 // longer than the pad (the caller then sorts the runs in device memory).
-constexpr int kExtChunk = 2048, kExtPad = 256;
-struct ExtLds {
-  int32_t k[kExtChunk + kExtPad];
-  double v[kExtChunk + kExtPad];
-};
 
 __device__ bool wg_extract_chunked(const int32_t *keys, const double *vals, int64_t alloc, WgScratch &ws,
                                    ExtLds &xl, int32_t *out_col, double *out_val, int64_t lim) {
@@ -1201,18 +1292,23 @@ __device__ bool wg_extract_chunked(const int32_t *keys, const double *vals, int6
       }
     }
     __syncthreads();
-    for (int i0 = 0; i0 < end; i0 += kBlock) {
-      const int i = i0 + t;
-      const int32_t key = i < end ? xl.k[i] : kEmpty;
-      const int64_t occ = key != kEmpty ? 1 : 0;
-      int64_t tot;
-      const int64_t ex = block_exclusive_sum(occ, ws.wtot, &tot);
-      if (occ && run + ex < lim) {
-        if (out_val) put_c(out_col, out_val, run + ex, key, xl.v[i]);
-        else out_col[run + ex] = key;
+    // compaction with one scan: thread t takes kExtPer consecutive slots
+    constexpr int kExtPer = (kExtChunk + kExtPad + kBlock - 1) / kBlock;
+    const int b0 = t * kExtPer, b1 = min(b0 + kExtPer, end);
+    int64_t occ = 0;
+    for (int i = b0; i < b1; ++i) occ += xl.k[i] != kEmpty ? 1 : 0;
+    int64_t tot;
+    int64_t o = run + block_exclusive_sum(occ, ws.wtot, &tot);
+    for (int i = b0; i < b1; ++i) {
+      const int32_t key = xl.k[i];
+      if (key == kEmpty) continue;
+      if (o < lim) {
+        if (out_val) put_c(out_col, out_val, o, key, xl.v[i]);
+        else out_col[o] = key;
       }
-      run += tot;
+      ++o;
     }
+    run += tot;
     c0 += end;
     __syncthreads();
   }
@@ -2291,39 +2387,38 @@ __global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
     }
     RowHash hs{};
     if (work) hs = make_hash(lo, hi, slots, dense);
-    const int32_t n = work ? wg_global_keys(op, row, c0, c1, gkeys, alloc, hs, ws, MODE == kNumeric ? gvals : nullptr,
-                                            err)
-                           : 0;
+    int32_t n = 0;
+    if (work)
+      n = MODE == kNumeric ? wg_global_accumulate(op, row, c0, c1, gkeys, gvals, alloc, hs, ws, xl, p.fast != 0, err)
+                           : wg_global_keys(op, row, c0, c1, gkeys, alloc, hs, ws, err);
     int64_t *pp = slot >= 0 ? p.parts + slot * (kSplitParts + 1) : nullptr;
     if (MODE == kSymbolic) {
       if (threadIdx.x == 0) {
         if (!pp) {
           p.cnt[row] = n;
         } else {
-          __hip_atomic_store(pp + g, kPartDone | (int64_t)n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-          const int64_t done =
-              __hip_atomic_fetch_add(pp + kSplitParts, (int64_t)1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-          if (done == kSplitParts - 1) {
-            int64_t tot = 0;
-            for (int k = 0; k < kSplitParts; ++k)
-              tot += __hip_atomic_load(pp + k, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) & kPartSize;
-            p.cnt[row] = (int32_t)tot;
-          }
+          // one word counts the finished parts (above kPartSize) and sums
+          // their sizes: the part that finishes last holds the row's size in
+          // what its own add returns.  Relaxed atomics: the payload is the
+          // word itself (an agent-scope release would write back the XCD's
+          // whole L2, which holds the tables of every other workgroup).
+          const int64_t before =
+              __hip_atomic_fetch_add(pp + kSplitParts, kPartDone + (int64_t)n, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+          if ((before >> 40) == kSplitParts - 1) p.cnt[row] = (int32_t)((before & kPartSize) + n);
         }
       }
     } else {
+      // the size travels in the flag word itself: relaxed atomics suffice
       if (threadIdx.x == 0 && pp)
-        __hip_atomic_store(pp + g, kPartDone | (int64_t)n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      // the extraction buffer is free until the extraction: it holds the
-      // ordered values' per-slot minima
-      if (work) wg_global_values(op, row, c0, c1, gkeys, gvals, alloc, hs, ws, xl.k, p.fast != 0);
+        __hip_atomic_store(pp + g, kPartDone | (int64_t)n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (threadIdx.x == 0) {
         int64_t pre = 0;
         if (pp) {
           for (int k = 0; k < g; ++k) {
             int64_t v = 0;
             for (int64_t polls = 0;; ++polls) {
-              v = __hip_atomic_load(pp + k, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+              v = __hip_atomic_load(pp + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               if (v & kPartDone) break;
               if (polls > kSpinLimit) {
                 atomicOr((unsigned long long *)err, (unsigned long long)kErrLookback);
