@@ -114,6 +114,12 @@ typedef struct spgemm_tuning {
     int32_t blocks_per_cu;   /* workgroups per compute unit of the workgroup-tier kernel   */
     float spill_ratio;       /* learned one pass: spill arena = ratio * summed capacities
                                 (at least 4096 entries), 0 < ratio <= 4; -1: no arena      */
+    int32_t bitmap_cols;     /* workgroup tier: when B has at most this many columns
+                                (<= 1,048,576), its rows keep a bitmap of their column
+                                region in LDS (Section IV-B's dense row, one bit per
+                                column) instead of a device table.  Opt-in (0 or -1:
+                                device tables, the default): this path is disabled
+                                pending a fault found in its first GPU run               */
 } spgemm_tuning;
 
 typedef struct spgemm_options {

@@ -100,6 +100,10 @@ spgemm_tuning default_tuning(const spgemm_csr *A, const spgemm_csr *B) {
   t.slack = 2;
   t.blocks_per_cu = 4;
   t.spill_ratio = 0.25f;
+  // the LDS bitmap path is opt-in: its first GPU run (a batched one pass
+  // with the learned sizer) ended in a memory violation whose cause has not
+  // been found; device tables stay the default
+  t.bitmap_cols = 0;
   return t;
 }
 
@@ -114,6 +118,7 @@ static void merge_tuning(spgemm_tuning *t, const spgemm_tuning *u) {
   if (u->slack) t->slack = u->slack;
   if (u->blocks_per_cu) t->blocks_per_cu = u->blocks_per_cu;
   if (u->spill_ratio) t->spill_ratio = u->spill_ratio < 0 ? 0.0f : u->spill_ratio;
+  if (u->bitmap_cols) t->bitmap_cols = u->bitmap_cols < 0 ? 0 : u->bitmap_cols;
 }
 
 static bool tuning_ok(const spgemm_tuning &t) {
@@ -122,7 +127,8 @@ static bool tuning_ok(const spgemm_tuning &t) {
   return t_ok && t.stage_slots >= 256 && t.stage_slots <= 8192 &&
          12 * ((int64_t)t.table_slots + t.stage_slots) <= 147456 && (t.merge_lists == 4 || t.merge_lists == 8) &&
          t.merge_max_nnz >= 0 && t.dense_ratio >= 0 && t.margin >= 0 && t.slack >= 0 && t.blocks_per_cu >= 1 &&
-         t.blocks_per_cu <= 16 && t.spill_ratio >= 0 && t.spill_ratio <= 4;
+         t.blocks_per_cu <= 16 && t.spill_ratio >= 0 && t.spill_ratio <= 4 && t.bitmap_cols >= 0 &&
+         t.bitmap_cols <= kBitmapMaxCols;
 }
 
 spgemm_status check_csr(const spgemm_csr *M, bool need_val) {
@@ -155,6 +161,7 @@ struct spgemm_plan {
   int64_t scratch_slots;   // per workgroup, current sizing
   int64_t scratch_slots_plan;
   int64_t scratch_rows;    // rows that may need a workgroup-tier table (plan sizing)
+  int32_t bitmap_words;    // > 0: workgroup-tier rows use the LDS bitmap of B's columns
   int64_t pad_total;       // one pass: entries of the padded buffer (sum of capacities)
   int64_t spill_cap;       // one pass, learned: entries of the spill arena after it
   int table_launch;        // LDS table slots of the wave-tile launch
@@ -302,7 +309,8 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   p->ntiles = mode == kSymbolic ? (R + 63) / 64 : h[kCtrTiles];
   p->nbig = h[kCtrGlobal];
   p->esc_rows = mode != kSymbolic ? h[kCtrEsc] : 0;
-  p->scratch_slots = (h[kCtrScratch] + 1) & ~(int64_t)1;
+  // the bitmap kernel needs no device tables
+  p->scratch_slots = p->bitmap_words > 0 ? 0 : (h[kCtrScratch] + 1) & ~(int64_t)1;
   p->scratch_rows = h[kCtrScratchRows];
   p->table_launch = (int)h[kCtrTable];
   // staging: every row of a one-pass tile; merge rows only in the numeric pass
@@ -420,6 +428,14 @@ static spgemm_status run_big(spgemm_plan *p, int mode, bool overflow_list, void 
   // the exact path after a one pass are not)
   bp.split = overflow_list ? 0 : 1;
   bp.parts = p->pa.parts;
+  bp.bitmap_words = p->bitmap_words;
+  if (p->bitmap_words > 0) {
+    // as many workgroups as the compute units hold with this window (the
+    // static LDS of a workgroup is under 8 KB)
+    const size_t lds = bitmap_lds_bytes(p->bitmap_words, mode == kSymbolic ? kSymbolic : kNumeric) + 8192;
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)(163840 / lds)));
+    bp.grid_bitmap = (int32_t)std::min<int64_t>((int64_t)device_cus() * per_cu, nrows);
+  }
   int64_t g = (int64_t)device_cus() * p->tune.blocks_per_cu;
   g = std::min(g, nrows * (bp.split ? kSplitParts : 1));
   if (per > 0) g = std::min<int64_t>(g, (int64_t)((scratch_bytes - off) / per));
@@ -571,6 +587,13 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   p->opts = *opts;
   p->opts.tuning = nullptr;
   p->tune = tune;
+  p->bitmap_words = (tune.bitmap_cols > 0 && B->cols > 0 && B->cols <= tune.bitmap_cols)
+                        ? (int32_t)((B->cols + 31) / 32)
+                        : 0;
+  if (p->bitmap_words > 0 && bitmap_kernels_prepare() != hipSuccess) {
+    free(p);
+    return SPGEMM_E_HIP;
+  }
   p->model = opts->model;
   p->ws = static_cast<char *>(workspace);
   p->ws_bytes = workspace_bytes;

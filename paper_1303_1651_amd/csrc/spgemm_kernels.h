@@ -193,7 +193,19 @@ struct BigParams {
   int64_t *parts;           // per split row: kSplitParts words (done flag |
                             // part size) and a finished-parts counter; cleared
                             // by the launcher
+  int32_t bitmap_words;     // > 0: every listed row's columns fit a window of
+                            // 32 * bitmap_words columns, and the rows take the
+                            // LDS bitmap kernel (k_bitmap) instead of k_big
+  int32_t grid_bitmap;      // workgroups of that kernel
 };
+
+// Workgroup-tier rows by a bitmap of the row's column window in LDS: B's
+// column count at most kBitmapMaxCols (128 KB of bits, plus the rank groups
+// and the step set: within one compute unit's 160 KB).
+constexpr int32_t kBitmapMaxCols = 1 << 20;
+constexpr int kBitmapGroup = 8;   // words per rank group
+size_t bitmap_lds_bytes(int32_t words, int mode);
+hipError_t bitmap_kernels_prepare();
 
 // Per row i of A: entries of the row (m), multiplication count (ub: the
 // paper's estimate of Section IV-B taken per row), the longest selected B

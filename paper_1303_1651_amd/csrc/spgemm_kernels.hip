@@ -11,6 +11,7 @@
 // whose rows all take the row-per-thread merge run k_wave_merge instead
 // (its one pass: a decoupled look-back over waves).
 #include <algorithm>
+#include <mutex>
 
 #include "device_common.h"
 #include "spgemm_kernels.h"
@@ -1081,16 +1082,86 @@ __device__ int32_t wg_global_keys(const Operands &op, int64_t row, int32_t c0, i
   return ws.cnt;
 }
 
+// One step's products applied in A's order.  `apply(go)` updates the
+// targets of the products with go[u] set, whose columns are distinct, and
+// waits for its stores; a barrier follows.  Columns that repeat within the
+// step are found through the LDS set `dset` (kDupSlots cells, kEmpty between
+// steps); such a step applies in rounds, in each of which the lowest-indexed
+// pending product of every column applies (the minimum kept in the column's
+// cell, INT32_MAX between rounds): as many rounds as the step's largest
+// repeat count.  Every target thus receives its products in A's order.
+template <typename Apply>
+__device__ __forceinline__ void wg_apply_in_order(int32_t *dset, const bool *live, const int32_t *j, Apply apply) {
+  const int t = threadIdx.x;
+  int32_t cell[kWgProducts], at[kWgProducts];
+  bool dup = false;
+#pragma unroll
+  for (int u = 0; u < kWgProducts; ++u) {
+    at[u] = -1;
+    cell[u] = 0;
+    if (!live[u]) continue;
+    uint32_t h = ((uint32_t)j[u] * 0x9E3779B1u) >> (32 - kDupBits);
+    while (true) {
+      const int32_t o = atomicCAS(&dset[h], kEmpty, j[u]);
+      if (o == kEmpty) {
+        at[u] = (int32_t)h;
+        break;
+      }
+      if (o == j[u]) {
+        dup = true;
+        break;
+      }
+      h = (h + 1) & (kDupSlots - 1);
+    }
+    cell[u] = (int32_t)h;
+  }
+  const bool ordered = __syncthreads_or(dup ? 1 : 0) != 0;
+  // the set's cells of this step's columns: free again, or (ordered) the
+  // columns' round minima
+#pragma unroll
+  for (int u = 0; u < kWgProducts; ++u)
+    if (at[u] >= 0) dset[at[u]] = ordered ? 0x7fffffff : kEmpty;
+  if (!ordered) {
+    apply(live);
+    __syncthreads();
+    return;
+  }
+  bool pend[kWgProducts];
+#pragma unroll
+  for (int u = 0; u < kWgProducts; ++u) pend[u] = live[u];
+  while (true) {
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < kWgProducts; ++u) any |= pend[u];
+    if (!__syncthreads_or(any ? 1 : 0)) break;
+#pragma unroll
+    for (int u = 0; u < kWgProducts; ++u)
+      if (pend[u]) atomicMin(&dset[cell[u]], u * kBlock + t);
+    __syncthreads();
+    bool go[kWgProducts];
+#pragma unroll
+    for (int u = 0; u < kWgProducts; ++u) go[u] = pend[u] && dset[cell[u]] == u * kBlock + t;
+    apply(go);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kWgProducts; ++u)
+      if (go[u]) {
+        dset[cell[u]] = 0x7fffffff;
+        pend[u] = false;
+      }
+  }
+  // the last round's barrier has passed: free the cells before the next
+  // step inserts
+#pragma unroll
+  for (int u = 0; u < kWgProducts; ++u)
+    if (at[u] >= 0) dset[at[u]] = kEmpty;
+  __syncthreads();
+}
+
 // Numeric pass of a workgroup-tier row (or of a column range): keys and
-// values in one sweep over the products, in A's order.  A step whose
-// columns are distinct (checked through an LDS set of its columns) inserts
-// its keys and updates their slots at once: a slot claimed by the step
-// starts at +0.0 + a*b, one claimed earlier adds a*b to what the earlier
-// steps left (their stores have completed before this step reads).  A step
-// where a column repeats applies in rounds, in each of which the
-// lowest-indexed pending product of every column inserts and updates (an
-// LDS minimum per column, kept in the column's cell of the set, INT32_MAX
-// between rounds): as many rounds as the step's largest repeat count.  So every entry of C sums its
+// values in one sweep over the products, in A's order (wg_apply_in_order):
+// a slot claimed by a product starts at +0.0 + a*b, one claimed earlier
+// adds a*b to what the earlier products left, so every entry of C sums its
 // products in A's column order, as the row-major kernel does (Section
 // IV-A).  Fast: every product at once, atomic adds into slots cleared to
 // +0.0 (the summation order is then not fixed).  Returns the row's size.
@@ -1131,66 +1202,17 @@ __device__ int32_t wg_global_accumulate(const Operands &op, int64_t row, int32_t
         for (int u = 0; u < kWgProducts; ++u) {
           nnew += fresh[u] ? 1 : 0;
           if (live[u] && !full) {
-            double p;
+            double pr;
             {
 #pragma clang fp contract(off)
-              p = a[u] * b[u];
+              pr = a[u] * b[u];
             }
-            atomicAdd(&vals[slot[u]], p);
+            atomicAdd(&vals[slot[u]], pr);
           }
         }
         continue;
       }
-      // does a column repeat within the step?
-      int32_t cell[kWgProducts], at[kWgProducts];
-      bool dup = false;
-#pragma unroll
-      for (int u = 0; u < kWgProducts; ++u) {
-        at[u] = -1;
-        cell[u] = 0;
-        if (!live[u]) continue;
-        uint32_t h = ((uint32_t)j[u] * 0x9E3779B1u) >> (32 - kDupBits);
-        while (true) {
-          const int32_t o = atomicCAS(&dset[h], kEmpty, j[u]);
-          if (o == kEmpty) {
-            at[u] = (int32_t)h;
-            break;
-          }
-          if (o == j[u]) {
-            dup = true;
-            break;
-          }
-          h = (h + 1) & (kDupSlots - 1);
-        }
-        cell[u] = (int32_t)h;
-      }
-      const bool ordered = __syncthreads_or(dup ? 1 : 0) != 0;
-      // the set's cells of this step's columns: free again, or (ordered)
-      // the columns' round minima
-#pragma unroll
-      for (int u = 0; u < kWgProducts; ++u)
-        if (at[u] >= 0) dset[at[u]] = ordered ? 0x7fffffff : kEmpty;
-      bool pend[kWgProducts];
-#pragma unroll
-      for (int u = 0; u < kWgProducts; ++u) pend[u] = live[u];
-      while (true) {
-        bool go[kWgProducts];
-        if (ordered) {
-          // the first pending product of every column applies
-          bool any = false;
-#pragma unroll
-          for (int u = 0; u < kWgProducts; ++u) any |= pend[u];
-          if (!__syncthreads_or(any ? 1 : 0)) break;
-#pragma unroll
-          for (int u = 0; u < kWgProducts; ++u)
-            if (pend[u]) atomicMin(&dset[cell[u]], u * kBlock + t);
-          __syncthreads();
-#pragma unroll
-          for (int u = 0; u < kWgProducts; ++u) go[u] = pend[u] && dset[cell[u]] == u * kBlock + t;
-        } else {
-#pragma unroll
-          for (int u = 0; u < kWgProducts; ++u) go[u] = pend[u];
-        }
+      wg_apply_in_order(dset, live, j, [&](const bool *go) {
         global_insert_n(keys, alloc, hs, j, go, slot, fresh, dmax, full);
         double old[kWgProducts];
 #pragma unroll
@@ -1202,23 +1224,7 @@ __device__ int32_t wg_global_accumulate(const Operands &op, int64_t row, int32_t
           gstored(vals + slot[u], fresh[u] ? first_add_rn(a[u], b[u]) : mul_add_rn(old[u], a[u], b[u]));
         }
         wave_mem_wait();
-        __syncthreads();
-        if (!ordered) break;
-#pragma unroll
-        for (int u = 0; u < kWgProducts; ++u)
-          if (go[u]) {
-            dset[cell[u]] = 0x7fffffff;
-            pend[u] = false;
-          }
-      }
-      if (ordered) {
-        // the last round's barrier has passed: free the cells before the
-        // next step inserts (uniform branch)
-#pragma unroll
-        for (int u = 0; u < kWgProducts; ++u)
-          if (at[u] >= 0) dset[at[u]] = kEmpty;
-        __syncthreads();
-      }
+      });
     }
     __syncthreads();
   }
@@ -2446,6 +2452,219 @@ __global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
 }
 
 
+// ============================================ workgroup tier: bitmap window
+// The paper's MinMax store keeps a dense temporary row over the column
+// region [lo, hi] of the row (Section IV-B).  On the GPU that region lives
+// in a workgroup's LDS as one bit per column (a 2^20-column region is
+// 128 KB), with a running count per group of kBitmapGroup words.
+//   counting pass: every product sets its column's bit; the row's size is
+//     the number of bits it set first.
+//   numeric pass: the bits are set again and their ranks (the count of set
+//     bits before each) summed per group; the row's columns are written to C
+//     in order, its values cleared to +0.0, and every product adds a*b into
+//     the value at its column's rank, the products in A's order
+//     (wg_apply_in_order), i.e. exactly the accumulation of the row-major
+//     kernel (Section IV-A) into C itself: no table, no sort.
+// Dynamic LDS: the window's words, then (numeric) the group counts and the
+// step set.
+__host__ __device__ inline int32_t bitmap_groups(int32_t words) { return (words + kBitmapGroup - 1) / kBitmapGroup; }
+size_t bitmap_lds_bytes(int32_t words, int mode) {
+  size_t b = (size_t)words * 4;
+  if (mode == kNumeric) b += (size_t)bitmap_groups(words) * 4 + (size_t)kDupSlots * 4;
+  return b;
+}
+
+// Rank of window position x: set bits before it.
+__device__ __forceinline__ int32_t bm_rank(const uint32_t *bm, const int32_t *pre, int32_t x) {
+  const int32_t w = x >> 5;
+  int32_t r = pre[w / kBitmapGroup];
+  for (int32_t k = w & ~(kBitmapGroup - 1); k < w; ++k) r += __popc(bm[k]);
+  return r + __popc(bm[w] & ((1u << (x & 31)) - 1u));
+}
+
+// Sets the bits of the row's products' columns; returns (through ws.cnt
+// after the closing barrier) the number of bits set first.
+__device__ int32_t wg_bitmap_fill(const Operands &op, int64_t row, int32_t lo, int32_t nw, uint32_t *bm,
+                                  WgScratch &ws) {
+  for (int32_t w = threadIdx.x; w < nw; w += kBlock) bm[w] = 0u;
+  if (threadIdx.x == 0) ws.cnt = 0;
+  __syncthreads();
+  int32_t nnew = 0;
+  const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
+  for (int64_t eb = as; eb < ae; eb += kBlock) {
+    const int64_t tot = wg_stage_entries(op, eb, ae, 0, -1, ws, false);
+    for (int64_t q0 = 0; q0 < tot; q0 += kWgChunk) {
+      int64_t bpos[kWgProducts];
+      double av[kWgProducts];
+      bool live[kWgProducts];
+      int32_t j[kWgProducts];
+      wg_step_products(ws, q0, tot, bpos, av, live);
+#pragma unroll
+      for (int u = 0; u < kWgProducts; ++u) j[u] = live[u] ? op.b_col[bpos[u]] - lo : 0;
+#pragma unroll
+      for (int u = 0; u < kWgProducts; ++u) {
+        if (!live[u]) continue;
+        const uint32_t bit = 1u << (j[u] & 31);
+        nnew += (atomicOr(&bm[j[u] >> 5], bit) & bit) ? 0 : 1;
+      }
+    }
+    __syncthreads();
+  }
+  const int32_t wn = (int32_t)wave_sum((int64_t)nnew);
+  if (lane_id() == 0 && wn) atomicAdd(&ws.cnt, wn);
+  __syncthreads();
+  return ws.cnt;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_bitmap(BigParams p);
+
+// Windows above 64 KB of dynamic LDS: raises both kernels' limit to the
+// largest window (within a compute unit's 160 KB with the static part), once
+// per device, outside any stream capture (the plan calls it).
+hipError_t bitmap_kernels_prepare() {
+  static std::mutex mu;
+  static bool raised[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev >= 0 && dev < 64 && raised[dev]) return hipSuccess;
+  const int most = (int)bitmap_lds_bytes(kBitmapMaxCols / 32, kNumeric);
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_bitmap<kSymbolic>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, most);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_bitmap<kNumeric>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, most);
+  if (e == hipSuccess && dev >= 0 && dev < 64) raised[dev] = true;
+  return e;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_bitmap(BigParams p) {
+  __shared__ WgScratch ws;
+  extern __shared__ uint32_t bm_lds[];
+  const int32_t W = p.bitmap_words;
+  uint32_t *bm = bm_lds;
+  int32_t *pre = reinterpret_cast<int32_t *>(bm_lds + W);
+  int32_t *dset = pre + bitmap_groups(W);
+  const Operands &op = p.op;
+  const int t = threadIdx.x;
+  const int64_t nbig = p.counters[p.count_ctr];
+  const int64_t nh = p.huge_ctr >= 0 ? p.counters[p.huge_ctr] : nbig;
+  int64_t *err = p.counters + kCtrError;
+  if (MODE == kNumeric)
+    for (int q = t; q < kDupSlots; q += kBlock) dset[q] = kEmpty;
+  __shared__ int64_t s_i;
+  while (true) {
+    if (t == 0) s_i = (int64_t)atomicAdd((unsigned long long *)&p.counters[kCtrBigTicket], 1ull);
+    __syncthreads();
+    const int64_t i = s_i;
+    __syncthreads();
+    if (i >= nbig) break;
+    const int64_t row = i < nh ? p.list[i] : p.list[p.list_len - 1 - (i - nh)];
+    const int32_t lo = p.lo[row];
+    const int64_t nw64 = (((int64_t)p.hi[row] - lo) >> 5) + 1;
+    if (p.hi[row] < lo || nw64 > W) {
+      // not a window this launch holds (the host sizes it by B's columns)
+      if (t == 0) atomicOr((unsigned long long *)err, (unsigned long long)kErrScratch);
+      continue;
+    }
+    const int32_t nw = (int32_t)nw64;
+    const int32_t n = wg_bitmap_fill(op, row, lo, nw, bm, ws);
+    if (MODE == kSymbolic) {
+      if (t == 0) p.cnt[row] = n;
+      continue;
+    }
+    const int64_t c = p.cnt[row];
+    const int64_t o = p.c_rp[row];
+    const int64_t lim = max((int64_t)0, min((int64_t)n, p.c_capacity - o));
+    if (t == 0 && n != c) atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
+    if (t == 0 && lim < n) atomicOr((unsigned long long *)err, (unsigned long long)kErrCapacity);
+    // group counts, then their exclusive sums: thread t takes a run of groups
+    const int32_t ng = bitmap_groups(nw);
+    const int32_t per = (ng + kBlock - 1) / kBlock, g0 = min(t * per, ng), g1 = min(g0 + per, ng);
+    int64_t mine = 0;
+    for (int32_t g = g0; g < g1; ++g) {
+      int32_t sg = 0;
+      for (int32_t w = g * kBitmapGroup; w < min((g + 1) * kBitmapGroup, nw); ++w) sg += __popc(bm[w]);
+      pre[g] = sg;
+      mine += sg;
+    }
+    int64_t tot;
+    int64_t run = block_exclusive_sum(mine, ws.wtot, &tot);
+    for (int32_t g = g0; g < g1; ++g) {
+      const int32_t sg = pre[g];
+      pre[g] = (int32_t)run;
+      run += sg;
+    }
+    __syncthreads();
+    // the row's columns into C in order, their values cleared to +0.0
+    int32_t *ccol = p.c_col + o;
+    double *cval = p.c_val + o;
+    for (int32_t w = t; w < nw; w += kBlock) {
+      uint32_t x = bm[w];
+      if (!x) continue;
+      int32_t r = bm_rank(bm, pre, w << 5);
+      while (x) {
+        const int b = __builtin_ctz(x);
+        x &= x - 1;
+        if (r < lim) {
+          ccol[r] = lo + (w << 5) + b;
+          gstored(cval + r, 0.0);
+        }
+        ++r;
+      }
+    }
+    wave_mem_wait();
+    wg_sync_global();
+    // values in A's order into the value at each column's rank
+    const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
+    for (int64_t eb = as; eb < ae; eb += kBlock) {
+      const int64_t tot2 = wg_stage_entries(op, eb, ae, 0, -1, ws, true);
+      for (int64_t q0 = 0; q0 < tot2; q0 += kWgChunk) {
+        int64_t bpos[kWgProducts];
+        double a[kWgProducts], b[kWgProducts];
+        bool live[kWgProducts];
+        int32_t j[kWgProducts], r[kWgProducts];
+        wg_step_products(ws, q0, tot2, bpos, a, live);
+#pragma unroll
+        for (int u = 0; u < kWgProducts; ++u) {
+          j[u] = live[u] ? op.b_col[bpos[u]] : 0;
+          b[u] = live[u] ? op.b_val[bpos[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kWgProducts; ++u) r[u] = live[u] ? bm_rank(bm, pre, j[u] - lo) : 0;
+        if (p.fast) {
+#pragma unroll
+          for (int u = 0; u < kWgProducts; ++u) {
+            if (!live[u] || r[u] >= lim) continue;
+            double pr;
+            {
+#pragma clang fp contract(off)
+              pr = a[u] * b[u];
+            }
+            atomicAdd(cval + r[u], pr);
+          }
+          continue;
+        }
+        wg_apply_in_order(dset, live, j, [&](const bool *go) {
+          double old[kWgProducts];
+#pragma unroll
+          for (int u = 0; u < kWgProducts; ++u) old[u] = (go[u] && r[u] < lim) ? gloadd(cval + r[u]) : 0.0;
+#pragma unroll
+          for (int u = 0; u < kWgProducts; ++u)
+            if (go[u] && r[u] < lim) gstored(cval + r[u], mul_add_rn(old[u], a[u], b[u]));
+          wave_mem_wait();
+        });
+      }
+      __syncthreads();
+    }
+    wave_mem_wait();
+    __syncthreads();
+  }
+}
+
 // ===================================================== register-merge rows
 // Matrices whose every row is a register-merge row need no tiles and no
 // workgroup barriers: one thread per row, 64 consecutive rows per wave.
@@ -2639,6 +2858,15 @@ hipError_t launch_big_rows(const BigParams &bp, int mode, int grid, hipStream_t 
   if (bp.split) {
     e = launch_fill_i64(bp.parts, 0, kMaxSplitRows * (kSplitParts + 1), s);
     if (e != hipSuccess) return e;
+  }
+  if (bp.bitmap_words > 0) {
+    const size_t lds = bitmap_lds_bytes(bp.bitmap_words, mode == kSymbolic ? kSymbolic : kNumeric);
+
+    if (mode == kSymbolic)
+      hipLaunchKernelGGL(k_bitmap<kSymbolic>, dim3(bp.grid_bitmap), dim3(kBlock), lds, s, bp);
+    else
+      hipLaunchKernelGGL(k_bitmap<kNumeric>, dim3(bp.grid_bitmap), dim3(kBlock), lds, s, bp);
+    return hipGetLastError();
   }
   if (mode == kSymbolic) hipLaunchKernelGGL(k_big<kSymbolic>, dim3(grid), dim3(kBlock), 0, s, bp);
   else hipLaunchKernelGGL(k_big<kNumeric>, dim3(grid), dim3(kBlock), 0, s, bp);

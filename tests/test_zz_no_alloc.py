@@ -14,12 +14,12 @@ from tests.gpu_util import assert_bit_exact
 pytestmark = pytest.mark.gpu
 
 
-def _product_both_ways(A, B, sizer):
+def _product_both_ways(A, B, sizer, tuning=None):
     import paper_1303_1651_amd as P
     import torch
     dA = P.DeviceCSR.from_host(A)
     dB = dA if B is A else P.DeviceCSR.from_host(B)
-    plan = P.Plan(dA, dB, sizer)
+    plan = P.Plan(dA, dB, sizer, tuning=tuning)
     dev = dA.row_ptr.device
     if sizer == "exact":
         rp, nnz = plan.symbolic()
