@@ -5,7 +5,10 @@ Default workload (the roofline study): the five-point Laplacian on a
 exactly 16 distinct uniform columns per row and values U(-1, 1) times an
 independent matrix drawn the same way.  One step is one full product of
 each on the plain two-pass path (plan, symbolic pass, scan, numeric pass);
-inputs are resident in HBM before the timed region.  Other workloads:
+inputs are resident in HBM before the timed region.  Before timing, the
+library's autotuner picks each product's tier thresholds and tile shapes
+(kept only when the whole product beats the default tuning; both times are
+reported; --no-autotune times the defaults).  Other workloads:
 --workload zipf (power-law rows, N = 2^20, the learned-sizer study), st9,
 st27, batched.
 
@@ -123,9 +126,12 @@ class Product:
         self.P, self.torch = P, torch
         self.name, self.A, self.B, self.dA, self.dB = name, A, B, dA, dB
         self.out = {}
+        self.tuning = None   # the autotuner's choice, when it beat the defaults
 
     def run(self, sizer, model, tuning=None):
         P, torch = self.P, self.torch
+        if tuning is None:
+            tuning = self.tuning
         plan = P.Plan(self.dA, self.dB, sizer, model, timing=True, tuning=tuning)
         dev = self.dA.row_ptr.device
         sym_ms = 0.0
@@ -558,6 +564,8 @@ def main():
     ap.add_argument("--sizer", default="exact", choices=["learned", "upper_bound", "exact"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other sizers")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default tuning block instead of the autotuner's choice")
     ap.add_argument("--workload", default="roofline",
                     choices=["roofline", "stencil", "random", "zipf", "st9", "st27", "batched", "fill"])
     ap.add_argument("--fill-max", type=int, default=196608, help="largest N of the 0.1%%-fill sweep")
@@ -634,6 +642,25 @@ def main():
         t0 = time.time()
         model, train_info = train_sizer(P, torch, args.workload)
         train_info["seconds"] = round(time.time() - t0, 2)
+
+    tuned = {}
+    if not args.no_autotune:
+        # thresholds and tile shapes picked per workload by the library's
+        # autotuner (row-kernel time of the exact path over its candidate
+        # grid), kept when the whole product is faster than with the defaults
+        from paper_1303_1651_amd.autotune import autotune
+        log("autotuning")
+        for p in products:
+            t0 = time.time()
+            cand = autotune(p.dA, p.dB, "exact", reps=2)
+            d_ms = time_product(torch, p, "exact", model, args.steps, tuning={})
+            t_ms = time_product(torch, p, "exact", model, args.steps, tuning=cand)
+            keep = t_ms < d_ms
+            if keep:
+                p.tuning = cand
+            tuned[p.name] = {"candidate": cand, "kept": keep, "product_ms_default_tuning": round(d_ms, 4),
+                             "product_ms_candidate": round(t_ms, 4), "seconds": round(time.time() - t0, 2)}
+            log("  %s: default %.3f ms, tuned %.3f ms (%s)" % (p.name, d_ms, t_ms, "kept" if keep else "dropped"))
 
     log("timed steps (%s)" % args.sizer)
     ms, wall_ms, per = time_steps(torch, products, args.sizer, model, args.steps, args.warmup)
@@ -754,6 +781,8 @@ def main():
         "wall_ms_per_step": round(wall_ms, 3),
         "workloads": details,
     }
+    if tuned:
+        out["autotuning"] = tuned
     if train_info:
         out["sizer_training"] = train_info
     if not args.no_cpu:
