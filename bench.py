@@ -394,8 +394,9 @@ def calibrate_copy(torch, nbytes=1 << 30):
 def pmc_summary(fetch_csv, write_csv, kernel_substr, copy_bytes, out_json, command):
     """Writes the traffic summary from two rocprofv3 --pmc runs (FETCH_SIZE,
     then WRITE_SIZE; counter_collection.csv files): per-dispatch KiB of the
-    kernel, scaled by what the same counters read for the calibration copy
-    (the largest device copy dispatch of the run, copy_bytes each way)."""
+    kernel, scaled by what the same counters read for the largest device copy
+    dispatch of the run (copy_bytes each way: the 2 GiB copies of the b_max
+    measurement)."""
     import csv
 
     def rows(path, counter):
@@ -585,7 +586,7 @@ def main():
         stats_summary(args.stats_summary[0], args.stats_summary[1], args.pmc_command)
         return
     if args.pmc_summary:
-        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_kernel, 1 << 30, args.pmc_summary[2],
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_kernel, 2 << 30, args.pmc_summary[2],
                     args.pmc_command)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
