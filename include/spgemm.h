@@ -120,6 +120,10 @@ typedef struct spgemm_tuning {
                                 column) instead of a device table.  Opt-in (0 or -1:
                                 device tables, the default): this path is disabled
                                 pending a fault found in its first GPU run               */
+    int32_t split_merge;     /* two-pass path: register-merge rows by the row-per-thread
+                                kernel and hashed rows by tiles without the merge lists,
+                                two launches each at its own occupancy (default); -1: one
+                                tile kernel for both                                      */
 } spgemm_tuning;
 
 typedef struct spgemm_options {

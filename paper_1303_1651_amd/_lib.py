@@ -45,7 +45,7 @@ class spgemm_tuning(ctypes.Structure):
     _fields_ = [("table_slots", I32), ("stage_slots", I32),
                 ("merge_max_nnz", I32), ("merge_lists", I32), ("dense_ratio", F32),
                 ("margin", F32), ("slack", I32), ("blocks_per_cu", I32),
-                ("spill_ratio", F32), ("bitmap_cols", I32)]
+                ("spill_ratio", F32), ("bitmap_cols", I32), ("split_merge", I32)]
 
 
 class spgemm_options(ctypes.Structure):

@@ -100,6 +100,7 @@ spgemm_tuning default_tuning(const spgemm_csr *A, const spgemm_csr *B) {
   t.slack = 2;
   t.blocks_per_cu = 4;
   t.spill_ratio = 0.25f;
+  t.split_merge = 1;
   // the LDS bitmap path is opt-in: its first GPU run (a batched one pass
   // with the learned sizer) ended in a memory violation whose cause has not
   // been found; device tables stay the default
@@ -119,6 +120,7 @@ static void merge_tuning(spgemm_tuning *t, const spgemm_tuning *u) {
   if (u->blocks_per_cu) t->blocks_per_cu = u->blocks_per_cu;
   if (u->spill_ratio) t->spill_ratio = u->spill_ratio < 0 ? 0.0f : u->spill_ratio;
   if (u->bitmap_cols) t->bitmap_cols = u->bitmap_cols < 0 ? 0 : u->bitmap_cols;
+  if (u->split_merge) t->split_merge = u->split_merge < 0 ? 0 : 1;
 }
 
 static bool tuning_ok(const spgemm_tuning &t) {
@@ -378,7 +380,18 @@ static spgemm_status run_wave(spgemm_plan *p, int mode, const double *a_val, con
   // a pass whose hashed rows are all expand-sort rows (and no merge rows)
   // runs the tile kernel without the table path (fewer registers)
   const bool esc_only = mode != kSymbolic && p->esc_rows > 0 && p->esc_rows == p->info.rows_hash;
-  HIPCK(p, launch_wave_tiles(wp, mode, p->tune.merge_lists, p->info.rows_merge > 0, esc_only, s));
+  bool has_merge = p->info.rows_merge > 0;
+  if (has_merge && mode != kOnePass && p->tune.split_merge > 0) {
+    // two-pass passes: the merge rows by the row-per-thread kernel at its own
+    // occupancy (first: a numeric wave that stages copies its whole range,
+    // which the tile and workgroup kernels then write their rows over), the
+    // hashed rows by tiles compiled without the merge lists
+    HIPCK(p, launch_wave_merge_tiered(wp.op, mode, p->tune.merge_lists, p->tune.stage_slots, p->pa.info, ctr(p),
+                                      p->pa.cnt, c_rp, c_col, c_val, c_capacity, s));
+    if (p->info.rows_hash == 0) return SPGEMM_OK;
+    has_merge = false;
+  }
+  HIPCK(p, launch_wave_tiles(wp, mode, p->tune.merge_lists, has_merge, esc_only && !has_merge, s));
   return SPGEMM_OK;
 }
 

@@ -206,6 +206,12 @@ constexpr int32_t kBitmapMaxCols = 1 << 20;
 constexpr int kBitmapGroup = 8;   // words per rank group
 size_t bitmap_lds_bytes(int32_t words, int mode);
 hipError_t bitmap_kernels_prepare();
+// Register-merge rows of a tiled counting or numeric pass (those whose tier
+// in `tiers` is the merge), by the row-per-thread kernel with merge_lists
+// (4 or 8) lists; numeric staging of `stage` entries per wave.
+hipError_t launch_wave_merge_tiered(const Operands &op, int mode, int merge_lists, int stage, const uint32_t *tiers,
+                                    int64_t *counters, int32_t *cnt_out, const int64_t *c_rp, int32_t *c_col,
+                                    double *c_val, int64_t c_capacity, hipStream_t s);
 
 // Per row i of A: entries of the row (m), multiplication count (ub: the
 // paper's estimate of Section IV-B taken per row), the longest selected B

@@ -2176,11 +2176,13 @@ k_wt(WaveTileParams p) {
       }
     }
 
+    // without MERGE, merge-tier rows are the row-per-thread kernel's
+    const bool own = valid && tier != kTierGlobal && (MERGE || tier != kTierMerge);
     if (MODE == kSymbolic) {
-      if (valid && tier != kTierGlobal) p.cnt_out[row] = (int32_t)n;
+      if (own) p.cnt_out[row] = (int32_t)n;
       continue;
     }
-    if (MODE == kNumeric && valid && tier != kTierGlobal && n != capr)
+    if (MODE == kNumeric && own && n != capr)
       atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
     if (lane == 0 && base + tile_len > p.c_capacity)
       atomicOr((unsigned long long *)err, (unsigned long long)kErrCapacity);
@@ -2688,10 +2690,14 @@ __host__ __device__ inline size_t wave_merge_lds(int mode, int stage) {
   return wave_merge_vals_offset(stage) + (size_t)kWavesPerBlock * stage * 8;
 }
 
+// tiers (not null): only the rows whose tier is the register merge are
+// merged (the other rows of a tiled pass are the tile and workgroup kernels';
+// a numeric wave that stages copies its whole range, and those kernels,
+// launched after it, write their rows over it); no partial sums.
 template <int M, int MODE>
 __global__ void __launch_bounds__(kBlock, M == 10 ? 3 : (M <= 8 ? 4 : 1))
 k_wave_merge(Operands op, int64_t *counters, int32_t *cnt_out, int64_t *partials, const int64_t *c_rp,
-             int32_t *c_col, double *c_val, int64_t c_capacity, int stage) {
+             int32_t *c_col, double *c_val, int64_t c_capacity, int stage, const uint32_t *tiers) {
   extern __shared__ __align__(16) unsigned char wm_lds[];
   const int l = lane_id();
   const int w = threadIdx.x / kWave;
@@ -2700,10 +2706,11 @@ k_wave_merge(Operands op, int64_t *counters, int32_t *cnt_out, int64_t *partials
     __shared__ int64_t s_part[2][kWavesPerBlock];
     const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int64_t n = 0, ub = 0;
-    if (row < op.rows) {
+    if (row < op.rows && (!tiers || info_tier(tiers[row]) == kTierMerge)) {
       n = merge_row<M, false>(op, row, nullptr, nullptr, 0, &ub);
       cnt_out[row] = (int32_t)n;
     }
+    if (tiers) return;
     const int64_t wu = wave_sum(ub), we = wave_sum(row < op.rows && ub == 0 ? 1 : 0);
     if (l == 0) {
       s_part[0][w] = wu;
@@ -2745,7 +2752,8 @@ k_wave_merge(Operands op, int64_t *counters, int32_t *cnt_out, int64_t *partials
   const int64_t o = valid ? c_rp[row] - base : 0;
   const int64_t n = valid ? c_rp[row + 1] - c_rp[row] : 0;
   const bool staged = tot <= stage;
-  if (staged && valid) {
+  const bool mine = valid && (!tiers || info_tier(tiers[row]) == kTierMerge);
+  if (staged && mine) {
     const int64_t got = merge_row<M, true>(op, row, scw + o, svw + o, n);
     if (got != n) atomicOr((unsigned long long *)&counters[kCtrError], (unsigned long long)kErrInconsistent);
   }
@@ -2754,7 +2762,7 @@ k_wave_merge(Operands op, int64_t *counters, int32_t *cnt_out, int64_t *partials
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   if (staged) {
     for (int64_t q = l; q < lim; q += kWave) put_c(c_col, c_val, base + q, scw[q], svw[q]);
-  } else if (valid) {
+  } else if (!staged && mine) {
     // the wave's output does not fit the staging: rows write their own entries
     const int64_t rl = max((int64_t)0, min(n, lim - o));
     const int64_t got = merge_row<M, true>(op, row, c_col + base + o, c_val + base + o, rl);
@@ -2765,7 +2773,7 @@ k_wave_merge(Operands op, int64_t *counters, int32_t *cnt_out, int64_t *partials
 template <int M, int MODE>
 static hipError_t launch_wave_merge_mm(const Operands &op, int stage, int64_t *counters, int32_t *cnt_out,
                                        int64_t *partials, const int64_t *c_rp, int32_t *c_col, double *c_val,
-                                       int64_t c_capacity, hipStream_t s) {
+                                       int64_t c_capacity, hipStream_t s, const uint32_t *tiers = nullptr) {
   const size_t lds = wave_merge_lds(MODE, stage);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wave_merge<M, MODE>),
@@ -2774,9 +2782,9 @@ static hipError_t launch_wave_merge_mm(const Operands &op, int stage, int64_t *c
   }
   const int64_t blocks = (op.rows + kBlock - 1) / kBlock;
   hipLaunchKernelGGL((k_wave_merge<M, MODE>), dim3((unsigned)blocks), dim3(kBlock), lds, s, op, counters, cnt_out,
-                     partials, c_rp, c_col, c_val, c_capacity, stage);
+                     partials, c_rp, c_col, c_val, c_capacity, stage, tiers);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || MODE != kSymbolic) return e;
+  if (e != hipSuccess || MODE != kSymbolic || tiers) return e;
   const int32_t dst[2] = {kCtrMults, kCtrEmpty};
   return launch_sum_partials(partials, blocks, 2, 2, dst, nullptr, counters, s);
 }
@@ -2807,6 +2815,27 @@ hipError_t launch_wave_merge(const Operands &op, int mode, int merge_lists, int 
     case 8: return launch_wave_merge_m<8>(op, mode, stage, counters, cnt_out, partials, c_rp, c_col, c_val, c_capacity, s);
     case 10: return launch_wave_merge_m<10>(op, mode, stage, counters, cnt_out, partials, c_rp, c_col, c_val, c_capacity, s);
     case 16: return launch_wave_merge_m<16>(op, mode, stage, counters, cnt_out, partials, c_rp, c_col, c_val, c_capacity, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_wave_merge_tiered(const Operands &op, int mode, int merge_lists, int stage, const uint32_t *tiers,
+                                    int64_t *counters, int32_t *cnt_out, const int64_t *c_rp, int32_t *c_col,
+                                    double *c_val, int64_t c_capacity, hipStream_t s) {
+  if (op.rows <= 0) return hipSuccess;
+  if (mode != kSymbolic && mode != kNumeric) return hipErrorInvalidValue;
+  const bool sym = mode == kSymbolic;
+  switch (merge_lists) {
+    case 4:
+      return sym ? launch_wave_merge_mm<4, kSymbolic>(op, 0, counters, cnt_out, nullptr, c_rp, c_col, c_val,
+                                                       c_capacity, s, tiers)
+                 : launch_wave_merge_mm<4, kNumeric>(op, stage, counters, cnt_out, nullptr, c_rp, c_col, c_val,
+                                                      c_capacity, s, tiers);
+    case 8:
+      return sym ? launch_wave_merge_mm<8, kSymbolic>(op, 0, counters, cnt_out, nullptr, c_rp, c_col, c_val,
+                                                       c_capacity, s, tiers)
+                 : launch_wave_merge_mm<8, kNumeric>(op, stage, counters, cnt_out, nullptr, c_rp, c_col, c_val,
+                                                      c_capacity, s, tiers);
     default: return hipErrorInvalidValue;
   }
 }
