@@ -291,6 +291,7 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   sp.stage_row_max = stage_row_max(p, mode);
   sp.merge_lists = p->tune.merge_lists;
   sp.merge_max = p->merge_off ? 0 : std::min(p->tune.merge_max_nnz, stage / 2);
+  sp.merge_apart = (mode == kNumeric && p->tune.split_merge > 0) ? 1 : 0;
   sp.dense_ratio = p->tune.dense_ratio;
   sp.margin = p->tune.margin;
   sp.slack = p->tune.slack;
@@ -334,8 +335,8 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
 // rows, say), the pass is sized again without staging hashed rows: they are
 // written straight to their place like the longer ones.
 static spgemm_status unstage_if_few(spgemm_plan *p, int mode, hipStream_t s) {
-  if (p->stage_off || p->info.rows_merge > 0 || p->staged_rows == 0 ||
-      p->staged_rows * kMergeFewRows >= p->A.rows)
+  if (p->stage_off || (p->info.rows_merge > 0 && !(mode == kNumeric && p->tune.split_merge > 0)) ||
+      p->staged_rows == 0 || p->staged_rows * kMergeFewRows >= p->A.rows)
     return SPGEMM_OK;
   p->stage_off = 1;
   return size_pass(p, mode, s);

@@ -99,6 +99,7 @@ struct SizeParams {
   int stage_row_max;    // kNumeric: hashed rows up to this size are staged
   int merge_lists;      // template M of the merge tier
   int merge_max;        // largest capacity the merge tier takes
+  int merge_apart;      // kNumeric: merge rows run in a launch of their own (not staged by tiles)
   float dense_ratio;
   float margin;
   int slack;

@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
       info = pack_info(kTierMerge, false, 0);
       if (!sym) {
         cost = max(min(c, HT), mincost);
-        staged = true;
+        staged = !sp.merge_apart;
       }
     } else {
       const int64_t span = (int64_t)pa.f.hi[i] - (int64_t)pa.f.lo[i] + 1;
