@@ -888,6 +888,7 @@ struct WgScratch {
   double av[kBlock];
   int64_t wtot[kWavesPerBlock + 1];
   int32_t cnt, dmax;
+  int32_t top;   // numeric: the highest slot a key was inserted at
   int64_t run;
   int32_t first;   // extraction: the end of a chunk
 };
@@ -1001,7 +1002,7 @@ __device__ __forceinline__ void wg_step_products(const WgScratch &ws, int64_t q0
 // leaves it; one that would sets *full (reported, never dropped silently).
 __device__ __forceinline__ void global_insert_n(int32_t *keys, int64_t alloc, const RowHash &hs, const int32_t *j,
                                                 const bool *go, int64_t *slot, bool *fresh, int32_t &dmax,
-                                                bool &full) {
+                                                bool &full, int32_t *top = nullptr) {
   int32_t old[kWgProducts];
 #pragma unroll
   for (int u = 0; u < kWgProducts; ++u) {
@@ -1035,15 +1036,22 @@ __device__ __forceinline__ void global_insert_n(int32_t *keys, int64_t alloc, co
     slot[u] = sl;
     dmax = max(dmax, (int32_t)(sl - h));
   }
+  if (top) {
+#pragma unroll
+    for (int u = 0; u < kWgProducts; ++u)
+      if (fresh[u]) *top = max(*top, (int32_t)slot[u]);
+  }
 }
 
 // Publishes a pass's distinct-key count and largest displacement to ws.
-__device__ __forceinline__ void wg_publish_keys(WgScratch &ws, int32_t nnew, int32_t dmax, bool full, int64_t *err) {
-  const int32_t wn = (int32_t)wave_sum((int64_t)nnew), wd = wave_max32(dmax);
+__device__ __forceinline__ void wg_publish_keys(WgScratch &ws, int32_t nnew, int32_t dmax, bool full, int64_t *err,
+                                                int32_t top = -1) {
+  const int32_t wn = (int32_t)wave_sum((int64_t)nnew), wd = wave_max32(dmax), wt = wave_max32(top);
   const bool wf = ballot(full) != 0;
   if (lane_id() == 0) {
     if (wn) atomicAdd(&ws.cnt, wn);
     if (wd) atomicMax(&ws.dmax, wd);
+    if (wt >= 0) atomicMax(&ws.top, wt);
     if (wf) atomicOr((unsigned long long *)err, (unsigned long long)kErrInconsistent);
   }
 }
@@ -1178,9 +1186,10 @@ __device__ int32_t wg_global_accumulate(const Operands &op, int64_t row, int32_t
   if (t == 0) {
     ws.cnt = 0;
     ws.dmax = 0;
+    ws.top = -1;
   }
   wg_sync_global();
-  int32_t nnew = 0, dmax = 0;
+  int32_t nnew = 0, dmax = 0, top = -1;
   bool full = false;
   const int64_t as = op.a_rp[row], ae = op.a_rp[row + 1];
   for (int64_t eb = as; eb < ae; eb += kBlock) {
@@ -1197,7 +1206,7 @@ __device__ int32_t wg_global_accumulate(const Operands &op, int64_t row, int32_t
         b[u] = live[u] ? op.b_val[bpos[u]] : 0.0;
       }
       if (fast) {
-        global_insert_n(keys, alloc, hs, j, live, slot, fresh, dmax, full);
+        global_insert_n(keys, alloc, hs, j, live, slot, fresh, dmax, full, &top);
 #pragma unroll
         for (int u = 0; u < kWgProducts; ++u) {
           nnew += fresh[u] ? 1 : 0;
@@ -1213,7 +1222,7 @@ __device__ int32_t wg_global_accumulate(const Operands &op, int64_t row, int32_t
         continue;
       }
       wg_apply_in_order(dset, live, j, [&](const bool *go) {
-        global_insert_n(keys, alloc, hs, j, go, slot, fresh, dmax, full);
+        global_insert_n(keys, alloc, hs, j, go, slot, fresh, dmax, full, &top);
         double old[kWgProducts];
 #pragma unroll
         for (int u = 0; u < kWgProducts; ++u) old[u] = (go[u] && !fresh[u] && !full) ? gloadd(vals + slot[u]) : 0.0;
@@ -1228,7 +1237,7 @@ __device__ int32_t wg_global_accumulate(const Operands &op, int64_t row, int32_t
     }
     __syncthreads();
   }
-  wg_publish_keys(ws, nnew, dmax, full, err);
+  wg_publish_keys(ws, nnew, dmax, full, err, top);
   wg_sync_global();
   return ws.cnt;
 }
@@ -1269,9 +1278,24 @@ __device__ bool wg_extract_chunked(const int32_t *keys, const double *vals, int6
   int64_t c0 = 0, run = 0;
   while (c0 < alloc) {
     const int n = (int)min((int64_t)(kExtChunk + kExtPad), alloc - c0);
-    for (int i = t; i < n; i += kBlock) {
-      xl.k[i] = gload(keys + c0 + i);
-      xl.v[i] = vals ? gloadd(vals + c0 + i) : 0.0;
+    // every load of the chunk in flight before the first is stored
+    constexpr int kLoadPer = (kExtChunk + kExtPad) / kBlock;
+    static_assert(kLoadPer * kBlock == kExtChunk + kExtPad, "chunk loads");
+    int32_t kk[kLoadPer];
+    double vv[kLoadPer];
+#pragma unroll
+    for (int u = 0; u < kLoadPer; ++u) {
+      const int i = t + u * kBlock;
+      kk[u] = i < n ? gload(keys + c0 + i) : kEmpty;
+      vv[u] = (vals && i < n) ? gloadd(vals + c0 + i) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadPer; ++u) {
+      const int i = t + u * kBlock;
+      if (i < n) {
+        xl.k[i] = kk[u];
+        xl.v[i] = vv[u];
+      }
     }
     if (t == 0) ws.first = n;
     __syncthreads();
@@ -2447,7 +2471,9 @@ __global__ void __launch_bounds__(kBlock) k_big(BigParams p) {
       const int64_t o = p.c_rp[row] + s_off;
       const int64_t lim = max((int64_t)0, min((int64_t)n, p.c_capacity - o));
       if (threadIdx.x == 0 && lim < n) atomicOr((unsigned long long *)err, (unsigned long long)kErrCapacity);
-      if (work) wg_global_extract(gkeys, gvals, alloc, ws.dmax, ws, xl, p.c_col + o, p.c_val + o, lim);
+      // the table holds no key above the highest slot one was inserted at
+      if (work) wg_global_extract(gkeys, gvals, min(alloc, (int64_t)ws.top + 1), ws.dmax, ws, xl, p.c_col + o,
+                                  p.c_val + o, lim);
     }
     __syncthreads();
   }
