@@ -859,6 +859,10 @@ __device__ int64_t merge_row(const Operands &op, int64_t row, int32_t *out_col, 
 __device__ __forceinline__ int32_t gload(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+// Two neighbouring keys (8-byte aligned) in one load.
+__device__ __forceinline__ uint64_t gload64(const int32_t *p) {
+  return __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 __device__ __forceinline__ double gloadd(const double *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -1000,6 +1004,7 @@ __device__ __forceinline__ void wg_step_products(const WgScratch &ws, int64_t q0
 // the thread's keys are issued together; a key displaced further probes on
 // one slot at a time.  The table has room for every product, so no probe
 // leaves it; one that would sets *full (reported, never dropped silently).
+template <bool GROUP>
 __device__ __forceinline__ void global_insert_n(int32_t *keys, int64_t alloc, const RowHash &hs, const int32_t *j,
                                                 const bool *go, int64_t *slot, bool *fresh, int32_t &dmax,
                                                 bool &full, int32_t *top = nullptr) {
@@ -1020,14 +1025,40 @@ __device__ __forceinline__ void global_insert_n(int32_t *keys, int64_t alloc, co
     if (old[u] == j[u]) continue;
     const int64_t h = slot[u];
     int64_t sl = h + 1;
-    while (sl < alloc) {
-      const int32_t o = gcas(&keys[sl], kEmpty, j[u]);
-      if (o == kEmpty) {
-        fresh[u] = true;
-        break;
+    bool done = false;
+    while (!done && sl < alloc) {
+      // the keys from slot sl to the end of its aligned group of four, read
+      // at once (a key once set never changes, so a stale read can only show
+      // a slot as empty, which the compare-and-swap then settles)
+      const int64_t g = GROUP ? sl & ~(int64_t)3 : sl;
+      int32_t kv[4];
+      if (!GROUP) {
+        kv[0] = kEmpty;   // one slot at a time: straight to the compare-and-swap
+      } else if (g + 4 <= alloc) {
+        const uint64_t w0 = gload64(keys + g), w1 = gload64(keys + g + 2);
+        kv[0] = (int32_t)(uint32_t)w0;
+        kv[1] = (int32_t)(uint32_t)(w0 >> 32);
+        kv[2] = (int32_t)(uint32_t)w1;
+        kv[3] = (int32_t)(uint32_t)(w1 >> 32);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) kv[q] = g + q < alloc ? gload(keys + g + q) : kEmpty;
       }
-      if (o == j[u]) break;
-      ++sl;
+      for (; sl < g + (GROUP ? 4 : 1) && sl < alloc; ++sl) {
+        int32_t kq = kv[sl - g];
+        if (kq == kEmpty) {
+          kq = gcas(&keys[sl], kEmpty, j[u]);
+          if (kq == kEmpty) {
+            fresh[u] = true;
+            done = true;
+            break;
+          }
+        }
+        if (kq == j[u]) {
+          done = true;
+          break;
+        }
+      }
     }
     if (sl >= alloc) {
       full = true;
@@ -1079,7 +1110,7 @@ __device__ int32_t wg_global_keys(const Operands &op, int64_t row, int32_t c0, i
       wg_step_products(ws, q0, tot, bpos, av, live);
 #pragma unroll
       for (int u = 0; u < kWgProducts; ++u) j[u] = live[u] ? op.b_col[bpos[u]] : 0;
-      global_insert_n(keys, alloc, hs, j, live, slot, fresh, dmax, full);
+      global_insert_n<true>(keys, alloc, hs, j, live, slot, fresh, dmax, full);
 #pragma unroll
       for (int u = 0; u < kWgProducts; ++u) nnew += fresh[u] ? 1 : 0;
     }
@@ -1206,7 +1237,7 @@ __device__ int32_t wg_global_accumulate(const Operands &op, int64_t row, int32_t
         b[u] = live[u] ? op.b_val[bpos[u]] : 0.0;
       }
       if (fast) {
-        global_insert_n(keys, alloc, hs, j, live, slot, fresh, dmax, full, &top);
+        global_insert_n<false>(keys, alloc, hs, j, live, slot, fresh, dmax, full, &top);
 #pragma unroll
         for (int u = 0; u < kWgProducts; ++u) {
           nnew += fresh[u] ? 1 : 0;
@@ -1222,7 +1253,7 @@ __device__ int32_t wg_global_accumulate(const Operands &op, int64_t row, int32_t
         continue;
       }
       wg_apply_in_order(dset, live, j, [&](const bool *go) {
-        global_insert_n(keys, alloc, hs, j, go, slot, fresh, dmax, full, &top);
+        global_insert_n<false>(keys, alloc, hs, j, go, slot, fresh, dmax, full, &top);
         double old[kWgProducts];
 #pragma unroll
         for (int u = 0; u < kWgProducts; ++u) old[u] = (go[u] && !fresh[u] && !full) ? gloadd(vals + slot[u]) : 0.0;
