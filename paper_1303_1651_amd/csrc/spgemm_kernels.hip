@@ -374,7 +374,7 @@ __device__ __forceinline__ int64_t global_table_bound(int64_t c, float ratio, in
 }
 
 constexpr int64_t kSortMax = 1024;   // keys a wave sorts in registers (64 lanes x 16)
-constexpr int64_t kEscMax = 512;    // products of an expand-sort row (64 lanes x 8)
+constexpr int64_t kEscMax = 1024;   // products of an expand-sort row (64 lanes x 16)
 constexpr int64_t kSortCountMax = 256;  // slots of a row counted by sorting (64 lanes x 4)
 
 // Smallest power of two >= x, at least kMinTable.
@@ -1849,7 +1849,8 @@ __device__ int32_t wave_esc_sort(const Operands &op, int64_t as, int64_t ae, int
   if (nl <= 64) wave_sort_buf<1>(buf, nl, n, from);
   else if (nl <= 128) wave_sort_buf<2>(buf, nl, n, from);
   else if (nl <= 256) wave_sort_buf<4>(buf, nl, n, from);
-  else wave_sort_buf<8>(buf, nl, n, from);   // nl <= T <= kEscMax
+  else if (nl <= 512) wave_sort_buf<8>(buf, nl, n, from);
+  else wave_sort_buf<16>(buf, nl, n, from);   // nl <= T <= kEscMax
   return n;
 }
 
