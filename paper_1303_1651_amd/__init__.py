@@ -127,7 +127,10 @@ class Model:
 
     def __del__(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
-            _lib.spgemm_model_destroy(self.handle)
+            try:
+                _lib.spgemm_model_destroy(self.handle)
+            except (AttributeError, TypeError):   # interpreter shutdown: module globals already cleared
+                pass
             self.handle = None
 
 
@@ -329,7 +332,10 @@ class Plan:
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except (AttributeError, TypeError):   # interpreter shutdown: module globals already cleared
+            pass
 
 
 def spgemm(A: DeviceCSR, B: DeviceCSR, sizer="exact", model: Model | None = None, fast=False,
@@ -460,4 +466,7 @@ class Batch:
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except (AttributeError, TypeError):   # interpreter shutdown: module globals already cleared
+            pass

@@ -164,6 +164,7 @@ struct spgemm_plan {
   int64_t scratch_slots_plan;
   int64_t scratch_rows;    // rows that may need a workgroup-tier table (plan sizing)
   int32_t bitmap_words;    // > 0: workgroup-tier rows use the LDS bitmap of B's columns
+  int64_t esc_big;         // numeric: expand-sort rows of more than kEscMaxSmall products
   int64_t pad_total;       // one pass: entries of the padded buffer (sum of capacities)
   int64_t spill_cap;       // one pass, learned: entries of the spill arena after it
   int table_launch;        // LDS table slots of the wave-tile launch
@@ -311,7 +312,10 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   if (h[kCtrError] & kErrLookback) return lookback_failed(p);
   p->ntiles = mode == kSymbolic ? (R + 63) / 64 : h[kCtrTiles];
   p->nbig = h[kCtrGlobal];
-  p->esc_rows = mode != kSymbolic ? h[kCtrEsc] : 0;
+  // expand-sort rows: their count, and above bit 32 those of more than
+  // kEscMaxSmall products (the numeric launch then sorts 16 keys per lane)
+  p->esc_rows = mode != kSymbolic ? (h[kCtrEsc] & 0xffffffffll) : 0;
+  p->esc_big = mode == kNumeric ? (h[kCtrEsc] >> 32) : 0;
   // the bitmap kernel needs no device tables
   p->scratch_slots = p->bitmap_words > 0 ? 0 : (h[kCtrScratch] + 1) & ~(int64_t)1;
   p->scratch_rows = h[kCtrScratchRows];
@@ -392,7 +396,8 @@ static spgemm_status run_wave(spgemm_plan *p, int mode, const double *a_val, con
     if (p->info.rows_hash == 0) return SPGEMM_OK;
     has_merge = false;
   }
-  HIPCK(p, launch_wave_tiles(wp, mode, p->tune.merge_lists, has_merge, esc_only && !has_merge, s));
+  HIPCK(p, launch_wave_tiles(wp, mode, p->tune.merge_lists, has_merge, esc_only && !has_merge,
+                             mode == kNumeric && p->esc_big > 0, s));
   return SPGEMM_OK;
 }
 

@@ -376,7 +376,7 @@ size_t wave_tile_lds(int mode, int table_slots, int stage_slots);
 // has_merge: some row of the pass takes the merge tier
 hipError_t launch_brow_ends(const Operands &op, Features f, hipStream_t s);
 hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, bool esc_only,
-                             hipStream_t s);
+                             bool esc_big, hipStream_t s);
 hipError_t launch_compact(const CompactParams &cp, hipStream_t s);
 hipError_t launch_big_rows(const BigParams &bp, int mode, int grid, hipStream_t s);
 hipError_t launch_sum_partials(const int64_t *partials, int64_t nblocks, int n, int stride, const int32_t *dst,

@@ -375,6 +375,7 @@ __device__ __forceinline__ int64_t global_table_bound(int64_t c, float ratio, in
 
 constexpr int64_t kSortMax = 1024;   // keys a wave sorts in registers (64 lanes x 16)
 constexpr int64_t kEscMax = 1024;   // products of an expand-sort row (64 lanes x 16)
+constexpr int64_t kEscMaxSmall = 512;  // ... in launches compiled without the 16-per-lane sort
 constexpr int64_t kSortCountMax = 256;  // slots of a row counted by sorting (64 lanes x 4)
 
 // Smallest power of two >= x, at least kMinTable.
@@ -472,7 +473,11 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
           T = te;
         }
       }
-      if (!dense && !sym && mx <= kWave && ub <= kEscMax && ub < op.b_cols && 4 * ub <= 5 * c) {
+      // rows of more than kEscMaxSmall products only where merge rows run
+      // apart: the tile launch is then a variant without the merge code, which
+      // has the registers for the 16-per-lane sort
+      if (!dense && !sym && mx <= kWave && ub <= (sp.merge_apart ? kEscMax : kEscMaxSmall) && ub < op.b_cols &&
+          4 * ub <= 5 * c) {
         const int64_t te = table_pow2(ub);
         if (te <= sp.table_max && (((int64_t)op.b_cols - pa.f.lo[i]) << __builtin_ctzll((uint64_t)te)) < ((int64_t)1 << 31)) {
           esc = true;
@@ -539,7 +544,8 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
   // sums, except the two maxima (scratch, tmax) at 6 and 7
   const int64_t want = scratch > 0 ? ((big && (int64_t)pa.f.ub[i] >= kSplitWork) ? kSplitParts : 1) : 0;
   int64_t v[kSizeParts] = {n_tier[kTierMerge], n_tier[kTierHash], n_tier[kTierEmpty], capsum, want,
-                           staged ? 1 : 0, scratch, tmax, esc_row ? 1 : 0};
+                           staged ? 1 : 0, scratch, tmax,
+                           esc_row ? 1 + ((int64_t)pa.f.ub[i] > kEscMaxSmall ? ((int64_t)1 << 32) : 0) : 0};
 #pragma unroll
   for (int j = 0; j < kSizeParts; ++j) {
     int64_t t = v[j];
@@ -1782,6 +1788,7 @@ constexpr int kEscSteps = 2;
 // products from +0.0 in that order, exactly the row-major kernel's
 // accumulation (Section IV-A).
 // wave_esc_sort: expands and sorts; returns the number of products.
+template <bool BIG>
 __device__ int32_t wave_esc_sort(const Operands &op, int64_t as, int64_t ae, int32_t maxb, int32_t lo, int32_t T,
                                  const RowEntries &re, int32_t *buf, double *pv) {
   const int lane = threadIdx.x;
@@ -1849,7 +1856,7 @@ __device__ int32_t wave_esc_sort(const Operands &op, int64_t as, int64_t ae, int
   if (nl <= 64) wave_sort_buf<1>(buf, nl, n, from);
   else if (nl <= 128) wave_sort_buf<2>(buf, nl, n, from);
   else if (nl <= 256) wave_sort_buf<4>(buf, nl, n, from);
-  else if (nl <= 512) wave_sort_buf<8>(buf, nl, n, from);
+  else if (!BIG || nl <= 512) wave_sort_buf<8>(buf, nl, n, from);   // !BIG: nl <= kEscMaxSmall
   else wave_sort_buf<16>(buf, nl, n, from);   // nl <= T <= kEscMax
   return n;
 }
@@ -1954,11 +1961,11 @@ __device__ int32_t wave_esc_emit(const int32_t *buf, const double *pv, int32_t n
 }
 
 // Expand, sort, combine and write (the numeric pass); returns the row's size.
-template <bool NT>
+template <bool NT, bool BIG>
 __device__ __forceinline__ int32_t wave_esc_row(const Operands &op, int64_t as, int64_t ae, int32_t maxb, int32_t lo,
                                                 int32_t T, const RowEntries &re, int32_t *buf, double *pv,
                                                 int32_t *ocol, double *oval, int64_t lim) {
-  const int32_t n = wave_esc_sort(op, as, ae, maxb, lo, T, re, buf, pv);
+  const int32_t n = wave_esc_sort<BIG>(op, as, ae, maxb, lo, T, re, buf, pv);
   return wave_esc_emit<true, NT>(buf, pv, n, lo, T, ocol, oval, lim);
 }
 
@@ -2052,7 +2059,9 @@ __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots,
 // table launches (the one pass spills a few registers there, which costs
 // less than the fourth wave gains: 24.0 -> 19.7 ms on the 27-point
 // product), fewer where the merge lists take registers.
-template <int MODE, int M, bool MERGE, bool ESCO = false>
+// BIG: expand-sort rows of up to kEscMax products (sorted 16 per lane);
+// launches without it take rows of at most kEscMaxSmall (fewer registers).
+template <int MODE, int M, bool MERGE, bool ESCO = false, bool BIG = false>
 __global__ void __launch_bounds__(kWave, ESCO ? 5
                                          : MODE == kSymbolic ? 7
                                          : (MODE == kOnePass ? (MERGE ? 2 : 4) : (MERGE && M == 8 ? 3 : 4)))
@@ -2142,7 +2151,7 @@ k_wt(WaveTileParams p) {
         if (MODE == kNumeric) {
           const int64_t o = base + __shfl(pos, r, kWave);
           const int64_t lim = max((int64_t)0, min((int64_t)cap_r, p.c_capacity - o));
-          const int32_t c = wave_esc_row<true>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], p.lo[hrow], T,
+          const int32_t c = wave_esc_row<true, BIG>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], p.lo[hrow], T,
                                                re, buf, tvals, p.c_col + o, p.c_val + o, lim);
           if (lane == r) {
             n = c;
@@ -2152,7 +2161,7 @@ k_wt(WaveTileParams p) {
         }
         // one pass: count first, then the place (the tile's range or the
         // spill arena, as for a hashed row), then write
-        const int32_t np = wave_esc_sort(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], p.lo[hrow], T, re, buf,
+        const int32_t np = wave_esc_sort<false>(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], p.lo[hrow], T, re, buf,
                                          tvals);
         const int32_t c = wave_esc_emit<false, false>(buf, tvals, np, p.lo[hrow], T, nullptr, nullptr, 0);
         bool keep = (int64_t)mtot + hsum + c <= tile_len, spill = false;
@@ -2902,16 +2911,16 @@ size_t wave_tile_lds(int mode, int table_slots, int stage_slots) {
   return wave_lds_layout(mode != kSymbolic, table_slots, stage_slots).total;
 }
 
-template <int MODE, int M, bool MERGE, bool ESCO = false>
+template <int MODE, int M, bool MERGE, bool ESCO = false, bool BIG = false>
 static hipError_t launch_wt_mm(const WaveTileParams &wp, size_t lds, hipStream_t s) {
-  const void *fn = reinterpret_cast<const void *>(&k_wt<MODE, M, MERGE, ESCO>);
+  const void *fn = reinterpret_cast<const void *>(&k_wt<MODE, M, MERGE, ESCO, BIG>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   const int64_t grid = std::min<int64_t>(wp.ntiles, 0x7fffffff);
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_wt<MODE, M, MERGE, ESCO>), dim3((unsigned)grid), dim3(kWave), lds, s, wp);
+  hipLaunchKernelGGL((k_wt<MODE, M, MERGE, ESCO, BIG>), dim3((unsigned)grid), dim3(kWave), lds, s, wp);
   return hipGetLastError();
 }
 
@@ -2925,8 +2934,12 @@ static hipError_t launch_wt_m(const WaveTileParams &wp, int mode, size_t lds, hi
 }
 
 hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists, bool has_merge, bool esc_only,
-                             hipStream_t s) {
+                             bool esc_big, hipStream_t s) {
   const size_t lds = wave_tile_lds(mode, wp.table_slots, wp.stage_slots);
+  if (esc_big && (mode != kNumeric || has_merge)) return hipErrorInvalidValue;   // sizing never asks for it
+  if (esc_big)
+    return esc_only ? launch_wt_mm<kNumeric, 4, false, true, true>(wp, lds, s)
+                    : launch_wt_mm<kNumeric, 4, false, false, true>(wp, lds, s);
   if (mode != kSymbolic && esc_only && !has_merge)
     return mode == kNumeric ? launch_wt_mm<kNumeric, 4, false, true>(wp, lds, s)
                             : launch_wt_mm<kOnePass, 4, false, true>(wp, lds, s);
