@@ -126,12 +126,12 @@ class Product:
         self.P, self.torch = P, torch
         self.name, self.A, self.B, self.dA, self.dB = name, A, B, dA, dB
         self.out = {}
-        self.tuning = None   # the autotuner's choice, when it beat the defaults
+        self.tuning = {}   # sizer -> the autotuner's choice, when it beat the defaults
 
     def run(self, sizer, model, tuning=None):
         P, torch = self.P, self.torch
         if tuning is None:
-            tuning = self.tuning
+            tuning = self.tuning.get(sizer)
         plan = P.Plan(self.dA, self.dB, sizer, model, timing=True, tuning=tuning)
         dev = self.dA.row_ptr.device
         sym_ms = 0.0
@@ -646,22 +646,30 @@ def main():
 
     tuned = {}
     if not args.no_autotune:
-        # thresholds and tile shapes picked per workload by the library's
-        # autotuner (row-kernel time of the exact path over its candidate
-        # grid), kept when the whole product is faster than with the defaults
+        # thresholds and tile shapes picked per workload and sizer by the
+        # library's autotuner (row-kernel time of that sizer's passes over its
+        # candidate grid), kept when the whole product is faster than with the
+        # defaults: a one-pass product lays rows out by other capacities than
+        # the exact one, so its best tiles differ
         from paper_1303_1651_amd.autotune import autotune
         log("autotuning")
+        sizers = [args.sizer] + ([] if args.no_compare else
+                                 [s for s in ("exact", "upper_bound", "learned") if s != args.sizer])
         for p in products:
-            t0 = time.time()
-            cand = autotune(p.dA, p.dB, "exact", reps=2)
-            d_ms = time_product(torch, p, "exact", model, args.steps, tuning={})
-            t_ms = time_product(torch, p, "exact", model, args.steps, tuning=cand)
-            keep = t_ms < d_ms
-            if keep:
-                p.tuning = cand
-            tuned[p.name] = {"candidate": cand, "kept": keep, "product_ms_default_tuning": round(d_ms, 4),
-                             "product_ms_candidate": round(t_ms, 4), "seconds": round(time.time() - t0, 2)}
-            log("  %s: default %.3f ms, tuned %.3f ms (%s)" % (p.name, d_ms, t_ms, "kept" if keep else "dropped"))
+            tuned[p.name] = {}
+            for sizer in sizers:
+                t0 = time.time()
+                cand = autotune(p.dA, p.dB, sizer, model if sizer == "learned" else None, reps=2)
+                d_ms = time_product(torch, p, sizer, model, args.steps, tuning={})
+                t_ms = time_product(torch, p, sizer, model, args.steps, tuning=cand)
+                keep = t_ms < d_ms
+                if keep:
+                    p.tuning[sizer] = cand
+                tuned[p.name][sizer] = {"candidate": cand, "kept": keep, "product_ms_default_tuning": round(d_ms, 4),
+                                        "product_ms_candidate": round(t_ms, 4),
+                                        "seconds": round(time.time() - t0, 2)}
+                log("  %s %s: default %.3f ms, tuned %.3f ms (%s)" % (p.name, sizer, d_ms, t_ms,
+                                                                     "kept" if keep else "dropped"))
 
     log("timed steps (%s)" % args.sizer)
     ms, wall_ms, per = time_steps(torch, products, args.sizer, model, args.steps, args.warmup)
