@@ -1642,14 +1642,32 @@ __device__ __forceinline__ void wave_clear(const WaveTable &tb) {
 // 31, a permute across the halves for 32 and 63.
 template <int LM>
 __device__ __forceinline__ int32_t xor_lane(int32_t v) {
-  if constexpr (LM == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad (1,0,3,2)
-  else if constexpr (LM == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // quad (2,3,0,1)
-  else if constexpr (LM == 3) return __builtin_amdgcn_update_dpp(0, v, 0x1B, 0xF, 0xF, false);  // quad (3,2,1,0)
-  else if constexpr (LM == 7) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false); // half-row mirror
-  else if constexpr (LM == 8) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false); // row rotate 8
-  else if constexpr (LM == 15) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false); // row mirror
+  if constexpr (LM == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);   // quad (1,0,3,2)
+  else if constexpr (LM == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);  // quad (2,3,0,1)
+  else if constexpr (LM == 3) return __builtin_amdgcn_update_dpp(0, v, 0x1B, 0xF, 0xF, true);  // quad (3,2,1,0)
+  else if constexpr (LM == 7) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true); // half-row mirror
+  else if constexpr (LM == 8) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, true); // row rotate 8
+  else if constexpr (LM == 15) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true); // row mirror
   else if constexpr (LM < 32) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (LM << 10));        // lane ^ LM
   else return __shfl_xor(v, LM, kWave);
+}
+
+// The middle of three keys: with c the smallest int the smaller of x and y,
+// with c the largest the larger; one instruction for the compare-exchange
+// of a lane with its partner lane.
+__device__ __forceinline__ int32_t med3_i32(int32_t x, int32_t y, int32_t c) {
+  int32_t r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(y), "v"(c));
+  return r;
+}
+// c for a stage whose lower lanes (bit B of the lane clear) keep the smaller
+// key: the smallest int there, the largest elsewhere.  Made where it is used
+// (not hoisted: one register instead of one per stage).
+template <int B>
+__device__ __forceinline__ int32_t lane_side(int lane) {
+  int32_t c;
+  asm volatile("v_bfe_i32 %0, %1, %2, 1\n\tv_xor_b32 %0, 0x80000000, %0" : "=&v"(c) : "v"(lane), "i"(B));
+  return c;
 }
 
 // Stage (K, J) of the sort: J == K / 2 is the mirror stage of level K.
@@ -1659,14 +1677,14 @@ __device__ __forceinline__ void wave_bitonic_stage(int32_t (&x)[E]) {
   if constexpr (J == K / 2 && K > E) {
     // mirror partner: lane ^ (K/E - 1), element E - 1 - e
     constexpr int lm = K / E - 1;
-    const bool lower = (lane & (K / (2 * E))) == 0;
+    const int32_t c = lane_side<__builtin_ctz(K / (2 * E))>(lane);
     // elements e and E - 1 - e trade partners: two values in flight
 #pragma unroll
     for (int e = 0; e < (E + 1) / 2; ++e) {
       const int32_t ya = xor_lane<lm>(x[E - 1 - e]);
       const int32_t yb = xor_lane<lm>(x[e]);
-      x[e] = lower ? min(x[e], ya) : max(x[e], ya);
-      if (E - 1 - e != e) x[E - 1 - e] = lower ? min(x[E - 1 - e], yb) : max(x[E - 1 - e], yb);
+      x[e] = med3_i32(x[e], ya, c);
+      if (E - 1 - e != e) x[E - 1 - e] = med3_i32(x[E - 1 - e], yb, c);
     }
   } else if constexpr (J == K / 2) {
 #pragma unroll
@@ -1679,11 +1697,11 @@ __device__ __forceinline__ void wave_bitonic_stage(int32_t (&x)[E]) {
     }
   } else if constexpr (J >= E) {
     constexpr int lm = J / E;
-    const bool lower = (lane & lm) == 0;
+    const int32_t c = lane_side<__builtin_ctz(lm)>(lane);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int32_t y = xor_lane<lm>(x[e]);
-      x[e] = lower ? min(x[e], y) : max(x[e], y);
+      x[e] = med3_i32(x[e], y, c);
     }
   } else {
 #pragma unroll
