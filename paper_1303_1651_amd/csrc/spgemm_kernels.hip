@@ -2080,7 +2080,7 @@ __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots,
 // BIG: expand-sort rows of up to kEscMax products (sorted 16 per lane);
 // launches without it take rows of at most kEscMaxSmall (fewer registers).
 template <int MODE, int M, bool MERGE, bool ESCO = false, bool BIG = false>
-__global__ void __launch_bounds__(kWave, ESCO ? 5
+__global__ void __launch_bounds__(kWave, ESCO ? (BIG ? 5 : (MODE == kNumeric ? 7 : 6))
                                          : MODE == kSymbolic ? 7
                                          : (MODE == kOnePass ? (MERGE ? 2 : 4) : (MERGE && M == 8 ? 3 : 4)))
 k_wt(WaveTileParams p) {
