@@ -35,7 +35,9 @@ def signature(A: DeviceCSR, B: DeviceCSR, sizer: str) -> str:
     return "%s:r%d:a%.0f:b%.0f" % (sizer, int(math.log2(max(A.rows, 1))), ra, rb)
 
 
-def _time(A, B, sizer, model, tuning, reps):
+def _time(A, B, sizer, model, tuning, reps, cutoff=None):
+    """Best row-kernel time over `reps` products; stops after the first one
+    slower than `cutoff` ms (a candidate far behind the best so far)."""
     best = None
     for _ in range(reps):
         plan = Plan(A, B, sizer, model, tuning=tuning, timing=True)
@@ -57,6 +59,8 @@ def _time(A, B, sizer, model, tuning, reps):
         ms = plan.info["tile_ms_total"]
         plan.close()
         best = ms if best is None else min(best, ms)
+        if cutoff is not None and best > cutoff:
+            break
     return best
 
 
@@ -72,11 +76,15 @@ def autotune(A: DeviceCSR, B: DeviceCSR, sizer: str = "exact", model=None, grid:
     grid = grid or DEFAULT_GRID
     names = list(grid)
     results = []
+    # the library's defaults first: a candidate more than twice as slow as
+    # the best so far is not timed again
+    lead = _time(A, B, sizer, model, {}, 1)
     for values in itertools.product(*[grid[n] for n in names]):
         t = dict(zip(names, values))
         if 12 * (t.get("table_slots", 1024) + t.get("stage_slots", 1024)) > 147456:
             continue
-        ms = _time(A, B, sizer, model, t, reps)
+        ms = _time(A, B, sizer, model, t, reps, cutoff=2.0 * lead)
+        lead = min(lead, ms)
         results.append((ms, t))
         if log:
             log("%8.3f ms  %s" % (ms, t))

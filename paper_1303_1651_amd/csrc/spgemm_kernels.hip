@@ -2073,10 +2073,13 @@ __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots,
 // one pass, no merge rows): the table path is not compiled, which frees
 // registers.
 // Resident waves per SIMD: seven for the counting pass (no values: it fits
-// 70 registers without spills), five for expand-sort launches, four for the
-// table launches (the one pass spills a few registers there, which costs
-// less than the fourth wave gains: 24.0 -> 19.7 ms on the 27-point
-// product), fewer where the merge lists take registers.
+// 72 registers with few spills); for expand-sort launches seven in the
+// numeric pass and six in the one pass (their spills, outside the sort,
+// cost less than the extra waves gain in hiding the gathers' latency), five
+// with the 16-per-lane sort (no spills); four for the table launches (the
+// one pass spills a few registers there, which costs less than the fourth
+// wave gains: 24.0 -> 19.7 ms on the 27-point product), fewer where the
+// merge lists take registers.
 // BIG: expand-sort rows of up to kEscMax products (sorted 16 per lane);
 // launches without it take rows of at most kEscMaxSmall (fewer registers).
 template <int MODE, int M, bool MERGE, bool ESCO = false, bool BIG = false>
