@@ -159,7 +159,7 @@ struct spgemm_plan {
   int cur_mode;        // mode the current tiles were sized for
   int64_t ntiles;
   int64_t nbig;            // workgroup-tier rows of the current sizing
-  int64_t esc_rows;        // expand-sort rows of the current (numeric or one-pass) sizing
+  int64_t esc_rows;        // expand-sort rows (counting: sort-count rows) of the current sizing
   int64_t scratch_slots;   // per workgroup, current sizing
   int64_t scratch_slots_plan;
   int64_t scratch_rows;    // rows that may need a workgroup-tier table (plan sizing)
@@ -314,7 +314,7 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
   p->nbig = h[kCtrGlobal];
   // expand-sort rows: their count, and above bit 32 those of more than
   // kEscMaxSmall products (the numeric launch then sorts 16 keys per lane)
-  p->esc_rows = mode != kSymbolic ? (h[kCtrEsc] & 0xffffffffll) : 0;
+  p->esc_rows = h[kCtrEsc] & 0xffffffffll;   // counting: the sort-count rows
   p->esc_big = mode == kNumeric ? (h[kCtrEsc] >> 32) : 0;
   // the bitmap kernel needs no device tables
   p->scratch_slots = p->bitmap_words > 0 ? 0 : (h[kCtrScratch] + 1) & ~(int64_t)1;
@@ -384,7 +384,7 @@ static spgemm_status run_wave(spgemm_plan *p, int mode, const double *a_val, con
   wp.stage_row_max = stage_row_max(p, mode);
   // a pass whose hashed rows are all expand-sort rows (and no merge rows)
   // runs the tile kernel without the table path (fewer registers)
-  const bool esc_only = mode != kSymbolic && p->esc_rows > 0 && p->esc_rows == p->info.rows_hash;
+  const bool esc_only = p->esc_rows > 0 && p->esc_rows == p->info.rows_hash;
   bool has_merge = p->info.rows_merge > 0;
   if (has_merge && mode != kOnePass && p->tune.split_merge > 0) {
     // two-pass passes: the merge rows by the row-per-thread kernel at its own

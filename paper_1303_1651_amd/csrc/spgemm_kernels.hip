@@ -2070,10 +2070,11 @@ __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots,
 }
 
 // ESCO: every hashed row of the launch is an expand-sort row (numeric or
-// one pass, no merge rows): the table path is not compiled, which frees
-// registers.
+// one pass) or, counting, a sort-count row (no merge rows): the table path
+// is not compiled, which frees registers.
 // Resident waves per SIMD: seven for the counting pass (no values: it fits
-// 72 registers with few spills); for expand-sort launches seven in the
+// 72 registers with few spills), eight when it only sorts; for expand-sort
+// launches seven in the
 // numeric pass and six in the one pass (their spills, outside the sort,
 // cost less than the extra waves gain in hiding the gathers' latency), five
 // with the 16-per-lane sort (no spills); four for the table launches (the
@@ -2083,7 +2084,7 @@ __host__ __device__ inline WaveLds wave_lds_layout(bool values, int table_slots,
 // BIG: expand-sort rows of up to kEscMax products (sorted 16 per lane);
 // launches without it take rows of at most kEscMaxSmall (fewer registers).
 template <int MODE, int M, bool MERGE, bool ESCO = false, bool BIG = false>
-__global__ void __launch_bounds__(kWave, ESCO ? (BIG ? 5 : (MODE == kNumeric ? 7 : 6))
+__global__ void __launch_bounds__(kWave, ESCO ? (BIG ? 5 : (MODE == kOnePass ? 6 : (MODE == kNumeric ? 7 : 8)))
                                          : MODE == kSymbolic ? 7
                                          : (MODE == kOnePass ? (MERGE ? 2 : 4) : (MERGE && M == 8 ? 3 : 4)))
 k_wt(WaveTileParams p) {
@@ -2209,7 +2210,7 @@ k_wt(WaveTileParams p) {
         }
         continue;
       }
-      if (MODE == kSymbolic && info_esc(__shfl(inf, r, kWave))) {
+      if (MODE == kSymbolic && (ESCO || info_esc(__shfl(inf, r, kWave)))) {
         const int32_t c = wave_sort_count(op, op.a_rp[hrow], op.a_rp[hrow + 1], p.maxb[hrow], re, tkeys);
         if (lane == r) n = c;
         continue;
@@ -2961,9 +2962,11 @@ hipError_t launch_wave_tiles(const WaveTileParams &wp, int mode, int merge_lists
   if (esc_big)
     return esc_only ? launch_wt_mm<kNumeric, 4, false, true, true>(wp, lds, s)
                     : launch_wt_mm<kNumeric, 4, false, false, true>(wp, lds, s);
-  if (mode != kSymbolic && esc_only && !has_merge)
+  if (esc_only && !has_merge) {
+    if (mode == kSymbolic) return launch_wt_mm<kSymbolic, 4, false, true>(wp, lds, s);
     return mode == kNumeric ? launch_wt_mm<kNumeric, 4, false, true>(wp, lds, s)
                             : launch_wt_mm<kOnePass, 4, false, true>(wp, lds, s);
+  }
   if (!has_merge) return launch_wt_m<4, false>(wp, mode, lds, s);
   switch (merge_lists) {
     case 4: return launch_wt_m<4, true>(wp, mode, lds, s);
