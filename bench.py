@@ -6,9 +6,9 @@ exactly 16 distinct uniform columns per row and values U(-1, 1) times an
 independent matrix drawn the same way.  One step is one full product of
 each on the plain two-pass path (plan, symbolic pass, scan, numeric pass);
 inputs are resident in HBM before the timed region.  Before timing, the
-library's autotuner picks each product's tier thresholds and tile shapes
-(kept only when the whole product beats the default tuning; both times are
-reported; --no-autotune times the defaults).  Other workloads:
+library's autotuner picks each product's tier thresholds and tile shapes,
+once per sizer the line times (kept only when that whole product beats the
+default tuning; both times are reported; --no-autotune times the defaults).  Other workloads:
 --workload zipf (power-law rows, N = 2^20, the learned-sizer study), st9,
 st27, batched.
 
