@@ -105,7 +105,7 @@ __device__ __forceinline__ float predict_coop(const float *W, float *hbuf, int32
 // a thread's rows, so more workgroups hide them better).
 template <bool FEAT>
 struct PredShape {
-  static constexpr int kRowsPerThread = FEAT ? 1 : 4;
+  static constexpr int kRowsPerThread = FEAT ? 2 : 4;
   static constexpr int kRows = kBlock * kRowsPerThread;
   static constexpr int kTab = 2 * kRows;
 };
