@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(kSumThreads) k_sum_partials(const int64_t *par
   for (int64_t b0 = threadIdx.x; b0 < nblocks; b0 += 8 * nt) {
 #pragma unroll
     for (int j = 0; j < kMaxPartials; ++j) {
-      if (j >= ps.n) break;
+      if (j >= ps.n) continue;
       int64_t v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(kSumThreads) k_sum_partials(const int64_t *par
   }
 #pragma unroll
   for (int j = 0; j < kMaxPartials; ++j) {
-    if (j >= ps.n) break;
+    if (j >= ps.n) continue;
     int64_t a = acc[j];
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) {
@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(kBlock) k_fold_partials(const int64_t *partial
   const int64_t b = (int64_t)blockIdx.x * kFold + threadIdx.x;
 #pragma unroll
   for (int j = 0; j < kMaxPartials; ++j) {
-    if (j >= ps.n) break;
+    if (j >= ps.n) continue;
     int64_t a = b < nblocks ? partials[b * ps.stride + j] : 0;
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) {
