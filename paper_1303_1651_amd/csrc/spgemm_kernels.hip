@@ -456,11 +456,6 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
         // load is high only where the capacity is close to the bound)
         if (sp.mode == kOnePass && T > sp.table_max) T = table_pow2(ub + 1);
       }
-      // rows whose products rarely share a column (the bound, not
-      // saturated, within a quarter of the count or the capacity), whose B
-      // rows fit one wave
-      // and whose column offsets pack with a product index into one word:
-      // expand, sort, combine (T slots hold the products)
       bool esc = false;
       if (sym && !dense && mx <= kWave) {
         // counting: the row's columns in blocks of pow2(mx) per entry of A,
@@ -473,7 +468,11 @@ __global__ void __launch_bounds__(kBlock) k_size_rows(Operands op, PlanArrays pa
           T = te;
         }
       }
-      // rows of more than kEscMaxSmall products only where merge rows run
+      // rows whose products rarely share a column (the bound, not
+      // saturated, within a quarter of the count or the capacity), whose B
+      // rows fit one wave and whose column offsets pack with a product index
+      // into one word: expand, sort, combine (T slots hold the products).
+      // Rows of more than kEscMaxSmall products only where merge rows run
       // apart: the tile launch is then a variant without the merge code, which
       // has the registers for the 16-per-lane sort
       if (!dense && !sym && mx <= kWave && ub <= (sp.merge_apart ? kEscMax : kEscMaxSmall) && ub < op.b_cols &&
