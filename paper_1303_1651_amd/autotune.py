@@ -88,6 +88,8 @@ def autotune(A: DeviceCSR, B: DeviceCSR, sizer: str = "exact", model=None, grid:
         results.append((ms, t))
         if log:
             log("%8.3f ms  %s" % (ms, t))
+    if not results:
+        return {}   # no candidate fits the LDS budget: the library's defaults
     results.sort(key=lambda r: r[0])
     best_ms, best = results[0]
     if cache:
