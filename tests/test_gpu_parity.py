@@ -422,3 +422,15 @@ def test_workgroup_bitmap_window(sizer):
     want = oracle.spgemm(A, B)
     got = gpu_product(A, B, sizer, tuning={"merge_max_nnz": -1, "table_slots": -1, "bitmap_cols": 1 << 20})
     assert_bit_exact(got, want)
+
+
+@pytest.mark.parametrize("k", [16, 24, 32])
+def test_expand_sort_rows_up_to_1024_products(k):
+    # rows of k x k products over a million columns (few shared): in the
+    # numeric pass expand-sort rows, those above 512 products sorted 16 keys
+    # per lane; the one pass takes them through its table
+    A = synth.random_fixed(1500, k, 41 + k, cols=1 << 16)
+    B = synth.random_fixed(1 << 16, k, 97 + k, cols=1 << 20)
+    want = oracle.spgemm(A, B)
+    for sizer in SIZERS:
+        assert_bit_exact(gpu_product(A, B, sizer), want)
