@@ -2380,6 +2380,18 @@ __global__ void __launch_bounds__(kBlock) k_compact(CompactParams p) {
   if (l == 0) s_dst[w][nr] = p.c_rp[r0 + nr] - base;
   wave_sync();
   const int64_t lim = min(base + s_dst[w][nr], p.c_capacity) - base;
+  if (s_dst[w][nr] >= 32 * (int64_t)nr) {
+    // rows of 32 or more entries on average: row by row, the whole wave on
+    // each row's contiguous range (no search per entry)
+    for (int r = 0; r < nr; ++r) {
+      const int64_t from = s_src[w][r];
+      const int64_t d0 = s_dst[w][r], d1 = min(s_dst[w][r + 1], lim);
+      if (from < 0) continue;
+      for (int64_t q = d0 + l; q < d1; q += kWave)
+        put_c<false>(p.c_col, p.c_val, base + q, p.pad_col[from + (q - d0)], p.pad_val[from + (q - d0)]);
+    }
+    return;
+  }
   for (int64_t q = l; q < lim; q += kWave) {
     // the row holding entry base + q: the last row whose start is <= q
     int lo = 0, hi = nr - 1;
