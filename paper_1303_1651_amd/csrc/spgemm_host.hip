@@ -680,15 +680,10 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   // Longest row of A (row pointers only) decides the path.  Every row
   // merges in registers when no row of A has more stored entries than the
   // merge tier's lists (and the tier is not switched off); then no per-row
-  // plan arrays are needed.
-  // The one-pass sizers get it with the sizes their merge path needs (the
-  // multiplication count, or the learned capacities, summed): the pass is
-  // wasted only for products that take the tiled path.
-  hipError_t he;
-  if (p->first_mode == kSymbolic) he = launch_row_max(op, p->pa.counters, p->pa.partials, s);
-  else if (learned) he = launch_mlp_capacity(dev, op, p->pa.counters, p->pa.partials, p->tune.margin, p->tune.slack, s);
-  else he = launch_features(op, p->pa.f, p->pa.counters, p->pa.partials, 0, s);
-  if (he != hipSuccess) return fail(SPGEMM_E_HIP);
+  // plan arrays are needed.  The one-pass sizers' sums for that path (the
+  // multiplication count, or the learned capacities) come from a pass of
+  // their own below, run only for products that take it.
+  if (launch_row_max(op, p->pa.counters, p->pa.partials, s) != hipSuccess) return fail(SPGEMM_E_HIP);
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return fail(st);
@@ -722,8 +717,13 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
     }
     // one pass: the capacities' sum (the size of C to allocate; the
     // multiplication count, or the learned sizes) and their largest sum
-    // over a wave's 64 rows (the staging of the numeric merge), from the
-    // pass above
+    // over a wave's 64 rows (the staging of the numeric merge)
+    const hipError_t he =
+        learned ? launch_mlp_capacity(dev, op, p->pa.counters, p->pa.partials, p->tune.margin, p->tune.slack, s)
+                : launch_features(op, p->pa.f, p->pa.counters, p->pa.partials, 0, s);
+    if (he != hipSuccess) return fail(SPGEMM_E_HIP);
+    st = read_counters(p, s, &h);
+    if (st != SPGEMM_OK) return fail(st);
     p->info.rows_empty = h[kCtrEmpty];
     p->info.rows_merge = A->rows - h[kCtrEmpty];
     p->info.c_capacity_hint = learned ? h[kCtrCapSum] + h[kCtrUnpacked] : h[kCtrMults];
