@@ -137,11 +137,20 @@ __device__ __forceinline__ uint32_t triple_hash(uint64_t k, int tab) {
 // features come from the per-row arrays and every row's prediction is stored.
 constexpr int kCapParts = 6;
 
+// gate (FEAT, may be null): the longest row of A, already summed; when it
+// exceeds gate_max the product takes the tiled path, which predicts its
+// rows' sizes there, and every workgroup only passes the longest row on.
 template <bool FEAT>
 __global__ void __launch_bounds__(kBlock) k_mlp_predict(const float *__restrict__ dev, Operands op,
                                                         const int32_t *f1a, const int32_t *f2a, const int32_t *f3a,
                                                         int64_t n, float *pred, float margin, int slack,
-                                                        int64_t *partials, int64_t *err) {
+                                                        int64_t *partials, int64_t *err, const int64_t *gate,
+                                                        int64_t gate_max) {
+  if (FEAT && gate && *gate > gate_max) {
+    if (partials && threadIdx.x < kCapParts)
+      partials[kCapParts * blockIdx.x + threadIdx.x] = threadIdx.x == 3 ? *gate : 0;
+    return;
+  }
   constexpr int kPredRowsPerThread = PredShape<FEAT>::kRowsPerThread;
   constexpr int kPredRows = PredShape<FEAT>::kRows;
   constexpr int kPredTab = PredShape<FEAT>::kTab;
@@ -308,12 +317,12 @@ hipError_t launch_mlp_predict(const float *dev, const int32_t *f1, const int32_t
   if (n <= 0) return hipSuccess;
   int64_t blocks = mlp_predict_blocks(n);
   hipLaunchKernelGGL(k_mlp_predict<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, dev, Operands{}, f1, f2, f3, n,
-                     pred, margin, slack, partials, (int64_t *)nullptr);
+                     pred, margin, slack, partials, (int64_t *)nullptr, (const int64_t *)nullptr, (int64_t)0);
   return hipGetLastError();
 }
 
 hipError_t launch_mlp_capacity(const float *dev, const Operands &op, int64_t *counters, int64_t *partials,
-                               float margin, int slack, hipStream_t s) {
+                               float margin, int slack, hipStream_t s, const int64_t *gate, int64_t gate_max) {
   const int32_t dst[kCapParts] = {kCtrCapSum, kCtrWaveCap, kCtrMults, kCtrMaxA, kCtrEmpty, kCtrUnpacked};
   const int32_t mx[kCapParts] = {0, 1, 0, 1, 0, 0};
   if (op.rows <= 0) {
@@ -326,7 +335,7 @@ hipError_t launch_mlp_capacity(const float *dev, const Operands &op, int64_t *co
   const int64_t blocks = (op.rows + PredShape<true>::kRows - 1) / PredShape<true>::kRows;
   hipLaunchKernelGGL(k_mlp_predict<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, dev, op,
                      (const int32_t *)nullptr, (const int32_t *)nullptr, (const int32_t *)nullptr, op.rows,
-                     (float *)nullptr, margin, slack, partials, counters + kCtrError);
+                     (float *)nullptr, margin, slack, partials, counters + kCtrError, gate, gate_max);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_sum_partials(partials, blocks, kCapParts, kCapParts, dst, mx, counters, s);

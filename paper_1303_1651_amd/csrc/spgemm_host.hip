@@ -680,21 +680,33 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
   // Longest row of A (row pointers only) decides the path.  Every row
   // merges in registers when no row of A has more stored entries than the
   // merge tier's lists (and the tier is not switched off); then no per-row
-  // plan arrays are needed.  The one-pass sizers' sums for that path (the
-  // multiplication count, or the learned capacities) come from a pass of
-  // their own below, run only for products that take it.
+  // plan arrays are needed.  The merge pays per output entry for every
+  // list: it takes rows with few entries of A and short outputs (estimated
+  // from the mean row lengths of A and B).
+  const double est_row = (A->rows > 0 ? (double)A->nnz / (double)A->rows : 0.0) *
+                         (B->rows > 0 ? (double)B->nnz / (double)B->rows : 0.0);
+  const int64_t merge_max_a = p->tune.merge_max_nnz <= 0 ? -1
+                              : est_row <= kMergeOnlyRowEst
+                                  ? kMergeOnlyLists
+                                  : std::min<int64_t>(p->tune.merge_lists, kMergeOnlyLists);
   if (launch_row_max(op, p->pa.counters, p->pa.partials, s) != hipSuccess) return fail(SPGEMM_E_HIP);
+  // The one-pass sizers' sums for the merge path (the multiplication count,
+  // or the learned capacities) in the same round trip: their kernel reads
+  // the longest row first and does the work only when the merge path is
+  // taken (the tiled path's plan computes its own).
+  if (p->first_mode != kSymbolic) {
+    const int64_t *gate = p->pa.counters + kCtrMaxA;
+    const hipError_t he = learned ? launch_mlp_capacity(dev, op, p->pa.counters, p->pa.partials, p->tune.margin,
+                                                        p->tune.slack, s, gate, merge_max_a)
+                                  : launch_features(op, p->pa.f, p->pa.counters, p->pa.partials, 0, s, gate,
+                                                    merge_max_a);
+    if (he != hipSuccess) return fail(SPGEMM_E_HIP);
+  }
   int64_t *h;
   st = read_counters(p, s, &h);
   if (st != SPGEMM_OK) return fail(st);
   if (h[kCtrError] & kErrDescriptor) return fail(SPGEMM_E_DIM);
-  // The merge pays per output entry for every list: it takes rows with
-  // few entries of A and short outputs (estimated from the mean row lengths
-  // of A and B).
-  const double est_row = (A->rows > 0 ? (double)A->nnz / (double)A->rows : 0.0) *
-                         (B->rows > 0 ? (double)B->nnz / (double)B->rows : 0.0);
-  p->merge_only = A->rows > 0 && h[kCtrMaxA] <= kMergeOnlyLists && p->tune.merge_max_nnz > 0 &&
-                  (h[kCtrMaxA] <= p->tune.merge_lists || est_row <= kMergeOnlyRowEst);
+  p->merge_only = A->rows > 0 && h[kCtrMaxA] <= merge_max_a;
   // the fewest lists that hold every row of A (registers grow with them)
   {
     const int64_t ma = h[kCtrMaxA];
@@ -717,13 +729,8 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
     }
     // one pass: the capacities' sum (the size of C to allocate; the
     // multiplication count, or the learned sizes) and their largest sum
-    // over a wave's 64 rows (the staging of the numeric merge)
-    const hipError_t he =
-        learned ? launch_mlp_capacity(dev, op, p->pa.counters, p->pa.partials, p->tune.margin, p->tune.slack, s)
-                : launch_features(op, p->pa.f, p->pa.counters, p->pa.partials, 0, s);
-    if (he != hipSuccess) return fail(SPGEMM_E_HIP);
-    st = read_counters(p, s, &h);
-    if (st != SPGEMM_OK) return fail(st);
+    // over a wave's 64 rows (the staging of the numeric merge), from the
+    // gated pass above
     p->info.rows_empty = h[kCtrEmpty];
     p->info.rows_merge = A->rows - h[kCtrEmpty];
     p->info.c_capacity_hint = learned ? h[kCtrCapSum] + h[kCtrUnpacked] : h[kCtrMults];

@@ -38,9 +38,12 @@ int64_t mlp_predict_blocks(int64_t n);
 // operands: sums into counters[kCtrCapSum] (rows whose triple does not pack
 // count 0; their summed bounds go to kCtrUnpacked), the largest sum over 64
 // consecutive rows into kCtrWaveCap, and the multiplication count, longest
-// row of A and empty rows into kCtrMults, kCtrMaxA and kCtrEmpty.
+// row of A and empty rows into kCtrMults, kCtrMaxA and kCtrEmpty.  With a
+// gate (the summed longest row of A) above gate_max only the longest row is
+// passed on.
 hipError_t launch_mlp_capacity(const float *dev_params, const Operands &op, int64_t *counters, int64_t *partials,
-                               float margin, int slack, hipStream_t s);
+                               float margin, int slack, hipStream_t s, const int64_t *gate = nullptr,
+                               int64_t gate_max = 0);
 
 // Capacity of a row sized by the learned prediction: ceil(pred * (1 +
 // margin)) + slack, clamped to [longest selected B row, multiplication

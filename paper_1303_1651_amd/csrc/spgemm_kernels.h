@@ -354,7 +354,7 @@ hipError_t launch_validate(const int64_t *rp, const int32_t *col, int64_t rows, 
 // largest multiplication count summed over 64 consecutive rows).  mode 2
 // also writes the per-row plan arrays in f.
 hipError_t launch_features(const Operands &op, const Features &f, int64_t *counters, int64_t *partials, int mode,
-                           hipStream_t s);
+                           hipStream_t s, const int64_t *gate = nullptr, int64_t gate_max = 0);
 // Longest row of A into counters[kCtrMaxA]; raises kErrDescriptor when a
 // descriptor's nnz differs from its row_ptr[rows].
 hipError_t launch_row_max(const Operands &op, int64_t *counters, int64_t *partials, hipStream_t s);

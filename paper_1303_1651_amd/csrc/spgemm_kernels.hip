@@ -131,9 +131,17 @@ __device__ __forceinline__ void b_row_part(const Operands &op, int64_t e, int32_
 // rows, largest multiplication count summed over 64 consecutive rows.
 // MODE 0: partial sums only.  MODE 2: also the per-row plan arrays
 // (entries, saturated count, longest B row, column span) for tiled passes.
+// gate (MODE 0, may be null): the longest row of A, already summed; when it
+// exceeds gate_max the product takes the tiled path, whose plan computes
+// these sums again, and every workgroup only passes the longest row on.
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_features(Operands op, Features f, int64_t *partials, int64_t *err) {
+__global__ void __launch_bounds__(kBlock) k_features(Operands op, Features f, int64_t *partials, int64_t *err,
+                                                     const int64_t *gate, int64_t gate_max) {
   __shared__ int64_t s_sum[4][kWavesPerBlock];
+  if (MODE == 0 && gate && *gate > gate_max) {
+    if (threadIdx.x < 4) partials[blockIdx.x * 4 + threadIdx.x] = threadIdx.x == 1 ? *gate : 0;
+    return;
+  }
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   // arrays sized by the descriptors' nnz rely on it
   if (i == 0 && (op.a_rp[op.rows] != op.a_nnz || op.b_rp[op.b_rows] != op.b_nnz))
@@ -319,7 +327,7 @@ hipError_t launch_sum_partials(const int64_t *partials, int64_t nblocks, int n, 
 }
 
 hipError_t launch_features(const Operands &op, const Features &f, int64_t *counters, int64_t *partials, int mode,
-                           hipStream_t s) {
+                           hipStream_t s, const int64_t *gate, int64_t gate_max) {
   const int32_t dst[4] = {kCtrMults, kCtrMaxA, kCtrEmpty, kCtrWaveCap};
   const int32_t mx[4] = {0, 1, 0, 1};
   if (op.rows <= 0) {
@@ -331,8 +339,12 @@ hipError_t launch_features(const Operands &op, const Features &f, int64_t *count
   }
   const int64_t blocks = (op.rows + kBlock - 1) / kBlock;
   int64_t *err = counters + kCtrError;
-  if (mode == 2) hipLaunchKernelGGL(k_features<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, partials, err);
-  else hipLaunchKernelGGL(k_features<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, partials, err);
+  if (mode == 2)
+    hipLaunchKernelGGL(k_features<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, partials, err,
+                       (const int64_t *)nullptr, (int64_t)0);
+  else
+    hipLaunchKernelGGL(k_features<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, op, f, partials, err, gate,
+                       gate_max);
   return launch_sum_partials(partials, blocks, 4, 4, dst, mx, counters, s);
 }
 
