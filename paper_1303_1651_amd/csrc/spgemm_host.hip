@@ -338,6 +338,15 @@ static spgemm_status size_pass(spgemm_plan *p, int mode, hipStream_t s) {
 // waves).  Where only a few rows would be staged (a stencil's boundary
 // rows, say), the pass is sized again without staging hashed rows: they are
 // written straight to their place like the longer ones.
+// Merge tier switched off for a re-sizing; staging too when the rows staged
+// after it (at most those staged now plus the merge rows) will be few, so
+// that one re-sizing does what unstage_if_few would otherwise size again.
+static void merge_off_for_resize(spgemm_plan *p) {
+  p->merge_off = 1;
+  const int64_t staged_max = p->staged_rows + p->info.rows_merge;
+  if (!p->stage_off && staged_max > 0 && staged_max * kMergeFewRows < p->A.rows) p->stage_off = 1;
+}
+
 static spgemm_status unstage_if_few(spgemm_plan *p, int mode, hipStream_t s) {
   if (p->stage_off || (p->info.rows_merge > 0 && !(mode == kNumeric && p->tune.split_merge > 0)) ||
       p->staged_rows == 0 || p->staged_rows * kMergeFewRows >= p->A.rows)
@@ -752,7 +761,7 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
     // (fewer resident waves) for every tile
     if (st == SPGEMM_OK && p->first_mode == kOnePass && p->info.rows_merge > 0 &&
         p->info.rows_merge * kMergeFewRows < A->rows) {
-      p->merge_off = 1;
+      merge_off_for_resize(p);
       st = size_pass(p, p->first_mode, s);
     }
     if (st == SPGEMM_OK && p->first_mode == kOnePass) st = unstage_if_few(p, p->first_mode, s);
@@ -828,7 +837,7 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, void *scratch, size_t scratch_byte
     st = size_pass(p, kNumeric, s);
     if (st == SPGEMM_OK && !p->merge_off && p->info.rows_merge > 0 &&
         p->info.rows_merge * kMergeFewRows < p->A.rows) {
-      p->merge_off = 1;
+      merge_off_for_resize(p);
       st = size_pass(p, kNumeric, s);
     }
     if (st == SPGEMM_OK) st = unstage_if_few(p, kNumeric, s);
