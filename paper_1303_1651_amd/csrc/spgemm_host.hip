@@ -766,12 +766,16 @@ spgemm_status spgemm_plan_create(const spgemm_csr *A, const spgemm_csr *B, const
     }
     if (st == SPGEMM_OK && p->first_mode == kOnePass) st = unstage_if_few(p, p->first_mode, s);
     if (st != SPGEMM_OK) return fail(st);
-    if (p->first_mode == kOnePass &&
-        launch_scan_i32(p->pa.cap, p->pa.pad_rp, A->rows, p->pa.scan_status, p->pa.counters + kCtrScanTicket,
-                        p->pa.counters + kCtrPadTotal, p->pa.counters + kCtrError, s) != hipSuccess)
-      return fail(SPGEMM_E_HIP);
-    st = read_counters(p, s, &h);
-    if (st != SPGEMM_OK) return fail(st);
+    if (p->first_mode == kOnePass) {
+      if (launch_scan_i32(p->pa.cap, p->pa.pad_rp, A->rows, p->pa.scan_status, p->pa.counters + kCtrScanTicket,
+                          p->pa.counters + kCtrPadTotal, p->pa.counters + kCtrError, s) != hipSuccess)
+        return fail(SPGEMM_E_HIP);
+      st = read_counters(p, s, &h);
+      if (st != SPGEMM_OK) return fail(st);
+    } else {
+      // the counters as the sizing pass read them (nothing has run since)
+      h = host_counters();
+    }
     p->pad_total = p->first_mode == kOnePass ? h[kCtrPadTotal] : 0;
     // learned capacities may fall short: rows their tile has no room for go
     // to an arena of spill_ratio times the padded buffer (at least kSpillMin)
